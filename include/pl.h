@@ -1,0 +1,177 @@
+/*
+ * pl.h -- C ABI of the MI355X Poisson-lognormal MAP filter library (libpl.so).
+ *
+ * The library finds the maximum a posteriori log-density field
+ * s = ln(1 + delta) on a periodic 3D grid under a lognormal prior and a
+ * Poisson likelihood with power-law bias (Kitaura, Jasche & Metcalf,
+ * arXiv:0911.1407): the minimiser of
+ *
+ *   f(s) = 1/2 (s - mu)^T S_L^-1 (s - mu)                 (section 2.3, log-prior)
+ *        + sum_i [ nbar w_i e^{beta s_i} - beta N_i s_i ]  (section 2.1 eqs. 1-3;
+ *                                                          1 + delta_g = (1 + delta)^beta,
+ *                                                          section 2.4)
+ *
+ * whose gradient and Hessian are those of section 3.1.2 (lognormal prior):
+ *   g(s) = S_L^-1 (s - mu) + beta (nbar w e^{beta s} - N)
+ *   H(s) = S_L^-1 + diag(beta^2 nbar w e^{beta s}).
+ * S_L is a convolution on the grid (section 2.3), diagonal in Fourier space
+ * with eigenvalues lambda_k = amp * pk_k * N_cells / V; the k = 0 mode uses
+ * the separate inverse eigenvalue inv_p0.  beta = 1 is the unity bias of
+ * section 2.4.2.
+ *
+ * Conventions
+ *  - Real fields are double arrays [nx][ny][nz], z fastest (numpy C order),
+ *    N = nx*ny*nz values.  Half spectra are interleaved complex arrays
+ *    [nx][ny][nz/2+1] (numpy rfftn layout), Nh = nx*ny*(nz/2+1) entries of
+ *    two values each.
+ *  - Every field pointer is a DEVICE pointer owned by the caller.  The
+ *    library allocates no device memory: pl_plan_create reports the
+ *    workspace size and the caller hands over a device buffer of that size
+ *    with pl_plan_set_workspace (it must stay valid until pl_plan_destroy or
+ *    the next pl_plan_set_workspace).
+ *  - A plan is bound to one HIP stream (hipStream_t passed as void*; NULL is
+ *    the default stream) and must not be used by two threads at once.
+ *  - pl_grad, pl_hessvec* are asynchronous on the plan's stream, except that
+ *    pl_grad synchronises when obj_out is non-NULL.  pl_newton_krylov_solve
+ *    and pl_solve_adjoint return after the work is complete.
+ *  - Every call returns a status code; pl_last_error(plan) returns a message
+ *    for the last failing call on that plan.
+ *  - Grid lengths: each of nx, ny, nz must be one of
+ *    8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 512
+ *    (else PL_ERR_UNSUPPORTED_SIZE).
+ */
+#ifndef PL_H
+#define PL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum pl_status {
+  PL_OK = 0,
+  PL_ERR_INVALID_ARG = 1,      /* NULL pointer, bad option, no workspace */
+  PL_ERR_DOMAIN = 2,           /* negative or non-finite counts, w < 0,
+                                  counts > 0 where w = 0, pk <= 0 at k != 0,
+                                  non-finite field values */
+  PL_ERR_UNSUPPORTED_SIZE = 3, /* grid length not in the supported set */
+  PL_ERR_NOT_CONVERGED = 4,    /* iteration cap reached; outputs still written */
+  PL_ERR_LINESEARCH = 5,       /* no Armijo step found; outputs hold last iterate */
+  PL_ERR_HIP = 6,              /* a HIP runtime call failed */
+  PL_ERR_NO_PROBLEM = 7        /* pl_set_problem not called, or no cached Hessian diagonal */
+};
+
+enum pl_precision {
+  PL_FP64 = 0,  /* everything in FP64 */
+  PL_MIXED = 1  /* FFTs, Hessian-vector products and Krylov vectors in FP32;
+                   Krylov dots/norms, likelihood sums, gradient and outer
+                   Newton iteration in FP64 */
+};
+
+typedef struct pl_plan pl_plan;
+
+/* The posterior's data and parameters (sections 2.1-2.4). */
+typedef struct pl_problem {
+  const double* w;      /* device, N: completeness w_i >= 0 (eq. 2) */
+  const double* counts; /* device, N: observed counts N_i >= 0 (integers for real
+                           data; non-integral values are accepted since f is
+                           linear in N, so dL/dN can be checked by perturbing
+                           N); counts > 0 requires w > 0 */
+  const double* pk;     /* device, Nh: power-spectrum shape per half-spectrum
+                           mode in (Mpc/h)^3, > 0 for k != 0 (entry 0 ignored) */
+  double amp;           /* amplitude A: lambda_k = amp * pk_k * N / V */
+  double mu;            /* uniform prior mean of s (eq. mu) */
+  double nbar;          /* mean count per cell (eq. 2), > 0 */
+  double beta;          /* power-law bias exponent, > 0; 1 = unity bias */
+  double inv_p0;        /* inverse prior eigenvalue of the k = 0 mode, >= 0 */
+} pl_problem;
+
+typedef struct pl_solve_opts {
+  double rtol;      /* stop when ||g|| <= rtol ||g(s0)|| (default 1e-8) */
+  int max_newton;   /* Newton iteration cap (default 100) */
+  int max_cg;       /* CG iterations per Newton step (default 500) */
+  double eta_max;   /* forcing: CG stops at ||r|| <= min(eta_max, sqrt(||g||/||g0||)) ||g|| (0.5) */
+  double ls_c1;     /* Armijo constant (default 1e-4) */
+  int precision;    /* PL_FP64 or PL_MIXED (default: the plan's precision) */
+  int check_every;  /* CG iterations queued between host convergence checks (default 8) */
+} pl_solve_opts;
+
+typedef struct pl_solve_info {
+  int newton_its;  /* Newton iterations taken */
+  int cg_its;      /* CG iterations that changed the iterate */
+  int hvps;        /* Hessian-vector products launched (>= cg_its) */
+  int status;      /* same as the return code */
+  double rel_grad; /* final ||g|| / ||g0|| (adjoint: final ||r|| / ||b||) */
+  double grad0;    /* ||g(s0)|| (adjoint: ||b||) */
+  double obj;      /* final objective f(s) (constants of eq. 3 dropped) */
+} pl_solve_info;
+
+/* Fill opts with defaults (precision = -1: use the plan's). */
+void pl_default_opts(pl_solve_opts* opts);
+
+/* Create a plan for an n[0] x n[1] x n[2] grid of box side lengths box[] (Mpc/h).
+   precision: PL_FP64 or PL_MIXED (a PL_MIXED plan also supports FP64 solves).
+   *workspace_bytes receives the device workspace size the caller must provide. */
+int pl_plan_create(pl_plan** out, const int32_t n[3], const double box[3], int precision,
+                   void* hip_stream, size_t* workspace_bytes);
+/* Hand over the device workspace (>= workspace_bytes, 256-byte aligned). */
+int pl_plan_set_workspace(pl_plan* plan, void* dev_ptr);
+/* Change the stream later calls are issued on. */
+int pl_plan_set_stream(pl_plan* plan, void* hip_stream);
+int pl_plan_destroy(pl_plan* plan);
+
+/* Set the posterior (sections 2.1-2.4).  Validates the inputs (PL_ERR_DOMAIN)
+   and builds the 1/lambda tables.  The w / counts arrays are read by later
+   calls, so they must stay valid while the plan uses them; pk is read only
+   here.  Synchronises the stream. */
+int pl_set_problem(pl_plan* plan, const pl_problem* prob);
+
+/* Gradient of f at the real field s (section 3.1.2): grad_out (device, N).
+   obj_out (host, nullable) receives f(s).  Caches the Hessian diagonal for
+   pl_hessvec(plan, NULL, ...).  S_L^-1 is applied through an FFT round trip,
+   so the result carries FFT roundoff amplified by max 1/lambda. */
+int pl_grad(pl_plan* plan, const double* s, double* grad_out, double* obj_out);
+
+/* Hessian-vector product H(s) v (section 3.1.2): hv_out (device, N).
+   s == NULL reuses the diagonal cached by the last pl_grad / pl_hessvec. */
+int pl_hessvec(pl_plan* plan, const double* s, const double* v, double* hv_out);
+/* Same with v and hv_out in FP32 (FP32 FFTs; the diagonal is rounded to FP32). */
+int pl_hessvec_f32(pl_plan* plan, const double* s, const float* v, float* hv_out);
+
+/* Hessian-vector product on half spectra (the form used inside the solver):
+   hv_hat = v_hat / lambda + F[d * F^-1 v_hat].  Uses the cached diagonal.
+   Interleaved complex device arrays of Nh entries. */
+int pl_hessvec_hat(pl_plan* plan, const double* v_hat, double* hv_hat);
+int pl_hessvec_hat_f32(pl_plan* plan, const float* v_hat, float* hv_hat);
+
+/* MAP by inexact Newton-Krylov (section 3.1: Newton-Raphson with a Krylov step,
+   eq. New5 being the CG step length).  s_inout (device, N): start on input
+   (uniform mu is the usual start), MAP s* on output.  opts/info nullable.
+   Returns PL_OK, PL_ERR_NOT_CONVERGED or PL_ERR_LINESEARCH with s_inout and
+   info written in every case. */
+int pl_newton_krylov_solve(pl_plan* plan, double* s_inout, const pl_solve_opts* opts,
+                           pl_solve_info* info);
+
+/* Adjoint of a scalar loss L(s*) at the MAP s* (device, N): solves
+   H(s*) lambda = dL_ds (device, N) by PCG to ||r|| <= opts->rtol ||dL_ds||, writes
+   lambda_out (device, N, nullable) and the derivatives (mu held fixed)
+     dL/dA    = lambda^T S_L'^-1 (s* - mu) / A   (k != 0 modes)  -> *dL_dA    (host, nullable)
+     dL/dbeta = -lambda^T [nbar w e^{beta s}(1 + beta s) - N]   -> *dL_dbeta (host, nullable)
+     dL/dnbar = -lambda^T (beta w e^{beta s})                   -> *dL_dnbar (host, nullable)
+     dL/dN_i  = beta lambda_i                                    -> dL_dN     (device, N, nullable)
+     dL/dw_i  = -lambda_i beta nbar e^{beta s_i}                 -> dL_dw     (device, N, nullable)
+   (implicit differentiation of g(s*; theta) = 0: dL/dtheta = -lambda^T dg/dtheta). */
+int pl_solve_adjoint(pl_plan* plan, const double* s_star, const double* dL_ds, double* lambda_out,
+                     double* dL_dA, double* dL_dbeta, double* dL_dnbar, double* dL_dN, double* dL_dw,
+                     const pl_solve_opts* opts, pl_solve_info* info);
+
+/* Message for the last failing call on plan (never NULL). */
+const char* pl_last_error(const pl_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PL_H */

@@ -1,0 +1,813 @@
+// Kernel templates of the Poisson-lognormal MAP hot path.
+//
+// Layouts (row-major, z fastest, as numpy):
+//   real field      [nx][ny][nz]            N = nx ny nz values
+//   half spectrum   [nx][ny][nz/2 + 1]      Nh complex values (interleaved)
+// Forward transforms are unnormalised (X_k = sum_x x_x e^{-2 pi i m.x/n});
+// inverse transforms are unnormalised too and callers pass 1/N as `scale`.
+//
+// Passes:
+//   col_kernel  -- FFT along x or y of the half spectrum, one workgroup per
+//                  tile of B adjacent columns (coalesced B*16 byte segments
+//                  per row in FP64), optional fused spectral operations on
+//                  the x pass (prior multiply, prior add + dots).
+//   row_kernel  -- the z axis: real <-> half-complex transforms of two rows
+//                  at once (row a in the real part, row b in the imaginary
+//                  part of one complex length-nz transform), with fused
+//                  pointwise likelihood / Hessian-diagonal work.
+#pragma once
+#include "pl_fft.hpp"
+
+namespace pl {
+
+constexpr int RED_THREADS = 256;
+
+// ---------------------------------------------------------------------------
+// Reductions: per-block partial sums in FP64, summed in a fixed order by a
+// separate finalize kernel (deterministic).
+// ---------------------------------------------------------------------------
+
+template <int K>
+__device__ __forceinline__ void block_reduce_store(double (&v)[K], double* __restrict__ partials,
+                                                   int block_linear) {
+  __shared__ double sh[K][16];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) sh[k][wid] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double acc = 0.0;
+      for (int i = 0; i < nw; ++i) acc += sh[k][i];
+      partials[(size_t)block_linear * K + k] = acc;
+    }
+  }
+}
+
+// Spectral bookkeeping for the half spectrum [nx][ny][h], h = nz/2 + 1.
+struct Grid {
+  int nx, ny, nz, h;
+  long nyh;  // ny * h
+};
+
+__device__ __forceinline__ int fold(int m, int n) { return m >= (n >> 1) ? m - n : m; }
+
+// 1/lambda_k (section 2.3: S_L^-1 is diagonal in Fourier space).  radial:
+// table indexed by mx^2 + my^2 + mz^2 (cubic box); else one entry per mode.
+template <typename TT>
+__device__ __forceinline__ TT inv_lam_at(const TT* __restrict__ tab, int radial, const Grid& g,
+                                         int kx, int ky, int kz, long mode) {
+  if (radial) {
+    int fx = fold(kx, g.nx), fy = fold(ky, g.ny);
+    return tab[fx * fx + fy * fy + kz * kz];
+  }
+  return tab[mode];
+}
+
+__device__ __forceinline__ double herm_w(int kz, const Grid& g) {
+  return (kz == 0 || 2 * kz == g.nz) ? 1.0 : 2.0;
+}
+
+// ---------------------------------------------------------------------------
+// Column pass (x or y axis)
+// ---------------------------------------------------------------------------
+
+enum ColOp { COL_PLAIN = 0, COL_PRIOR = 1, COL_ADDPRIOR = 2 };
+
+template <typename T>
+struct ColArgs {
+  const cx<T>* in;
+  cx<T>* out;
+  int ncols;         // columns per slab
+  long row_stride;   // distance (complex elements) between consecutive transform entries
+  long slab_stride;  // distance between slabs (blockIdx.y)
+  const cx<T>* tw;   // twiddles of this length
+  // fused x-pass operations (columns are flattened (ky, kz) pairs)
+  Grid g;
+  const T* inv_lam;  // 1/lambda table (see inv_lam_at)
+  int radial;
+  const cx<T>* base;  // COL_ADDPRIOR: vector added through the prior
+  double k0_shift;    // subtracted from mode 0 before the prior multiply
+  T out_scale;        // COL_ADDPRIOR: scale of the transformed input
+  double* partials;   // COL_PRIOR: K = 1; COL_ADDPRIOR: K = 3
+};
+
+// Column tile width B: 256 threads per block where possible, at most 64 KB
+// of LDS for the stage exchanges, at least 8 columns (128-byte segments).
+constexpr int col_tile(int P, int N, int elem_bytes) {
+  int b = 256 / P;
+  if (b > 64) b = 64;
+  if (b < 8) b = 8;
+  while (b > 8 && P > 1 && b * N * elem_bytes > 65536) b /= 2;
+  return b;
+}
+
+template <typename T, int N>
+struct ColShape {
+  static constexpr int P = Plan<N>::P;
+  static constexpr int B = col_tile(P, N, (int)sizeof(cx<T>));
+  static constexpr int THREADS = B * P;
+};
+
+template <typename T, int N, bool INV, int OP>
+__global__ void __launch_bounds__((ColShape<T, N>::THREADS)) col_kernel(ColArgs<T> a) {
+  using PL = Plan<N>;
+  constexpr int B = ColShape<T, N>::B;
+  constexpr int P = PL::P;
+  constexpr int W = PL::W;
+  constexpr int R0 = PL::R0;
+  constexpr int RL = LastStage<PL>::R;
+  using MAP = LdsMap<B, false>;
+  __shared__ cx<T> lds_all[P > 1 ? N * B : 1];
+
+  const int cl = threadIdx.x % B;
+  const int t = threadIdx.x / B;
+  const int c = blockIdx.x * B + cl;
+  const bool valid = c < a.ncols;
+  const long base_off = (long)blockIdx.y * a.slab_stride + (valid ? c : 0);
+  cx<T>* lds = lds_all + cl;
+
+  cx<T> v[W];
+#pragma unroll
+  for (int q = 0; q < W / R0; ++q)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      int e = in_pos<PL, 0>(t, q, r);
+      v[q * R0 + r] = valid ? a.in[base_off + (long)e * a.row_stride] : cx<T>{T(0), T(0)};
+    }
+
+  if constexpr (OP == COL_PLAIN) {
+    fft_thread<PL, INV, MAP>(v, t, lds, a.tw);
+  } else if constexpr (OP == COL_PRIOR) {
+    // forward transform, multiply by 1/lambda (after removing the prior mean
+    // from mode 0), inverse transform: S_L^-1 applied along the last axis of
+    // a field already transformed along y and z.
+    fft_thread<PL, false, MAP>(v, t, lds, a.tw);
+    const int ky = c / a.g.h, kz = c % a.g.h;
+    double acc[1] = {0.0};
+#pragma unroll
+    for (int q = 0; q < W / RL; ++q)
+#pragma unroll
+      for (int m = 0; m < RL; ++m) {
+        int kx = out_pos<PL, PL::NS - 1>(t, q, m);
+        long mode = (long)kx * a.g.nyh + c;
+        cx<T> x = v[q * RL + m];
+        if (mode == 0) x.x -= (T)a.k0_shift;
+        T il = valid ? inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode) : T(0);
+        if (valid) acc[0] += herm_w(kz, a.g) * (double)il * ((double)x.x * x.x + (double)x.y * x.y);
+        v[q * RL + m] = {x.x * il, x.y * il};
+      }
+    last_to_first<PL, MAP>(v, t, lds);
+    fft_thread<PL, true, MAP>(v, t, lds, a.tw);
+    block_reduce_store<1>(acc, a.partials, blockIdx.x + gridDim.x * blockIdx.y);
+  } else {
+    // forward transform; out = scale * X + (1/lambda) (base - shift at mode 0)
+    fft_thread<PL, false, MAP>(v, t, lds, a.tw);
+    const int ky = c / a.g.h, kz = c % a.g.h;
+    double acc[3] = {0.0, 0.0, 0.0};
+    const double hw = herm_w(kz, a.g);
+#pragma unroll
+    for (int q = 0; q < W / RL; ++q)
+#pragma unroll
+      for (int m = 0; m < RL; ++m) {
+        int kx = out_pos<PL, PL::NS - 1>(t, q, m);
+        long mode = (long)kx * a.g.nyh + c;
+        if (valid) {
+          cx<T> b = a.base[mode];
+          cx<T> bs = b;
+          if (mode == 0) bs.x -= (T)a.k0_shift;
+          T il = inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode);
+          cx<T> x = v[q * RL + m];
+          cx<T> o = {x.x * a.out_scale + il * bs.x, x.y * a.out_scale + il * bs.y};
+          v[q * RL + m] = o;
+          acc[0] += hw * ((double)b.x * o.x + (double)b.y * o.y);
+          acc[1] += hw * ((double)o.x * o.x + (double)o.y * o.y);
+          acc[2] += hw * (double)il * ((double)bs.x * bs.x + (double)bs.y * bs.y);
+        }
+      }
+    block_reduce_store<3>(acc, a.partials, blockIdx.x + gridDim.x * blockIdx.y);
+  }
+
+  if (valid) {
+#pragma unroll
+    for (int q = 0; q < W / RL; ++q)
+#pragma unroll
+      for (int m = 0; m < RL; ++m) {
+        int e = out_pos<PL, PL::NS - 1>(t, q, m);
+        a.out[base_off + (long)e * a.row_stride] = v[q * RL + m];
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Row pass (z axis): two real rows per complex transform
+// ---------------------------------------------------------------------------
+
+enum RowOp {
+  ROW_R2C = 0,         // real rows -> half rows
+  ROW_C2R = 1,         // half rows -> real rows (times scale)
+  ROW_HVP = 2,         // half -> real, times scale * d, -> half
+  ROW_GRAD = 3,        // half (s_hat) -> s -> likelihood gradient l -> half;
+                       // writes s, e, d; partials sum(e - beta N s), sum(d)
+  ROW_C2R_DIAG = 4,    // half -> real: scale * x + d * v
+  ROW_C2R_GRADLIK = 5  // half -> real: scale * x + beta (nbar w e^{beta s} - N);
+                       // writes d; partials sum(e - beta N s)
+};
+
+template <typename T>
+struct RowArgs {
+  const cx<T>* in_c;
+  cx<T>* out_c;
+  const T* in_r;
+  T* out_r;
+  int nunits;  // row pairs
+  const cx<T>* tw;
+  T scale;
+  const double* d;  // Hessian diagonal beta^2 nbar w e^{beta s} (unscaled)
+  const float* d32;  // same in FP32 (mixed-precision HVP)
+  const T* v;
+  const double* w;
+  const double* counts;
+  double nbar, beta;
+  const double* s_in;
+  double* s_out;
+  double* e_out;
+  double* d_out;
+  double* partials;
+};
+
+template <int N>
+struct RowShape {
+  static constexpr int P = Plan<N>::P;
+  static constexpr int G = (256 / P) > 32 ? 32 : 256 / P;  // row pairs per block
+  static constexpr int THREADS = G * P;
+  static constexpr int LEN = PaddedLen<N + 2, true>::value;  // LDS slots per pair
+};
+
+template <typename T, int N, int OP>
+__global__ void __launch_bounds__(RowShape<N>::THREADS) row_kernel(RowArgs<T> a) {
+  using PL = Plan<N>;
+  constexpr int P = PL::P;
+  constexpr int W = PL::W;
+  constexpr int R0 = PL::R0;
+  constexpr int RL = LastStage<PL>::R;
+  constexpr int G = RowShape<N>::G;
+  constexpr int LEN = RowShape<N>::LEN;
+  constexpr int H = N / 2 + 1;
+  using MAP = LdsMap<1, true>;
+  __shared__ cx<T> lds_all[G * LEN];
+
+  const int t = threadIdx.x % P;
+  const int ul = threadIdx.x / P;
+  const int u = blockIdx.x * G + ul;
+  const bool valid = u < a.nunits;
+  const int uc = valid ? u : 0;
+  cx<T>* lds = lds_all + ul * LEN;
+  const long rowA = 2L * uc, rowB = 2L * uc + 1;
+
+  cx<T> v[W];
+
+  // ---- gather the complex length-N input Z = A + i B (stage-0 slots) ----
+  if constexpr (OP == ROW_R2C) {
+#pragma unroll
+    for (int q = 0; q < W / R0; ++q)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        int e = in_pos<PL, 0>(t, q, r);
+        v[q * R0 + r] = {a.in_r[rowA * N + e], a.in_r[rowB * N + e]};
+      }
+  } else {
+    // load the two half rows (2H contiguous complex values) into LDS
+    const cx<T>* src = a.in_c + rowA * H;
+    for (int i = t; i < 2 * H; i += P) lds[MAP::off(i)] = src[i];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < W / R0; ++q)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        int e = in_pos<PL, 0>(t, q, r);
+        cx<T> A, Bv;
+        if (e <= N / 2) {
+          A = lds[MAP::off(e)];
+          Bv = lds[MAP::off(H + e)];
+          if (e == 0 || e == N / 2) { A.y = T(0); Bv.y = T(0); }
+        } else {
+          A = conj(lds[MAP::off(N - e)]);
+          Bv = conj(lds[MAP::off(H + N - e)]);
+        }
+        v[q * R0 + r] = {A.x - Bv.y, A.y + Bv.x};
+      }
+  }
+
+  double acc[2] = {0.0, 0.0};
+
+  if constexpr (OP == ROW_R2C) {
+    fft_thread<PL, false, MAP>(v, t, lds, a.tw);
+  } else {
+    fft_thread<PL, true, MAP>(v, t, lds, a.tw);
+    // v now holds z[e] = a[e] + i b[e] at last-stage slots (unscaled)
+    if constexpr (OP == ROW_C2R) {
+      if (valid) {
+#pragma unroll
+        for (int q = 0; q < W / RL; ++q)
+#pragma unroll
+          for (int m = 0; m < RL; ++m) {
+            int e = out_pos<PL, PL::NS - 1>(t, q, m);
+            a.out_r[rowA * N + e] = v[q * RL + m].x * a.scale;
+            a.out_r[rowB * N + e] = v[q * RL + m].y * a.scale;
+          }
+      }
+      return;
+    } else if constexpr (OP == ROW_C2R_DIAG) {
+      if (valid) {
+#pragma unroll
+        for (int q = 0; q < W / RL; ++q)
+#pragma unroll
+          for (int m = 0; m < RL; ++m) {
+            int e = out_pos<PL, PL::NS - 1>(t, q, m);
+            long iA = rowA * N + e, iB = rowB * N + e;
+            if constexpr (sizeof(T) == 8) {
+              a.out_r[iA] = v[q * RL + m].x * a.scale + (T)a.d[iA] * a.v[iA];
+              a.out_r[iB] = v[q * RL + m].y * a.scale + (T)a.d[iB] * a.v[iB];
+            } else {
+              a.out_r[iA] = v[q * RL + m].x * a.scale + a.d32[iA] * a.v[iA];
+              a.out_r[iB] = v[q * RL + m].y * a.scale + a.d32[iB] * a.v[iB];
+            }
+          }
+      }
+      return;
+    } else if constexpr (OP == ROW_C2R_GRADLIK) {
+      if (valid) {
+#pragma unroll
+        for (int q = 0; q < W / RL; ++q)
+#pragma unroll
+          for (int m = 0; m < RL; ++m) {
+            int e = out_pos<PL, PL::NS - 1>(t, q, m);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              long i = (h ? rowB : rowA) * N + e;
+              double prior = (double)(h ? v[q * RL + m].y : v[q * RL + m].x) * (double)a.scale;
+              double s = a.s_in[i];
+              double ex = a.nbar * a.w[i] * exp(a.beta * s);
+              double cnt = a.counts[i];
+              a.out_r[i] = (T)(prior + a.beta * (ex - cnt));
+              a.d_out[i] = a.beta * a.beta * ex;
+              acc[0] += ex - a.beta * cnt * s;
+            }
+          }
+      }
+      block_reduce_store<2>(acc, a.partials, blockIdx.x);
+      return;
+    } else {
+      // pointwise work on the real values, then back to half spectra
+      if constexpr (OP == ROW_HVP) {
+#pragma unroll
+        for (int q = 0; q < W / RL; ++q)
+#pragma unroll
+          for (int m = 0; m < RL; ++m) {
+            int e = out_pos<PL, PL::NS - 1>(t, q, m);
+            T dA, dB;
+            if constexpr (sizeof(T) == 8) {
+              dA = valid ? (T)a.d[rowA * N + e] : T(0);
+              dB = valid ? (T)a.d[rowB * N + e] : T(0);
+            } else {
+              dA = valid ? a.d32[rowA * N + e] : T(0);
+              dB = valid ? a.d32[rowB * N + e] : T(0);
+            }
+            cx<T> z = v[q * RL + m];
+            v[q * RL + m] = {z.x * a.scale * dA, z.y * a.scale * dB};
+          }
+      } else {  // ROW_GRAD (double only)
+#pragma unroll
+        for (int q = 0; q < W / RL; ++q)
+#pragma unroll
+          for (int m = 0; m < RL; ++m) {
+            int e = out_pos<PL, PL::NS - 1>(t, q, m);
+            cx<T> z = v[q * RL + m];
+            double l[2] = {0.0, 0.0};
+            if (valid) {
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                long i = (h ? rowB : rowA) * N + e;
+                double s = (double)(h ? z.y : z.x) * (double)a.scale;
+                double ex = a.nbar * a.w[i] * exp(a.beta * s);
+                double cnt = a.counts[i];
+                a.s_out[i] = s;
+                a.e_out[i] = ex;
+                double dd = a.beta * a.beta * ex;
+                a.d_out[i] = dd;
+                acc[0] += ex - a.beta * cnt * s;
+                acc[1] += dd;
+                l[h] = a.beta * (ex - cnt);
+              }
+            }
+            v[q * RL + m] = {(T)l[0], (T)l[1]};
+          }
+      }
+      last_to_first<PL, MAP>(v, t, lds);
+      fft_thread<PL, false, MAP>(v, t, lds, a.tw);
+    }
+  }
+
+  // ---- split Z' into the two half rows: A'[k] = (Z[k] + conj Z[N-k])/2,
+  //      B'[k] = (Z[k] - conj Z[N-k])/(2i) ----
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < W / RL; ++q)
+#pragma unroll
+    for (int m = 0; m < RL; ++m) lds[MAP::off(out_pos<PL, PL::NS - 1>(t, q, m))] = v[q * RL + m];
+  __syncthreads();
+  if (valid) {
+    cx<T>* dst = a.out_c + rowA * H;
+    for (int k = t; k < H; k += P) {
+      cx<T> zk = lds[MAP::off(k)];
+      cx<T> zc = lds[MAP::off(k == 0 ? 0 : N - k)];
+      dst[k] = {T(0.5) * (zk.x + zc.x), T(0.5) * (zk.y - zc.y)};
+      dst[H + k] = {T(0.5) * (zk.y + zc.y), T(0.5) * (zc.x - zk.x)};
+    }
+  }
+  if constexpr (OP == ROW_GRAD) block_reduce_store<2>(acc, a.partials, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise / Krylov kernels on half spectra (grid-stride loops)
+// ---------------------------------------------------------------------------
+
+// Device scalar slots
+enum Scal {
+  SC_RZ = 0, SC_PQ = 1, SC_ALPHA = 2, SC_BETA = 3, SC_RR = 4, SC_TOL2 = 5, SC_DONE = 6,
+  SC_ITS = 7, SC_DBAR = 8,
+  SC_GG = 10, SC_PRIOR = 11, SC_LIK = 12, SC_DSUM = 13,
+  SC_LS_B = 16, SC_LS_C = 17, SC_LS_SLOPE = 18,
+  SC_DF = 20,  // 4 slots
+  SC_ADJ = 26,  // adjoint sums: beta, nbar, A
+  SC_COUNT = 32
+};
+
+struct ModeIter {
+  Grid g;
+  __device__ __forceinline__ void decompose(long i, int& kx, int& ky, int& kz) const {
+    kx = (int)(i / g.nyh);
+    long r = i - (long)kx * g.nyh;
+    ky = (int)(r / g.h);
+    kz = (int)(r - (long)ky * g.h);
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ double precond_inv(const T* tab, int radial, const Grid& g, int kx, int ky,
+                                              int kz, long i, double dbar) {
+  double m = (double)inv_lam_at(tab, radial, g, kx, ky, kz, i) + dbar;
+  return m > 0.0 ? 1.0 / m : 0.0;
+}
+
+// CG start on H x = rhs: x = 0, r = rhs_sign * rhs, p = M^-1 r; partials (r^H z, r^H r)
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS) cg_init_kernel(const cx<double>* __restrict__ rhs, double rhs_sign,
+                                                              cx<T>* __restrict__ x, cx<T>* __restrict__ r,
+                                                              cx<T>* __restrict__ p, const T* __restrict__ tab,
+                                                              int radial, Grid g, long nh,
+                                                              const double* __restrict__ scal,
+                                                              double* __restrict__ partials) {
+  ModeIter mi{g};
+  const double dbar = scal[SC_DBAR];
+  double acc[2] = {0.0, 0.0};
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nh; i += (long)gridDim.x * blockDim.x) {
+    int kx, ky, kz;
+    mi.decompose(i, kx, ky, kz);
+    cx<double> b = rhs[i];
+    cx<T> rv = {(T)(rhs_sign * b.x), (T)(rhs_sign * b.y)};
+    double minv = precond_inv(tab, radial, g, kx, ky, kz, i, dbar);
+    cx<T> z = {(T)(minv * rv.x), (T)(minv * rv.y)};
+    x[i] = {T(0), T(0)};
+    r[i] = rv;
+    p[i] = z;
+    double hw = herm_w(kz, g);
+    acc[0] += hw * ((double)rv.x * z.x + (double)rv.y * z.y);
+    acc[1] += hw * ((double)rv.x * rv.x + (double)rv.y * rv.y);
+  }
+  block_reduce_store<2>(acc, partials, blockIdx.x);
+}
+
+// x += alpha p; r -= alpha q; partials (r^H r, r^H M^-1 r)
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS) cg_update1_kernel(cx<T>* __restrict__ x, const cx<T>* __restrict__ p,
+                                                                 cx<T>* __restrict__ r, const cx<T>* __restrict__ q,
+                                                                 const T* __restrict__ tab, int radial, Grid g,
+                                                                 long nh, const double* __restrict__ scal,
+                                                                 double* __restrict__ partials) {
+  ModeIter mi{g};
+  const T alpha = (T)scal[SC_ALPHA];
+  const double dbar = scal[SC_DBAR];
+  double acc[2] = {0.0, 0.0};
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nh; i += (long)gridDim.x * blockDim.x) {
+    int kx, ky, kz;
+    mi.decompose(i, kx, ky, kz);
+    cx<T> pv = p[i], qv = q[i], xv = x[i], rv = r[i];
+    xv = {xv.x + alpha * pv.x, xv.y + alpha * pv.y};
+    rv = {rv.x - alpha * qv.x, rv.y - alpha * qv.y};
+    x[i] = xv;
+    r[i] = rv;
+    double minv = precond_inv(tab, radial, g, kx, ky, kz, i, dbar);
+    double hw = herm_w(kz, g);
+    double rr = (double)rv.x * rv.x + (double)rv.y * rv.y;
+    acc[0] += hw * rr;
+    acc[1] += hw * minv * rr;
+  }
+  block_reduce_store<2>(acc, partials, blockIdx.x);
+}
+
+// p = M^-1 r + beta p
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS) cg_update2_kernel(cx<T>* __restrict__ p, const cx<T>* __restrict__ r,
+                                                                 const T* __restrict__ tab, int radial, Grid g,
+                                                                 long nh, const double* __restrict__ scal) {
+  ModeIter mi{g};
+  const T beta = (T)scal[SC_BETA];
+  const double dbar = scal[SC_DBAR];
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nh; i += (long)gridDim.x * blockDim.x) {
+    int kx, ky, kz;
+    mi.decompose(i, kx, ky, kz);
+    T minv = (T)precond_inv(tab, radial, g, kx, ky, kz, i, dbar);
+    cx<T> rv = r[i], pv = p[i];
+    p[i] = {minv * rv.x + beta * pv.x, minv * rv.y + beta * pv.y};
+  }
+}
+
+#ifdef PL_OPS_KERNELS
+enum FinKind { FIN_STORE = 0, FIN_CG_INIT = 1, FIN_CG_ALPHA = 2, FIN_CG_BETA = 3, FIN_DBAR = 4 };
+
+// Sum partials[nb][K] in a fixed order; then scalar bookkeeping.
+__global__ void __launch_bounds__(256) finalize_kernel(const double* __restrict__ partials, int nb, int K,
+                                                       int kind, int dst, double scale, double* __restrict__ scal,
+                                                       double aux) {
+  __shared__ double sh[8][256];
+  for (int k = 0; k < K; ++k) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) acc += partials[(size_t)i * K + k];
+    sh[k][threadIdx.x] = acc;
+  }
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+      for (int k = 0; k < K; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  double v[8];
+  for (int k = 0; k < K; ++k) v[k] = sh[k][0] * scale;
+  switch (kind) {
+    case FIN_STORE:
+      for (int k = 0; k < K; ++k) scal[dst + k] = v[k];
+      break;
+    case FIN_CG_INIT:
+      scal[SC_RZ] = v[0];
+      scal[SC_RR] = v[1];
+      scal[SC_DONE] = (v[1] <= scal[SC_TOL2]) ? 1.0 : 0.0;
+      scal[SC_ITS] = 0.0;
+      scal[SC_ALPHA] = 0.0;
+      scal[SC_BETA] = 0.0;
+      break;
+    case FIN_CG_ALPHA: {
+      scal[SC_PQ] = v[0];
+      double al = 0.0;
+      if (scal[SC_DONE] == 0.0 && v[0] > 0.0) al = scal[SC_RZ] / v[0];
+      if (scal[SC_DONE] == 0.0 && !(v[0] > 0.0)) scal[SC_DONE] = 2.0;  // breakdown
+      scal[SC_ALPHA] = al;
+      break;
+    }
+    case FIN_CG_BETA: {
+      if (scal[SC_DONE] == 0.0) {
+        scal[SC_ITS] += 1.0;
+        scal[SC_RR] = v[0];
+        double b = scal[SC_RZ] > 0.0 ? v[1] / scal[SC_RZ] : 0.0;
+        scal[SC_RZ] = v[1];
+        scal[SC_BETA] = b;
+        if (v[0] <= scal[SC_TOL2] || scal[SC_ITS] >= aux) scal[SC_DONE] = 1.0;
+      } else {
+        scal[SC_BETA] = 0.0;
+      }
+      break;
+    }
+    case FIN_DBAR:
+      scal[SC_DBAR] = v[0];
+      break;
+  }
+}
+
+__global__ void set_scalar_kernel(double* scal, int idx, double value) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) scal[idx] = value;
+}
+
+#endif  // PL_OPS_KERNELS
+
+// s_hat += alpha x  (alpha from the host)
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS) axpy_hat_kernel(cx<double>* __restrict__ y, const cx<T>* __restrict__ x,
+                                                               double alpha, long nh) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nh; i += (long)gridDim.x * blockDim.x) {
+    cx<T> xv = x[i];
+    cx<double> yv = y[i];
+    y[i] = {yv.x + alpha * (double)xv.x, yv.y + alpha * (double)xv.y};
+  }
+}
+
+// Line-search dots on half spectra: b = <p, S^-1 (s - mu)>, c = <p, S^-1 p>,
+// slope = <g, p> (times N; the finalize applies 1/N).
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS) ls_dots_kernel(const cx<T>* __restrict__ p, const cx<double>* __restrict__ s_hat,
+                                                              const cx<double>* __restrict__ g_hat,
+                                                              const double* __restrict__ tab, int radial, Grid g,
+                                                              long nh, double k0_shift,
+                                                              double* __restrict__ partials) {
+  ModeIter mi{g};
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nh; i += (long)gridDim.x * blockDim.x) {
+    int kx, ky, kz;
+    mi.decompose(i, kx, ky, kz);
+    double il = inv_lam_at(tab, radial, g, kx, ky, kz, i);
+    cx<T> pv = p[i];
+    cx<double> sv = s_hat[i], gv = g_hat[i];
+    if (i == 0) sv.x -= k0_shift;
+    double hw = herm_w(kz, g);
+    acc[0] += hw * il * ((double)pv.x * sv.x + (double)pv.y * sv.y);
+    acc[1] += hw * il * ((double)pv.x * pv.x + (double)pv.y * pv.y);
+    acc[2] += hw * ((double)pv.x * gv.x + (double)pv.y * gv.y);
+  }
+  block_reduce_store<3>(acc, partials, blockIdx.x);
+}
+
+// Likelihood part of f(s + a p) - f(s) for four trial steps a_j:
+// sum_i [e_i expm1(a_j beta p_i) - a_j beta N_i p_i]
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS) ls_eval_kernel(const T* __restrict__ p, const double* __restrict__ e,
+                                                              const double* __restrict__ counts, double beta,
+                                                              double a0, long n, double* __restrict__ partials) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    double bp = beta * (double)p[i];
+    double ei = e[i], ci = counts[i];
+    double a = a0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc[j] += ei * expm1(a * bp) - a * ci * bp;
+      a *= 0.5;
+    }
+  }
+  block_reduce_store<4>(acc, partials, blockIdx.x);
+}
+
+#ifdef PL_OPS_KERNELS
+// Non-template kernels are defined in one translation unit only.
+// d = beta^2 nbar w e^{beta s}, e = nbar w e^{beta s} (real-space input s)
+__global__ void __launch_bounds__(RED_THREADS) linearize_kernel(const double* __restrict__ s, const double* __restrict__ w,
+                                                                double nbar, double beta, double* __restrict__ e,
+                                                                double* __restrict__ d, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    double ex = nbar * w[i] * exp(beta * s[i]);
+    if (e) e[i] = ex;
+    d[i] = beta * beta * ex;
+  }
+}
+
+__global__ void __launch_bounds__(RED_THREADS) d_to_f32_kernel(const double* __restrict__ d, float* __restrict__ d32,
+                                                               long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    d32[i] = (float)d[i];
+}
+
+// Sum of d (for the preconditioner's mean diagonal)
+__global__ void __launch_bounds__(RED_THREADS) sum_kernel(const double* __restrict__ x, long n,
+                                                          double* __restrict__ partials) {
+  double acc[1] = {0.0};
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) acc[0] += x[i];
+  block_reduce_store<1>(acc, partials, blockIdx.x);
+}
+
+// Adjoint per-cell parameter derivatives (mu held fixed):
+// dL/dN_i = beta lambda_i, dL/dw_i = -lambda_i beta nbar e^{beta s_i};
+// partial sums of lambda (nbar w e^{bs}(1 + beta s) - N) and lambda beta w e^{bs}
+__global__ void __launch_bounds__(RED_THREADS) adjoint_cells_kernel(const double* __restrict__ lam, const double* __restrict__ s,
+                                                                    const double* __restrict__ w,
+                                                                    const double* __restrict__ counts, double nbar,
+                                                                    double beta, double* __restrict__ dN,
+                                                                    double* __restrict__ dw, long n,
+                                                                    double* __restrict__ partials) {
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    double l = lam[i], sv = s[i];
+    double ebs = exp(beta * sv);
+    double ex = nbar * w[i] * ebs;
+    acc[0] += l * (ex * (1.0 + beta * sv) - counts[i]);
+    acc[1] += l * beta * w[i] * ebs;
+    acc[2] += l;
+    if (dN) dN[i] = beta * l;
+    if (dw) dw[i] = -l * beta * nbar * ebs;
+  }
+  block_reduce_store<3>(acc, partials, blockIdx.x);
+}
+
+// <lambda, S'^-1 (s - mu)> over k != 0 modes (times N)
+__global__ void __launch_bounds__(RED_THREADS) adjoint_prior_dot_kernel(const cx<double>* __restrict__ lam_hat,
+                                                                        const cx<double>* __restrict__ s_hat,
+                                                                        const double* __restrict__ tab, int radial,
+                                                                        Grid g, long nh, double* __restrict__ partials) {
+  ModeIter mi{g};
+  double acc[1] = {0.0};
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nh; i += (long)gridDim.x * blockDim.x) {
+    if (i == 0) continue;
+    int kx, ky, kz;
+    mi.decompose(i, kx, ky, kz);
+    double il = inv_lam_at(tab, radial, g, kx, ky, kz, i);
+    cx<double> l = lam_hat[i], sv = s_hat[i];
+    acc[0] += herm_w(kz, g) * il * (l.x * sv.x + l.y * sv.y);
+  }
+  block_reduce_store<1>(acc, partials, blockIdx.x);
+}
+
+// Build 1/lambda per mode from pk: V / (N amp pk); mode 0 -> inv_p0.  Also
+// scatters into the radial table and flags entries that disagree.
+__global__ void __launch_bounds__(RED_THREADS) inv_lam_mode_kernel(const double* __restrict__ pk, double coef,
+                                                                   double inv_p0, Grid g, long nh,
+                                                                   double* __restrict__ per_mode,
+                                                                   int* __restrict__ bad) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nh; i += (long)gridDim.x * blockDim.x) {
+    double v;
+    if (i == 0) {
+      v = inv_p0;
+    } else {
+      double p = pk[i];
+      if (!(p > 0.0) || !isfinite(p)) {
+        atomicOr(bad, 1);
+        v = 0.0;
+      } else {
+        v = coef / p;
+      }
+    }
+    per_mode[i] = v;
+  }
+}
+
+__global__ void __launch_bounds__(RED_THREADS) radial_scatter_kernel(const double* __restrict__ per_mode, Grid g, long nh,
+                                                                     double* __restrict__ radial) {
+  ModeIter mi{g};
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nh; i += (long)gridDim.x * blockDim.x) {
+    int kx, ky, kz;
+    mi.decompose(i, kx, ky, kz);
+    int fx = fold(kx, g.nx), fy = fold(ky, g.ny);
+    radial[fx * fx + fy * fy + kz * kz] = per_mode[i];
+  }
+}
+
+__global__ void __launch_bounds__(RED_THREADS) radial_check_kernel(const double* __restrict__ per_mode, Grid g, long nh,
+                                                                   const double* __restrict__ radial,
+                                                                   int* __restrict__ mismatch) {
+  ModeIter mi{g};
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nh; i += (long)gridDim.x * blockDim.x) {
+    int kx, ky, kz;
+    mi.decompose(i, kx, ky, kz);
+    int fx = fold(kx, g.nx), fy = fold(ky, g.ny);
+    if (radial[fx * fx + fy * fy + kz * kz] != per_mode[i]) atomicOr(mismatch, 1);
+  }
+}
+
+__global__ void __launch_bounds__(RED_THREADS) to_f32_kernel(const double* __restrict__ x, float* __restrict__ y, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) y[i] = (float)x[i];
+}
+
+// Input validation: counts >= 0, w >= 0, counts > 0 => w > 0, all finite.
+// Counts need not be integral: the s-dependent part of the log-likelihood is
+// linear in N, which keeps derivatives with respect to N well defined.
+// flags bit 1: bad counts, bit 2: bad w, bit 4: counts where w = 0
+__global__ void __launch_bounds__(RED_THREADS) validate_kernel(const double* __restrict__ w, const double* __restrict__ counts,
+                                                               long n, int* __restrict__ flags) {
+  int f = 0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    double c = counts[i], wv = w[i];
+    if (!(c >= 0.0) || !isfinite(c)) f |= 1;
+    if (!(wv >= 0.0) || !isfinite(wv)) f |= 2;
+    if (c > 0.0 && !(wv > 0.0)) f |= 4;
+  }
+  if (f) atomicOr(flags, f);
+}
+
+// all finite check on a real field; flags |= 8 if not
+__global__ void __launch_bounds__(RED_THREADS) finite_kernel(const double* __restrict__ x, long n, int* __restrict__ flags) {
+  int f = 0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    if (!isfinite(x[i])) f = 8;
+  if (f) atomicOr(flags, f);
+}
+
+#endif  // PL_OPS_KERNELS
+
+}  // namespace pl

@@ -1,0 +1,45 @@
+"""The C-ABI library loads and exports every symbol the header declares (CPU only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pl.h")
+LIB = os.path.join(ROOT, "paper_0911_1407_amd", "libpl.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pl_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("pl_grad", "pl_hessvec", "pl_newton_krylov_solve", "pl_solve_adjoint"):
+        assert required in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpl.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpl.so not built")
+def test_binding_covers_header():
+    from paper_0911_1407_amd import binding
+    assert set(declared_functions()) == set(binding.EXPORTED)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpl.so not built")
+def test_plan_create_rejects_unsupported_sizes_without_gpu():
+    # plan creation validates sizes on the host before any device call
+    from paper_0911_1407_amd import binding
+    for n in [(10, 16, 16), (16, 16, 7), (1024, 16, 16)]:
+        with pytest.raises(binding.PLError) as e:
+            binding.pl_plan_create(n, (1.0, 1.0, 1.0))
+        assert e.value.code == binding.PL_ERR_UNSUPPORTED_SIZE
