@@ -55,6 +55,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only-hvp", action="store_true", help="profiling aid: only the isolated HVP loop")
     ap.add_argument("--n", type=int, default=256, help="grid (default: the 256^3 workload)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="profiling aid: also run a 1 GiB device-to-device copy (counter scale reference)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -112,6 +114,12 @@ def main():
     gbs32 = b32 / (ms32 * 1e-3) / 1e9
     print(f"# HVP fp64 {ms64:.3f} ms ({gbs64:.0f} GB/s), fp32 {ms32:.3f} ms ({gbs32:.0f} GB/s)",
           file=sys.stderr, flush=True)
+    if args.copy_probe:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
     if args.only_hvp:
         print(json.dumps({"hvp_ms_fp64": ms64, "hvp_ms_fp32": ms32}))
         return
@@ -158,11 +166,11 @@ def main():
     dL = 2.0 * (s_fp64 - s_true)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    grads, ainfo = plan.adjoint(s_fp64, dL, want_fields=False, rtol=1e-6, precision=0)
+    grads, ainfo = plan.adjoint(s_fp64, dL, want_fields=False, rtol=1e-6, precision=0, max_cg=5000)
     torch.cuda.synchronize()
     t_adj = time.perf_counter() - t0
     t0 = time.perf_counter()
-    grads32, ainfo32 = plan.adjoint(s_fp64, dL, want_fields=False, rtol=1e-6, precision=1)
+    grads32, ainfo32 = plan.adjoint(s_fp64, dL, want_fields=False, rtol=1e-6, precision=1, max_cg=5000)
     torch.cuda.synchronize()
     t_adj32 = time.perf_counter() - t0
     print(f"# adjoint fp64 {1e3 * t_adj:.1f} ms {ainfo}; mixed {1e3 * t_adj32:.1f} ms",

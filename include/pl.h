@@ -92,10 +92,10 @@ typedef struct pl_solve_opts {
   double rtol;      /* stop when ||g|| <= rtol ||g(s0)|| (default 1e-8) */
   int max_newton;   /* Newton iteration cap (default 100) */
   int max_cg;       /* CG iterations per Newton step (default 500) */
-  double eta_max;   /* forcing: CG stops at ||r|| <= min(eta_max, sqrt(||g||/||g0||)) ||g|| (0.5) */
+  double eta_max;   /* forcing: CG stops at ||r|| <= eta ||g||, eta = min(eta_max, max(sqrt(||g||/||g0||), rtol ||g0|| / (2 ||g||))) (eta_max 0.5) */
   double ls_c1;     /* Armijo constant (default 1e-4) */
   int precision;    /* PL_FP64 or PL_MIXED (default: the plan's precision) */
-  int check_every;  /* CG iterations queued between host convergence checks (default 8) */
+  int check_every;  /* CG iterations queued between host convergence checks (default 16) */
 } pl_solve_opts;
 
 typedef struct pl_solve_info {

@@ -77,11 +77,45 @@ __device__ __forceinline__ double herm_w(int kz, const Grid& g) {
   return (kz == 0 || 2 * kz == g.nz) ? 1.0 : 2.0;
 }
 
+// Device scalar slots
+enum Scal {
+  SC_RZ = 0,      // r^H M^-1 r
+  SC_PQ = 1,      // p^H H p
+  SC_ALPHA = 2,   // CG step
+  SC_BETA = 3,    // CG direction update
+  SC_RR = 4,      // r^H r
+  SC_TOL2 = 5,    // stop when r^H r <= TOL2
+  SC_DONE = 6,    // 0 running, 1 converged / capped, 2 breakdown
+  SC_ITS = 7,     // CG iterations that changed the iterate
+  SC_DBAR = 8,    // mean of the Hessian diagonal (preconditioner)
+  SC_JUNK = 10,   // sink for an unused partial
+  SC_GG = 11, SC_PRIOR = 12, SC_LIK = 13, SC_DSUM = 14,
+  SC_LS_B = 16, SC_LS_C = 17, SC_LS_SLOPE = 18,
+  SC_DF = 20,     // 4 slots
+  SC_ADJ = 26,    // adjoint sums (4 slots)
+  SC_COUNT = 32
+};
+
+// Inverse of the preconditioner M_k = 1/lambda_k + mean(d), the exact
+// diagonal of H in the Fourier basis.
+template <typename T>
+__device__ __forceinline__ double precond_inv(const T* tab, int radial, const Grid& g, int kx, int ky,
+                                              int kz, long i, double dbar) {
+  double m = (double)inv_lam_at(tab, radial, g, kx, ky, kz, i) + dbar;
+  return m > 0.0 ? 1.0 / m : 0.0;
+}
+
 // ---------------------------------------------------------------------------
 // Column pass (x or y axis)
 // ---------------------------------------------------------------------------
 
-enum ColOp { COL_PLAIN = 0, COL_PRIOR = 1, COL_ADDPRIOR = 2 };
+enum ColOp {
+  COL_PLAIN = 0,     // transform only
+  COL_PRIOR = 1,     // forward, times 1/lambda, inverse (partials K = 1)
+  COL_ADDPRIOR = 2,  // forward; out = X + (1/lambda) base (partials K = 3)
+  COL_CG_FIRST = 3,  // CG prologue on the input, then inverse transform (partials K = 1)
+  COL_CG_LAST = 4    // forward; q = X + p/lambda; r -= alpha q (partials K = 2)
+};
 
 template <typename T>
 struct ColArgs {
@@ -98,7 +132,12 @@ struct ColArgs {
   const cx<T>* base;  // COL_ADDPRIOR: vector added through the prior
   double k0_shift;    // subtracted from mode 0 before the prior multiply
   T out_scale;        // COL_ADDPRIOR: scale of the transformed input
-  double* partials;   // COL_PRIOR: K = 1; COL_ADDPRIOR: K = 3
+  double* partials;   // per-block partial sums
+  // Krylov operands (COL_CG_FIRST / COL_CG_LAST), same layout as the input
+  cx<T>* cg_r;
+  cx<T>* cg_x;
+  const double* scal;  // device scalars (SC_*)
+  const double* skip;  // if non-null and *skip != 0 the launch does nothing
 };
 
 // Column tile width B: 256 threads per block where possible, at most 64 KB
@@ -129,14 +168,59 @@ __global__ void __launch_bounds__((ColShape<T, N>::THREADS)) col_kernel(ColArgs<
   using MAP = LdsMap<B, false>;
   __shared__ cx<T> lds_all[P > 1 ? N * B : 1];
 
+  if (a.skip && *a.skip != 0.0) return;  // Krylov iteration after convergence
   const int cl = threadIdx.x % B;
   const int t = threadIdx.x / B;
-  const int c = blockIdx.x * B + cl;
+  // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+  // L2).  Give every XCD a contiguous range of (tile, slab) work items so
+  // that neighbouring column tiles, whose row segments share cache lines
+  // when the row pitch is not a multiple of 128 bytes, meet in one L2.
+  int tile = blockIdx.x, slab = blockIdx.y;
+  if (gridDim.y > 1) {
+    const int total = gridDim.x * gridDim.y;
+    const int hw = blockIdx.x + gridDim.x * blockIdx.y;
+    const int xcd = hw & 7, k = hw >> 3;
+    const int per = total >> 3, rem = total & 7;
+    const int logical = xcd * per + (xcd < rem ? xcd : rem) + k;
+    tile = logical % gridDim.x;
+    slab = logical / gridDim.x;
+  }
+  const int c = tile * B + cl;
   const bool valid = c < a.ncols;
-  const long base_off = (long)blockIdx.y * a.slab_stride + (valid ? c : 0);
+  const long base_off = (long)slab * a.slab_stride + (valid ? c : 0);
   cx<T>* lds = lds_all + cl;
 
   cx<T> v[W];
+  if constexpr (OP == COL_CG_FIRST) {
+    // Krylov prologue on the x pass of a half spectrum (columns = (ky, kz)):
+    //   p = M^-1 r + beta p_old (in place), partial sum of p^H Lambda^-1 p;
+    // then the inverse transform of p.
+    const double beta = a.scal[SC_BETA], dbar = a.scal[SC_DBAR];
+    const int ky = c / a.g.h, kz = c % a.g.h;
+    const double hw = herm_w(kz, a.g);
+    double acc[1] = {0.0};
+    cx<T>* pio = const_cast<cx<T>*>(a.in);
+#pragma unroll
+    for (int q = 0; q < W / R0; ++q)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        int kx = in_pos<PL, 0>(t, q, r);
+        long idx = base_off + (long)kx * a.row_stride;
+        cx<T> pn = {T(0), T(0)};
+        if (valid) {
+          cx<T> po = pio[idx], rv = a.cg_r[idx];
+          long mode = (long)kx * a.g.nyh + c;
+          double il = (double)inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode);
+          double mi = (il + dbar) > 0.0 ? 1.0 / (il + dbar) : 0.0;
+          pn = {(T)(mi * rv.x + beta * po.x), (T)(mi * rv.y + beta * po.y)};
+          pio[idx] = pn;
+          acc[0] += hw * il * ((double)pn.x * pn.x + (double)pn.y * pn.y);
+        }
+        v[q * R0 + r] = pn;
+      }
+    fft_thread<PL, true, MAP>(v, t, lds, a.tw);
+    block_reduce_store<1>(acc, a.partials, blockIdx.x + gridDim.x * blockIdx.y);
+  } else {
 #pragma unroll
   for (int q = 0; q < W / R0; ++q)
 #pragma unroll
@@ -144,8 +228,11 @@ __global__ void __launch_bounds__((ColShape<T, N>::THREADS)) col_kernel(ColArgs<
       int e = in_pos<PL, 0>(t, q, r);
       v[q * R0 + r] = valid ? a.in[base_off + (long)e * a.row_stride] : cx<T>{T(0), T(0)};
     }
+  }
 
-  if constexpr (OP == COL_PLAIN) {
+  if constexpr (OP == COL_CG_FIRST) {
+    // done above
+  } else if constexpr (OP == COL_PLAIN) {
     fft_thread<PL, INV, MAP>(v, t, lds, a.tw);
   } else if constexpr (OP == COL_PRIOR) {
     // forward transform, multiply by 1/lambda (after removing the prior mean
@@ -169,6 +256,37 @@ __global__ void __launch_bounds__((ColShape<T, N>::THREADS)) col_kernel(ColArgs<
     last_to_first<PL, MAP>(v, t, lds);
     fft_thread<PL, true, MAP>(v, t, lds, a.tw);
     block_reduce_store<1>(acc, a.partials, blockIdx.x + gridDim.x * blockIdx.y);
+  } else if constexpr (OP == COL_CG_LAST) {
+    // forward transform; q = X + p/lambda (= H p); r -= alpha q and
+    // x += alpha p in place; partials (r^H r, r^H M^-1 r).  q is not stored.
+    fft_thread<PL, false, MAP>(v, t, lds, a.tw);
+    const int ky = c / a.g.h, kz = c % a.g.h;
+    const double hw = herm_w(kz, a.g);
+    const double alpha = a.scal[SC_ALPHA], dbar = a.scal[SC_DBAR];
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < W / RL; ++q)
+#pragma unroll
+      for (int m = 0; m < RL; ++m) {
+        int kx = out_pos<PL, PL::NS - 1>(t, q, m);
+        long mode = (long)kx * a.g.nyh + c;
+        if (valid) {
+          cx<T> pv = a.base[mode];
+          T il = inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode);
+          cx<T> x = v[q * RL + m];
+          double qx = (double)x.x + (double)il * pv.x, qy = (double)x.y + (double)il * pv.y;
+          cx<T> rv = a.cg_r[mode], xv = a.cg_x[mode];
+          cx<T> rn = {(T)(rv.x - alpha * qx), (T)(rv.y - alpha * qy)};
+          a.cg_r[mode] = rn;
+          a.cg_x[mode] = {(T)(xv.x + alpha * pv.x), (T)(xv.y + alpha * pv.y)};
+          double rr = (double)rn.x * rn.x + (double)rn.y * rn.y;
+          double mi = ((double)il + dbar) > 0.0 ? 1.0 / ((double)il + dbar) : 0.0;
+          acc[0] += hw * rr;
+          acc[1] += hw * mi * rr;
+        }
+      }
+    block_reduce_store<2>(acc, a.partials, blockIdx.x + gridDim.x * blockIdx.y);
+    return;
   } else {
     // forward transform; out = scale * X + (1/lambda) (base - shift at mode 0)
     fft_thread<PL, false, MAP>(v, t, lds, a.tw);
@@ -215,7 +333,7 @@ __global__ void __launch_bounds__((ColShape<T, N>::THREADS)) col_kernel(ColArgs<
 enum RowOp {
   ROW_R2C = 0,         // real rows -> half rows
   ROW_C2R = 1,         // half rows -> real rows (times scale)
-  ROW_HVP = 2,         // half -> real, times scale * d, -> half
+  ROW_HVP = 2,         // half -> real v, times d, -> half; partials (sum d v^2)
   ROW_GRAD = 3,        // half (s_hat) -> s -> likelihood gradient l -> half;
                        // writes s, e, d; partials sum(e - beta N s), sum(d)
   ROW_C2R_DIAG = 4,    // half -> real: scale * x + d * v
@@ -243,6 +361,7 @@ struct RowArgs {
   double* e_out;
   double* d_out;
   double* partials;
+  const double* skip;  // if non-null and *skip != 0 the launch does nothing
 };
 
 template <int N>
@@ -266,6 +385,7 @@ __global__ void __launch_bounds__(RowShape<N>::THREADS) row_kernel(RowArgs<T> a)
   using MAP = LdsMap<1, true>;
   __shared__ cx<T> lds_all[G * LEN];
 
+  if (a.skip && *a.skip != 0.0) return;  // Krylov iteration after convergence
   const int t = threadIdx.x % P;
   const int ul = threadIdx.x / P;
   const int u = blockIdx.x * G + ul;
@@ -384,7 +504,9 @@ __global__ void __launch_bounds__(RowShape<N>::THREADS) row_kernel(RowArgs<T> a)
               dB = valid ? a.d32[rowB * N + e] : T(0);
             }
             cx<T> z = v[q * RL + m];
-            v[q * RL + m] = {z.x * a.scale * dA, z.y * a.scale * dB};
+            T va = z.x * a.scale, vb = z.y * a.scale;
+            acc[0] += (double)dA * va * va + (double)dB * vb * vb;
+            v[q * RL + m] = {va * dA, vb * dB};
           }
       } else {  // ROW_GRAD (double only)
 #pragma unroll
@@ -435,23 +557,14 @@ __global__ void __launch_bounds__(RowShape<N>::THREADS) row_kernel(RowArgs<T> a)
       dst[H + k] = {T(0.5) * (zk.y + zc.y), T(0.5) * (zc.x - zk.x)};
     }
   }
-  if constexpr (OP == ROW_GRAD) block_reduce_store<2>(acc, a.partials, blockIdx.x);
+  if constexpr (OP == ROW_GRAD || OP == ROW_HVP) block_reduce_store<2>(acc, a.partials, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
 // Elementwise / Krylov kernels on half spectra (grid-stride loops)
 // ---------------------------------------------------------------------------
 
-// Device scalar slots
-enum Scal {
-  SC_RZ = 0, SC_PQ = 1, SC_ALPHA = 2, SC_BETA = 3, SC_RR = 4, SC_TOL2 = 5, SC_DONE = 6,
-  SC_ITS = 7, SC_DBAR = 8,
-  SC_GG = 10, SC_PRIOR = 11, SC_LIK = 12, SC_DSUM = 13,
-  SC_LS_B = 16, SC_LS_C = 17, SC_LS_SLOPE = 18,
-  SC_DF = 20,  // 4 slots
-  SC_ADJ = 26,  // adjoint sums: beta, nbar, A
-  SC_COUNT = 32
-};
+
 
 struct ModeIter {
   Grid g;
@@ -463,14 +576,9 @@ struct ModeIter {
   }
 };
 
-template <typename T>
-__device__ __forceinline__ double precond_inv(const T* tab, int radial, const Grid& g, int kx, int ky,
-                                              int kz, long i, double dbar) {
-  double m = (double)inv_lam_at(tab, radial, g, kx, ky, kz, i) + dbar;
-  return m > 0.0 ? 1.0 / m : 0.0;
-}
 
-// CG start on H x = rhs: x = 0, r = rhs_sign * rhs, p = M^-1 r; partials (r^H z, r^H r)
+// CG start on H x = rhs: x = 0, r = rhs_sign * rhs, p = 0 (the first
+// fused first pass then forms p = M^-1 r); partials (r^H M^-1 r, r^H r)
 template <typename T>
 __global__ void __launch_bounds__(RED_THREADS) cg_init_kernel(const cx<double>* __restrict__ rhs, double rhs_sign,
                                                               cx<T>* __restrict__ x, cx<T>* __restrict__ r,
@@ -487,69 +595,26 @@ __global__ void __launch_bounds__(RED_THREADS) cg_init_kernel(const cx<double>* 
     cx<double> b = rhs[i];
     cx<T> rv = {(T)(rhs_sign * b.x), (T)(rhs_sign * b.y)};
     double minv = precond_inv(tab, radial, g, kx, ky, kz, i, dbar);
-    cx<T> z = {(T)(minv * rv.x), (T)(minv * rv.y)};
     x[i] = {T(0), T(0)};
     r[i] = rv;
-    p[i] = z;
+    p[i] = {T(0), T(0)};
     double hw = herm_w(kz, g);
-    acc[0] += hw * ((double)rv.x * z.x + (double)rv.y * z.y);
+    acc[0] += hw * minv * ((double)rv.x * rv.x + (double)rv.y * rv.y);
     acc[1] += hw * ((double)rv.x * rv.x + (double)rv.y * rv.y);
   }
   block_reduce_store<2>(acc, partials, blockIdx.x);
-}
-
-// x += alpha p; r -= alpha q; partials (r^H r, r^H M^-1 r)
-template <typename T>
-__global__ void __launch_bounds__(RED_THREADS) cg_update1_kernel(cx<T>* __restrict__ x, const cx<T>* __restrict__ p,
-                                                                 cx<T>* __restrict__ r, const cx<T>* __restrict__ q,
-                                                                 const T* __restrict__ tab, int radial, Grid g,
-                                                                 long nh, const double* __restrict__ scal,
-                                                                 double* __restrict__ partials) {
-  ModeIter mi{g};
-  const T alpha = (T)scal[SC_ALPHA];
-  const double dbar = scal[SC_DBAR];
-  double acc[2] = {0.0, 0.0};
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nh; i += (long)gridDim.x * blockDim.x) {
-    int kx, ky, kz;
-    mi.decompose(i, kx, ky, kz);
-    cx<T> pv = p[i], qv = q[i], xv = x[i], rv = r[i];
-    xv = {xv.x + alpha * pv.x, xv.y + alpha * pv.y};
-    rv = {rv.x - alpha * qv.x, rv.y - alpha * qv.y};
-    x[i] = xv;
-    r[i] = rv;
-    double minv = precond_inv(tab, radial, g, kx, ky, kz, i, dbar);
-    double hw = herm_w(kz, g);
-    double rr = (double)rv.x * rv.x + (double)rv.y * rv.y;
-    acc[0] += hw * rr;
-    acc[1] += hw * minv * rr;
-  }
-  block_reduce_store<2>(acc, partials, blockIdx.x);
-}
-
-// p = M^-1 r + beta p
-template <typename T>
-__global__ void __launch_bounds__(RED_THREADS) cg_update2_kernel(cx<T>* __restrict__ p, const cx<T>* __restrict__ r,
-                                                                 const T* __restrict__ tab, int radial, Grid g,
-                                                                 long nh, const double* __restrict__ scal) {
-  ModeIter mi{g};
-  const T beta = (T)scal[SC_BETA];
-  const double dbar = scal[SC_DBAR];
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nh; i += (long)gridDim.x * blockDim.x) {
-    int kx, ky, kz;
-    mi.decompose(i, kx, ky, kz);
-    T minv = (T)precond_inv(tab, radial, g, kx, ky, kz, i, dbar);
-    cx<T> rv = r[i], pv = p[i];
-    p[i] = {minv * rv.x + beta * pv.x, minv * rv.y + beta * pv.y};
-  }
 }
 
 #ifdef PL_OPS_KERNELS
 enum FinKind { FIN_STORE = 0, FIN_CG_INIT = 1, FIN_CG_ALPHA = 2, FIN_CG_BETA = 3, FIN_DBAR = 4 };
 
 // Sum partials[nb][K] in a fixed order; then scalar bookkeeping.
+// kind FIN_CG_ALPHA: p^H H p = scale2 * sum(partials2[nb2]) (prior part from
+// the first pass) + scale * sum(partials[nb][K], k = 0) (diagonal part).
 __global__ void __launch_bounds__(256) finalize_kernel(const double* __restrict__ partials, int nb, int K,
                                                        int kind, int dst, double scale, double* __restrict__ scal,
-                                                       double aux) {
+                                                       double aux, const double* __restrict__ partials2, int nb2,
+                                                       double scale2) {
   __shared__ double sh[8][256];
   for (int k = 0; k < K; ++k) {
     double acc = 0.0;
@@ -561,6 +626,19 @@ __global__ void __launch_bounds__(256) finalize_kernel(const double* __restrict_
     if (threadIdx.x < s)
       for (int k = 0; k < K; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
     __syncthreads();
+  }
+  double extra = 0.0;
+  if (partials2) {
+    __syncthreads();
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nb2; i += 256) acc += partials2[i];
+    sh[7][threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (threadIdx.x < st) sh[7][threadIdx.x] += sh[7][threadIdx.x + st];
+      __syncthreads();
+    }
+    extra = sh[7][0] * scale2;
   }
   if (threadIdx.x != 0) return;
   double v[8];
@@ -578,24 +656,23 @@ __global__ void __launch_bounds__(256) finalize_kernel(const double* __restrict_
       scal[SC_BETA] = 0.0;
       break;
     case FIN_CG_ALPHA: {
-      scal[SC_PQ] = v[0];
+      if (scal[SC_DONE] != 0.0) break;  // iteration skipped
+      const double pq = v[0] + extra;
+      scal[SC_PQ] = pq;
       double al = 0.0;
-      if (scal[SC_DONE] == 0.0 && v[0] > 0.0) al = scal[SC_RZ] / v[0];
-      if (scal[SC_DONE] == 0.0 && !(v[0] > 0.0)) scal[SC_DONE] = 2.0;  // breakdown
+      if (scal[SC_DONE] == 0.0 && pq > 0.0) al = scal[SC_RZ] / pq;
+      if (scal[SC_DONE] == 0.0 && !(pq > 0.0)) scal[SC_DONE] = 2.0;  // breakdown
       scal[SC_ALPHA] = al;
       break;
     }
     case FIN_CG_BETA: {
-      if (scal[SC_DONE] == 0.0) {
-        scal[SC_ITS] += 1.0;
-        scal[SC_RR] = v[0];
-        double b = scal[SC_RZ] > 0.0 ? v[1] / scal[SC_RZ] : 0.0;
-        scal[SC_RZ] = v[1];
-        scal[SC_BETA] = b;
-        if (v[0] <= scal[SC_TOL2] || scal[SC_ITS] >= aux) scal[SC_DONE] = 1.0;
-      } else {
-        scal[SC_BETA] = 0.0;
-      }
+      if (scal[SC_DONE] != 0.0) break;  // iteration skipped
+      scal[SC_ITS] += 1.0;
+      scal[SC_RR] = v[0];
+      const double b = scal[SC_RZ] > 0.0 ? v[1] / scal[SC_RZ] : 0.0;
+      scal[SC_RZ] = v[1];
+      scal[SC_BETA] = b;
+      if (v[0] <= scal[SC_TOL2] || scal[SC_ITS] >= aux) scal[SC_DONE] = 1.0;
       break;
     }
     case FIN_DBAR:

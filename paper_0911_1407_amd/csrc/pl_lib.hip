@@ -37,10 +37,9 @@ struct pl_plan {
   size_t ws_bytes = 0;
   char* ws = nullptr;
   // spectral FP64 vectors
-  cx<double>*s_hat = nullptr, *g_hat = nullptr, *x64 = nullptr, *r64 = nullptr, *p64 = nullptr, *q64 = nullptr,
-  *t64 = nullptr;
+  cx<double>*s_hat = nullptr, *g_hat = nullptr, *x64 = nullptr, *r64 = nullptr, *p64 = nullptr, *t64 = nullptr;
   // spectral FP32 vectors (mixed precision)
-  cx<float>*x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *t32 = nullptr;
+  cx<float>*x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *t32 = nullptr;
   // real fields
   double *s_ws = nullptr, *e = nullptr, *d = nullptr, *preal = nullptr, *rtmp = nullptr;
   float *d32 = nullptr, *preal32 = nullptr;
@@ -97,7 +96,6 @@ size_t carve(pl_plan* p, char* base) {
   p->x64 = (cx<double>*)take(c64);
   p->r64 = (cx<double>*)take(c64);
   p->p64 = (cx<double>*)take(c64);
-  p->q64 = (cx<double>*)take(c64);
   p->t64 = (cx<double>*)take(c64);
   p->s_ws = (double*)take(r64);
   p->e = (double*)take(r64);
@@ -113,7 +111,6 @@ size_t carve(pl_plan* p, char* base) {
     p->x32 = (cx<float>*)take(c32);
     p->r32 = (cx<float>*)take(c32);
     p->p32 = (cx<float>*)take(c32);
-    p->q32 = (cx<float>*)take(c32);
     p->t32 = (cx<float>*)take(c32);
     p->d32 = (float*)take(r32);
     p->preal32 = (float*)take(r32);
@@ -129,7 +126,9 @@ size_t carve(pl_plan* p, char* base) {
     maxb = std::max(maxb, (long)p->n[0] * p->n[1] / 2 + 1);  // row pass, >= 1 pair per block
   }
   p->partials_len = maxb * 4;
-  p->partials = (double*)take(sizeof(double) * p->partials_len);
+  // two regions: the fused CG keeps the first pass's partials while the z
+  // pass writes its own
+  p->partials = (double*)take(sizeof(double) * p->partials_len * 2);
   p->scal = (double*)take(sizeof(double) * SC_COUNT);
   p->flags = (int*)take(sizeof(int) * 4);
   return off;
@@ -158,7 +157,6 @@ struct View<double> {
   static cx<double>* x(pl_plan* p) { return p->x64; }
   static cx<double>* r(pl_plan* p) { return p->r64; }
   static cx<double>* pv(pl_plan* p) { return p->p64; }
-  static cx<double>* q(pl_plan* p) { return p->q64; }
   static cx<double>* t(pl_plan* p) { return p->t64; }
   static double* preal(pl_plan* p) { return p->preal; }
   static const double* tab(pl_plan* p) { return p->radial ? p->tab_rad : p->tab_mode; }
@@ -169,7 +167,6 @@ struct View<float> {
   static cx<float>* x(pl_plan* p) { return p->x32; }
   static cx<float>* r(pl_plan* p) { return p->r32; }
   static cx<float>* pv(pl_plan* p) { return p->p32; }
-  static cx<float>* q(pl_plan* p) { return p->q32; }
   static cx<float>* t(pl_plan* p) { return p->t32; }
   static float* preal(pl_plan* p) { return p->preal32; }
   static const float* tab(pl_plan* p) { return p->radial ? p->tab_rad32 : p->tab_mode32; }
@@ -232,9 +229,11 @@ hipError_t run_row(pl_plan* p, int op, const RowArgs<T>& a, int* nb) {
   return launch_row<T>(p->n[2], op, a, p->stream, nb ? nb : &dummy);
 }
 
-hipError_t finalize(pl_plan* p, int nb, int K, int kind, int dst, double scale, double aux = 0.0) {
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, p->stream, p->partials, nb, K, kind, dst, scale,
-                     p->scal, aux);
+hipError_t finalize(pl_plan* p, int nb, int K, int kind, int dst, double scale, double aux = 0.0,
+                    const double* partials = nullptr, const double* partials2 = nullptr, int nb2 = 0,
+                    double scale2 = 0.0) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, p->stream, partials ? partials : p->partials, nb, K,
+                     kind, dst, scale, p->scal, aux, partials2, nb2, scale2);
   return hipGetLastError();
 }
 
@@ -330,15 +329,28 @@ int ensure_d32(pl_plan* p) {
 }
 
 // ---------------------------------------------------------------------------
-// Preconditioned CG on H x = sign * rhs (spectral), T precision vectors.
-// Returns PL_OK; *its receives iterations that changed x, *hvps launches.
+// Preconditioned CG on H x = sign * rhs (spectral, T-precision vectors), with
+// the vector updates fused into the Hessian-vector passes:
+//   pass 1 (x, inverse):  p = M^-1 r + beta p; partial p^H Lambda^-1 p
+//   passes 2-4:           y inverse, z (c2r, times d, r2c; partial sum d v^2), y forward
+//   finalize:             alpha = r^H M^-1 r / (p^H Lambda^-1 p + sum d v^2)
+//   pass 5 (x, forward):  r -= alpha (F[d v] + p/lambda); x += alpha p;
+//                         partials r^H r, r^H M^-1 r
+//   finalize:             beta, convergence
+// alpha = -(xi^T grad Q)/(xi^T H xi) is the step of eq. (New5) for the
+// local quadratic model; it is known before the last pass, which applies it
+// to r and x without storing H p.  Iterations queued after convergence exit
+// at once on the device (the passes read the done flag).
+// *its receives iterations that changed x, *hvps the Hessian products run.
 // ---------------------------------------------------------------------------
 template <typename T>
 int pcg(pl_plan* p, const cx<double>* rhs, double sign, double tol_abs, double tol_rel_of_rhs, int max_cg,
         int check_every, int* its, int* hvps, double* rel_res, double* rhs_norm) {
-  cx<T>*x = View<T>::x(p), *r = View<T>::r(p), *pp = View<T>::pv(p), *q = View<T>::q(p);
+  cx<T>*x = View<T>::x(p), *r = View<T>::r(p), *pp = View<T>::pv(p), *t = View<T>::t(p);
   const T* tab = View<T>::tab(p);
   const double invN = 1.0 / (double)p->N;
+  double* part_a = p->partials;
+  double* part_b = p->partials + p->partials_len;
   HIPCHK(p, set_scalar(p, SC_TOL2, tol_abs * tol_abs));
   hipLaunchKernelGGL((cg_init_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, rhs, sign, x, r, pp, tab,
                      p->radial, p->g, p->Nh, p->scal, p->partials);
@@ -353,22 +365,40 @@ int pcg(pl_plan* p, const cx<double>* rhs, double sign, double tol_abs, double t
     HIPCHK(p, set_scalar(p, SC_TOL2, tol2));
     HIPCHK(p, set_scalar(p, SC_DONE, rr0 <= tol2 ? 1.0 : 0.0));
   }
-  *hvps = 0;
   int launched = 0;
   while (launched < max_cg) {
     int chunk = std::min(check_every, max_cg - launched);
     for (int k = 0; k < chunk; ++k) {
-      int nb = 0;
-      int rc = hvp_hat<T>(p, pp, q, &nb);
-      if (rc) return rc;
-      HIPCHK(p, finalize(p, nb, 3, FIN_CG_ALPHA, 0, invN));
-      hipLaunchKernelGGL((cg_update1_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, x, pp, r, q, tab,
-                         p->radial, p->g, p->Nh, p->scal, p->partials);
-      HIPCHK(p, hipGetLastError());
-      HIPCHK(p, finalize(p, NB_RED, 2, FIN_CG_BETA, 0, invN, (double)max_cg));
-      hipLaunchKernelGGL((cg_update2_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, pp, r, tab,
-                         p->radial, p->g, p->Nh, p->scal);
-      HIPCHK(p, hipGetLastError());
+      int nb1 = 0, nb3 = 0, nb5 = 0;
+      const double* skip = p->scal + SC_DONE;
+      ColArgs<T> c1 = col_args<T>(p, 0, pp, t);
+      c1.cg_r = r;
+      c1.scal = p->scal;
+      c1.partials = part_a;
+      c1.skip = skip;
+      HIPCHK(p, run_col<T>(p, 0, true, COL_CG_FIRST, c1, &nb1));
+      ColArgs<T> c2 = col_args<T>(p, 1, t, t);
+      c2.skip = skip;
+      HIPCHK(p, run_col<T>(p, 1, true, COL_PLAIN, c2, nullptr));
+      RowArgs<T> ra = row_args<T>(p);
+      ra.in_c = t;
+      ra.out_c = t;
+      ra.partials = part_b;
+      ra.skip = skip;
+      HIPCHK(p, run_row<T>(p, ROW_HVP, ra, &nb3));
+      HIPCHK(p, finalize(p, nb3, 2, FIN_CG_ALPHA, 0, 1.0, 0.0, part_b, part_a, nb1, invN));
+      ColArgs<T> c4 = col_args<T>(p, 1, t, t);
+      c4.skip = skip;
+      HIPCHK(p, run_col<T>(p, 1, false, COL_PLAIN, c4, nullptr));
+      ColArgs<T> c5 = col_args<T>(p, 0, t, t);
+      c5.base = pp;
+      c5.cg_r = r;
+      c5.cg_x = x;
+      c5.scal = p->scal;
+      c5.partials = part_a;
+      c5.skip = skip;
+      HIPCHK(p, run_col<T>(p, 0, false, COL_CG_LAST, c5, &nb5));
+      HIPCHK(p, finalize(p, nb5, 2, FIN_CG_BETA, 0, invN, (double)max_cg, part_a));
     }
     launched += chunk;
     int rc = read_scalars(p);
@@ -378,7 +408,9 @@ int pcg(pl_plan* p, const cx<double>* rhs, double sign, double tol_abs, double t
   int rc = read_scalars(p);
   if (rc) return rc;
   *its = (int)p->h_scal[SC_ITS];
-  *hvps = launched;
+  // Hessian products that ran: one per counted iteration, plus the partial
+  // one of a breakdown; queued iterations after convergence exit at once
+  *hvps = *its + (p->h_scal[SC_DONE] == 2.0 ? 1 : 0);
   if (rel_res) *rel_res = std::sqrt(std::max(0.0, p->h_scal[SC_RR]));
   if (rhs_norm) *rhs_norm = std::sqrt(rr0);
   return PL_OK;
@@ -407,7 +439,7 @@ pl_solve_opts resolve_opts(pl_plan* p, const pl_solve_opts* o) {
   pl_default_opts(&r);
   if (o) r = *o;
   if (r.precision < 0) r.precision = p->precision;
-  if (r.check_every <= 0) r.check_every = 8;
+  if (r.check_every <= 0) r.check_every = 16;
   return r;
 }
 
@@ -439,7 +471,9 @@ int newton_solve(pl_plan* p, double* s_io, const pl_solve_opts& o, pl_solve_info
         p->err = "Newton iteration cap reached";
         break;
       }
-      const double eta = std::min(o.eta_max, std::sqrt(gn / g0));
+      // forcing term: sqrt(||g||/||g0||), but no tighter than needed to
+      // reach the stopping tolerance from here (half of it, for margin)
+      const double eta = std::min(o.eta_max, std::max(std::sqrt(gn / g0), 0.5 * o.rtol * g0 / gn));
       HIPCHK(p, set_scalar(p, SC_DBAR, p->h_scal[SC_DSUM] * invN));
       if constexpr (sizeof(T) == 4) {
         rc = ensure_d32(p);
@@ -588,7 +622,7 @@ void pl_default_opts(pl_solve_opts* o) {
   o->eta_max = 0.5;
   o->ls_c1 = 1e-4;
   o->precision = -1;
-  o->check_every = 8;
+  o->check_every = 16;
 }
 
 int pl_plan_create(pl_plan** out, const int32_t n[3], const double box[3], int precision, void* hip_stream,

@@ -19,6 +19,10 @@ static hipError_t col_launch_n(bool inverse, int op, const ColArgs<T>& a, int ns
     hipLaunchKernelGGL((col_kernel<T, N, false, COL_PRIOR>), grid, dim3(S::THREADS), 0, st, a);
   } else if (op == COL_ADDPRIOR) {
     hipLaunchKernelGGL((col_kernel<T, N, false, COL_ADDPRIOR>), grid, dim3(S::THREADS), 0, st, a);
+  } else if (op == COL_CG_FIRST) {
+    hipLaunchKernelGGL((col_kernel<T, N, true, COL_CG_FIRST>), grid, dim3(S::THREADS), 0, st, a);
+  } else if (op == COL_CG_LAST) {
+    hipLaunchKernelGGL((col_kernel<T, N, false, COL_CG_LAST>), grid, dim3(S::THREADS), 0, st, a);
   } else {
     return hipErrorInvalidValue;
   }

@@ -43,3 +43,19 @@ def test_plan_create_rejects_unsupported_sizes_without_gpu():
         with pytest.raises(binding.PLError) as e:
             binding.pl_plan_create(n, (1.0, 1.0, 1.0))
         assert e.value.code == binding.PL_ERR_UNSUPPORTED_SIZE
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpl.so not built")
+def test_every_pass_variant_is_instantiated():
+    # each supported length has a device kernel for every column / row
+    # operation the host dispatches (catches a dispatch table that misses one)
+    import subprocess
+    syms = subprocess.run(["nm", "-C", LIB], capture_output=True, text=True).stdout
+    from paper_0911_1407_amd import binding
+    col_ops = [("true", 0), ("false", 0), ("false", 1), ("false", 2), ("true", 3), ("false", 4)]
+    for n in binding.SUPPORTED_LENGTHS:
+        for T in ("double", "float"):
+            for inv, op in col_ops:
+                assert f"col_kernel<{T}, {n}, {inv}, {op}>" in syms, (T, n, inv, op)
+            for op in ((0, 1, 2, 3, 4, 5) if T == "double" else (0, 1, 2, 4)):
+                assert f"row_kernel<{T}, {n}, {op}>" in syms, (T, n, op)
