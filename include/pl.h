@@ -170,6 +170,33 @@ int pl_solve_adjoint(pl_plan* plan, const double* s_star, const double* dL_ds, d
 /* Message for the last failing call on plan (never NULL). */
 const char* pl_last_error(const pl_plan* plan);
 
+/* ---------------------------------------------------------------------------
+ * Batched MAP solves: many independent reconstructions (each its own grid,
+ * box and posterior) solved together.  Every pass of every Newton / CG step
+ * is ONE launch over all instances (a per-block work list of (instance,
+ * tile)); converged instances are masked out on the device; the CG steps
+ * between host convergence checks are captured once as a HIP graph and
+ * replayed.  Each axis length must be one of 32, 48, 64, 96, 128.
+ * ------------------------------------------------------------------------- */
+typedef struct pl_batch pl_batch;
+
+/* n: n_inst * 3 grid lengths, box: n_inst * 3 box sides (Mpc/h), host arrays.
+   precision: PL_FP64 or PL_MIXED (Krylov/HVP in FP32 for PL_MIXED solves).
+   The batch runs on its own internal stream and joins hip_stream (the
+   caller's) at the start and end of pl_batch_solve. */
+int pl_batch_create(pl_batch** out, int n_inst, const int32_t* n, const double* box, int precision,
+                    void* hip_stream, size_t* workspace_bytes);
+int pl_batch_set_workspace(pl_batch* batch, void* dev_ptr);
+/* Set instance i's posterior (same contract as pl_set_problem). */
+int pl_batch_set_problem(pl_batch* batch, int i, const pl_problem* prob);
+/* s_inout: host array of n_inst device pointers (start on input, MAP on
+   output); infos: host array of n_inst (nullable).  Returns PL_OK if every
+   instance converged, else the first failing instance's status; per-instance
+   statuses are in infos[i].status. */
+int pl_batch_solve(pl_batch* batch, double* const* s_inout, const pl_solve_opts* opts, pl_solve_info* infos);
+int pl_batch_destroy(pl_batch* batch);
+const char* pl_batch_last_error(const pl_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -31,7 +31,10 @@ SUPPORTED_LENGTHS = (8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 512)
 EXPORTED = ("pl_default_opts", "pl_plan_create", "pl_plan_set_workspace", "pl_plan_set_stream",
             "pl_plan_destroy", "pl_set_problem", "pl_grad", "pl_hessvec", "pl_hessvec_f32",
             "pl_hessvec_hat", "pl_hessvec_hat_f32", "pl_newton_krylov_solve", "pl_solve_adjoint",
-            "pl_last_error")
+            "pl_last_error", "pl_batch_create", "pl_batch_set_workspace", "pl_batch_set_problem",
+            "pl_batch_solve", "pl_batch_destroy", "pl_batch_last_error")
+
+BATCH_LENGTHS = (32, 48, 64, 96, 128)
 
 
 class PLError(RuntimeError):
@@ -93,8 +96,17 @@ def load(path=LIB_PATH):
                                      ctypes.POINTER(pl_solve_info)]
     lib.pl_last_error.argtypes = [vp]
     lib.pl_last_error.restype = ctypes.c_char_p
+    lib.pl_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(dbl), i32, vp, ctypes.POINTER(ctypes.c_size_t)]
+    lib.pl_batch_set_workspace.argtypes = [vp, vp]
+    lib.pl_batch_set_problem.argtypes = [vp, i32, ctypes.POINTER(pl_problem)]
+    lib.pl_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(pl_solve_opts),
+                                   ctypes.POINTER(pl_solve_info)]
+    lib.pl_batch_destroy.argtypes = [vp]
+    lib.pl_batch_last_error.argtypes = [vp]
+    lib.pl_batch_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
-        if name not in ("pl_default_opts", "pl_last_error"):
+        if name not in ("pl_default_opts", "pl_last_error", "pl_batch_last_error"):
             getattr(lib, name).restype = i32
     _lib = lib
     return lib
@@ -194,6 +206,53 @@ def pl_solve_adjoint(h, s_star, dL_ds, lambda_out=None, dL_dN=None, dL_dw=None, 
 
 def pl_last_error(h):
     return load().pl_last_error(h).decode()
+
+
+def pl_batch_create(ns, boxes, precision=PL_FP64, stream=None):
+    """ns, boxes: sequences of 3-tuples.  Returns (handle, workspace_bytes)."""
+    lib = load()
+    k = len(ns)
+    h = ctypes.c_void_p()
+    nn = (ctypes.c_int32 * (3 * k))(*[int(v) for n in ns for v in n])
+    bb = (ctypes.c_double * (3 * k))(*[float(v) for b in boxes for v in b])
+    ws = ctypes.c_size_t()
+    rc = lib.pl_batch_create(ctypes.byref(h), k, nn, bb, int(precision), stream, ctypes.byref(ws))
+    if rc != PL_OK:
+        raise PLError(rc, "pl_batch_create")
+    return h, ws.value
+
+
+def _bcheck(h, rc, allow=()):
+    if rc != PL_OK and rc not in allow:
+        raise PLError(rc, load().pl_batch_last_error(h).decode() if h else "")
+    return rc
+
+
+def pl_batch_set_workspace(h, ws_tensor):
+    return _bcheck(h, load().pl_batch_set_workspace(h, _ptr(ws_tensor)))
+
+
+def pl_batch_set_problem(h, i, w, counts, pk, amp, mu, nbar, beta=1.0, inv_p0=0.0):
+    pr = pl_problem(_ptr(w).value, _ptr(counts).value, _ptr(pk).value, float(amp), float(mu), float(nbar),
+                    float(beta), float(inv_p0))
+    return _bcheck(h, load().pl_batch_set_problem(h, int(i), ctypes.byref(pr)))
+
+
+def pl_batch_solve(h, s_list, opts=None):
+    k = len(s_list)
+    ptrs = (ctypes.c_void_p * k)(*[t.data_ptr() for t in s_list])
+    infos = (pl_solve_info * k)()
+    rc = load().pl_batch_solve(h, ptrs, ctypes.byref(opts) if opts else None, infos)
+    _bcheck(h, rc, allow=(PL_ERR_NOT_CONVERGED, PL_ERR_LINESEARCH))
+    return [infos[i].as_dict() for i in range(k)]
+
+
+def pl_batch_destroy(h):
+    return load().pl_batch_destroy(h)
+
+
+def pl_batch_last_error(h):
+    return load().pl_batch_last_error(h).decode()
 
 
 # ---------------------------------------------------------------------------
@@ -296,6 +355,52 @@ class Plan:
     def close(self):
         if self.h:
             pl_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent reconstructions solved together (one launch per pass)."""
+
+    def __init__(self, instances, precision="mixed", device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.precision = PL_MIXED if precision in ("mixed", PL_MIXED) else PL_FP64
+        self.ns = [tuple(int(v) for v in it["n"]) for it in instances]
+        boxes = [tuple(float(v) for v in it["box"]) for it in instances]
+        st = torch.cuda.current_stream(self.device)
+        self.h, ws_bytes = pl_batch_create(self.ns, boxes, self.precision, ctypes.c_void_p(st.cuda_stream))
+        self.ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.ws.data_ptr()) % 256
+        pl_batch_set_workspace(self.h, self.ws[off:])
+        self._keep = []
+        self.mus = []
+        for i, it in enumerate(instances):
+            w, c, pk = (torch.from_numpy(np.ascontiguousarray(it[k])).to(self.device, torch.float64)
+                        for k in ("w", "counts", "pk"))
+            self._keep.append((w, c, pk))
+            pl_batch_set_problem(self.h, i, w, c, pk, it["amp"], it["mu"], it["nbar"], it.get("beta", 1.0),
+                                 it.get("inv_p0", 0.0))
+            self.mus.append(float(it["mu"]))
+
+    def solve(self, s0_list=None, **kw):
+        t = self.torch
+        if s0_list is None:
+            s = [t.full(n, mu, dtype=t.float64, device=self.device) for n, mu in zip(self.ns, self.mus)]
+        else:
+            s = [x.to(self.device, t.float64).clone() for x in s0_list]
+        infos = pl_batch_solve(self.h, s, make_opts(**kw))
+        return s, infos
+
+    def close(self):
+        if self.h:
+            pl_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -16,7 +16,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 OUT = os.path.join(HERE, "libpl.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["pl_passes_f64.hip", "pl_passes_f32.hip", "pl_lib.hip"]
+SOURCES = ["pl_passes_f64.hip", "pl_passes_f32.hip", "pl_batch_kernels.hip", "pl_lib.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("PL_OFFLOAD_ARCH", "gfx950")

@@ -255,9 +255,10 @@ struct PaddedLen {
   static constexpr int value = PAD ? (N + (N >> 4) + 1) : N;
 };
 
-// Exchange between stage S-1 (outputs) and stage S (inputs).
+// Exchange between stage S-1 (outputs) and stage S (inputs).  Threads with
+// active == false take part in the barriers only.
 template <class PL, int S, class MAP, typename T>
-__device__ __forceinline__ void stage_exchange(cx<T>* v, int t, cx<T>* lds) {
+__device__ __forceinline__ void stage_exchange(cx<T>* v, int t, cx<T>* lds, bool active) {
   constexpr int RP = StageInfo<PL, S - 1>::R;
   constexpr int R = StageInfo<PL, S>::R;
   if constexpr (PL::P == 1) {
@@ -272,15 +273,19 @@ __device__ __forceinline__ void stage_exchange(cx<T>* v, int t, cx<T>* lds) {
       for (int r = 0; r < R; ++r) v[q * R + r] = tmp[in_pos<PL, S>(0, q, r)];
   } else {
     __syncthreads();
+    if (active) {
 #pragma unroll
-    for (int q = 0; q < PL::W / RP; ++q)
+      for (int q = 0; q < PL::W / RP; ++q)
 #pragma unroll
-      for (int m = 0; m < RP; ++m) lds[MAP::off(out_pos<PL, S - 1>(t, q, m))] = v[q * RP + m];
+        for (int m = 0; m < RP; ++m) lds[MAP::off(out_pos<PL, S - 1>(t, q, m))] = v[q * RP + m];
+    }
     __syncthreads();
+    if (active) {
 #pragma unroll
-    for (int q = 0; q < PL::W / R; ++q)
+      for (int q = 0; q < PL::W / R; ++q)
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q * R + r] = lds[MAP::off(in_pos<PL, S>(t, q, r))];
+        for (int r = 0; r < R; ++r) v[q * R + r] = lds[MAP::off(in_pos<PL, S>(t, q, r))];
+    }
   }
 }
 
@@ -288,22 +293,23 @@ __device__ __forceinline__ void stage_exchange(cx<T>* v, int t, cx<T>* lds) {
 // returns last-stage outputs (slot (q,m) <-> out_pos<NS-1>).  All threads of
 // the block must call this together when P > 1 (it contains barriers).
 template <class PL, bool INV, class MAP, typename T>
-__device__ __forceinline__ void fft_thread(cx<T>* v, int t, cx<T>* lds, const cx<T>* __restrict__ tw) {
-  stage_compute<PL, 0, INV>(v, t, tw);
+__device__ __forceinline__ void fft_thread(cx<T>* v, int t, cx<T>* lds, const cx<T>* __restrict__ tw,
+                                           bool active = true) {
+  if (active) stage_compute<PL, 0, INV>(v, t, tw);
   if constexpr (PL::NS > 1) {
-    stage_exchange<PL, 1, MAP>(v, t, lds);
-    stage_compute<PL, 1, INV>(v, t, tw);
+    stage_exchange<PL, 1, MAP>(v, t, lds, active);
+    if (active) stage_compute<PL, 1, INV>(v, t, tw);
   }
   if constexpr (PL::NS > 2) {
-    stage_exchange<PL, 2, MAP>(v, t, lds);
-    stage_compute<PL, 2, INV>(v, t, tw);
+    stage_exchange<PL, 2, MAP>(v, t, lds, active);
+    if (active) stage_compute<PL, 2, INV>(v, t, tw);
   }
 }
 
 // Move data held in last-stage output slots into stage-0 input slots (used
 // between an inverse and a forward transform of the same data).
 template <class PL, class MAP, typename T>
-__device__ __forceinline__ void last_to_first(cx<T>* v, int t, cx<T>* lds) {
+__device__ __forceinline__ void last_to_first(cx<T>* v, int t, cx<T>* lds, bool active = true) {
   constexpr int RL = LastStage<PL>::R;
   constexpr int R0 = PL::R0;
   if constexpr (RL == R0) {
@@ -321,15 +327,19 @@ __device__ __forceinline__ void last_to_first(cx<T>* v, int t, cx<T>* lds) {
       for (int r = 0; r < R0; ++r) v[q * R0 + r] = tmp[in_pos<PL, 0>(0, q, r)];
   } else {
     __syncthreads();
+    if (active) {
 #pragma unroll
-    for (int q = 0; q < PL::W / RL; ++q)
+      for (int q = 0; q < PL::W / RL; ++q)
 #pragma unroll
-      for (int m = 0; m < RL; ++m) lds[MAP::off(out_pos<PL, PL::NS - 1>(t, q, m))] = v[q * RL + m];
+        for (int m = 0; m < RL; ++m) lds[MAP::off(out_pos<PL, PL::NS - 1>(t, q, m))] = v[q * RL + m];
+    }
     __syncthreads();
+    if (active) {
 #pragma unroll
-    for (int q = 0; q < PL::W / R0; ++q)
+      for (int q = 0; q < PL::W / R0; ++q)
 #pragma unroll
-      for (int r = 0; r < R0; ++r) v[q * R0 + r] = lds[MAP::off(in_pos<PL, 0>(t, q, r))];
+        for (int r = 0; r < R0; ++r) v[q * R0 + r] = lds[MAP::off(in_pos<PL, 0>(t, q, r))];
+    }
   }
 }
 

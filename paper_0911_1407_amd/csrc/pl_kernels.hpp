@@ -90,6 +90,7 @@ enum Scal {
   SC_DBAR = 8,    // mean of the Hessian diagonal (preconditioner)
   SC_JUNK = 10,   // sink for an unused partial
   SC_GG = 11, SC_PRIOR = 12, SC_LIK = 13, SC_DSUM = 14,
+  SC_INACTIVE = 15,  // batched solves: instance finished, every pass skips it
   SC_LS_B = 16, SC_LS_C = 17, SC_LS_SLOPE = 18,
   SC_DF = 20,     // 4 slots
   SC_ADJ = 26,    // adjoint sums (4 slots)
@@ -119,6 +120,7 @@ enum ColOp {
 
 template <typename T>
 struct ColArgs {
+  int n;             // transform length
   const cx<T>* in;
   cx<T>* out;
   int ncols;         // columns per slab
@@ -155,10 +157,15 @@ struct ColShape {
   static constexpr int P = Plan<N>::P;
   static constexpr int B = col_tile(P, N, (int)sizeof(cx<T>));
   static constexpr int THREADS = B * P;
+  static constexpr int LDS = P > 1 ? N * B : 1;  // complex elements
 };
 
+// One workgroup's share of a column pass: tile `tile` of slab `slab`.
+// Threads beyond ColShape::THREADS (when a batched launch uses a larger
+// block) only take part in the barriers.
 template <typename T, int N, bool INV, int OP>
-__global__ void __launch_bounds__((ColShape<T, N>::THREADS)) col_kernel(ColArgs<T> a) {
+__device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab, cx<T>* lds_all,
+                                         int block_linear) {
   using PL = Plan<N>;
   constexpr int B = ColShape<T, N>::B;
   constexpr int P = PL::P;
@@ -166,27 +173,12 @@ __global__ void __launch_bounds__((ColShape<T, N>::THREADS)) col_kernel(ColArgs<
   constexpr int R0 = PL::R0;
   constexpr int RL = LastStage<PL>::R;
   using MAP = LdsMap<B, false>;
-  __shared__ cx<T> lds_all[P > 1 ? N * B : 1];
 
-  if (a.skip && *a.skip != 0.0) return;  // Krylov iteration after convergence
+  const bool active = (int)threadIdx.x < ColShape<T, N>::THREADS;
   const int cl = threadIdx.x % B;
-  const int t = threadIdx.x / B;
-  // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
-  // L2).  Give every XCD a contiguous range of (tile, slab) work items so
-  // that neighbouring column tiles, whose row segments share cache lines
-  // when the row pitch is not a multiple of 128 bytes, meet in one L2.
-  int tile = blockIdx.x, slab = blockIdx.y;
-  if (gridDim.y > 1) {
-    const int total = gridDim.x * gridDim.y;
-    const int hw = blockIdx.x + gridDim.x * blockIdx.y;
-    const int xcd = hw & 7, k = hw >> 3;
-    const int per = total >> 3, rem = total & 7;
-    const int logical = xcd * per + (xcd < rem ? xcd : rem) + k;
-    tile = logical % gridDim.x;
-    slab = logical / gridDim.x;
-  }
+  const int t = active ? (int)threadIdx.x / B : 0;
   const int c = tile * B + cl;
-  const bool valid = c < a.ncols;
+  const bool valid = active && c < a.ncols;
   const long base_off = (long)slab * a.slab_stride + (valid ? c : 0);
   cx<T>* lds = lds_all + cl;
 
@@ -218,8 +210,8 @@ __global__ void __launch_bounds__((ColShape<T, N>::THREADS)) col_kernel(ColArgs<
         }
         v[q * R0 + r] = pn;
       }
-    fft_thread<PL, true, MAP>(v, t, lds, a.tw);
-    block_reduce_store<1>(acc, a.partials, blockIdx.x + gridDim.x * blockIdx.y);
+    fft_thread<PL, true, MAP>(v, t, lds, a.tw, active);
+    block_reduce_store<1>(acc, a.partials, block_linear);
   } else {
 #pragma unroll
   for (int q = 0; q < W / R0; ++q)
@@ -233,12 +225,12 @@ __global__ void __launch_bounds__((ColShape<T, N>::THREADS)) col_kernel(ColArgs<
   if constexpr (OP == COL_CG_FIRST) {
     // done above
   } else if constexpr (OP == COL_PLAIN) {
-    fft_thread<PL, INV, MAP>(v, t, lds, a.tw);
+    fft_thread<PL, INV, MAP>(v, t, lds, a.tw, active);
   } else if constexpr (OP == COL_PRIOR) {
     // forward transform, multiply by 1/lambda (after removing the prior mean
     // from mode 0), inverse transform: S_L^-1 applied along the last axis of
     // a field already transformed along y and z.
-    fft_thread<PL, false, MAP>(v, t, lds, a.tw);
+    fft_thread<PL, false, MAP>(v, t, lds, a.tw, active);
     const int ky = c / a.g.h, kz = c % a.g.h;
     double acc[1] = {0.0};
 #pragma unroll
@@ -253,13 +245,13 @@ __global__ void __launch_bounds__((ColShape<T, N>::THREADS)) col_kernel(ColArgs<
         if (valid) acc[0] += herm_w(kz, a.g) * (double)il * ((double)x.x * x.x + (double)x.y * x.y);
         v[q * RL + m] = {x.x * il, x.y * il};
       }
-    last_to_first<PL, MAP>(v, t, lds);
-    fft_thread<PL, true, MAP>(v, t, lds, a.tw);
-    block_reduce_store<1>(acc, a.partials, blockIdx.x + gridDim.x * blockIdx.y);
+    last_to_first<PL, MAP>(v, t, lds, active);
+    fft_thread<PL, true, MAP>(v, t, lds, a.tw, active);
+    block_reduce_store<1>(acc, a.partials, block_linear);
   } else if constexpr (OP == COL_CG_LAST) {
     // forward transform; q = X + p/lambda (= H p); r -= alpha q and
     // x += alpha p in place; partials (r^H r, r^H M^-1 r).  q is not stored.
-    fft_thread<PL, false, MAP>(v, t, lds, a.tw);
+    fft_thread<PL, false, MAP>(v, t, lds, a.tw, active);
     const int ky = c / a.g.h, kz = c % a.g.h;
     const double hw = herm_w(kz, a.g);
     const double alpha = a.scal[SC_ALPHA], dbar = a.scal[SC_DBAR];
@@ -285,11 +277,11 @@ __global__ void __launch_bounds__((ColShape<T, N>::THREADS)) col_kernel(ColArgs<
           acc[1] += hw * mi * rr;
         }
       }
-    block_reduce_store<2>(acc, a.partials, blockIdx.x + gridDim.x * blockIdx.y);
+    block_reduce_store<2>(acc, a.partials, block_linear);
     return;
   } else {
     // forward transform; out = scale * X + (1/lambda) (base - shift at mode 0)
-    fft_thread<PL, false, MAP>(v, t, lds, a.tw);
+    fft_thread<PL, false, MAP>(v, t, lds, a.tw, active);
     const int ky = c / a.g.h, kz = c % a.g.h;
     double acc[3] = {0.0, 0.0, 0.0};
     const double hw = herm_w(kz, a.g);
@@ -312,7 +304,7 @@ __global__ void __launch_bounds__((ColShape<T, N>::THREADS)) col_kernel(ColArgs<
           acc[2] += hw * (double)il * ((double)bs.x * bs.x + (double)bs.y * bs.y);
         }
       }
-    block_reduce_store<3>(acc, a.partials, blockIdx.x + gridDim.x * blockIdx.y);
+    block_reduce_store<3>(acc, a.partials, block_linear);
   }
 
   if (valid) {
@@ -324,6 +316,28 @@ __global__ void __launch_bounds__((ColShape<T, N>::THREADS)) col_kernel(ColArgs<
         a.out[base_off + (long)e * a.row_stride] = v[q * RL + m];
       }
   }
+}
+
+
+template <typename T, int N, bool INV, int OP>
+__global__ void __launch_bounds__((ColShape<T, N>::THREADS)) col_kernel(ColArgs<T> a) {
+  __shared__ cx<T> lds_all[ColShape<T, N>::LDS];
+  if (a.skip && *a.skip != 0.0) return;  // Krylov iteration after convergence
+  // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+  // L2).  Give every XCD a contiguous range of (tile, slab) work items so
+  // that neighbouring column tiles, whose row segments share cache lines
+  // when the row pitch is not a multiple of 128 bytes, meet in one L2.
+  int tile = blockIdx.x, slab = blockIdx.y;
+  if (gridDim.y > 1) {
+    const int total = gridDim.x * gridDim.y;
+    const int hw = blockIdx.x + gridDim.x * blockIdx.y;
+    const int xcd = hw & 7, k = hw >> 3;
+    const int per = total >> 3, rem = total & 7;
+    const int logical = xcd * per + (xcd < rem ? xcd : rem) + k;
+    tile = logical % gridDim.x;
+    slab = logical / gridDim.x;
+  }
+  col_body<T, N, INV, OP>(a, tile, slab, lds_all, blockIdx.x + gridDim.x * blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -343,6 +357,7 @@ enum RowOp {
 
 template <typename T>
 struct RowArgs {
+  int n;  // transform length (z)
   const cx<T>* in_c;
   cx<T>* out_c;
   const T* in_r;
@@ -373,7 +388,7 @@ struct RowShape {
 };
 
 template <typename T, int N, int OP>
-__global__ void __launch_bounds__(RowShape<N>::THREADS) row_kernel(RowArgs<T> a) {
+__device__ __forceinline__ void row_body(const RowArgs<T>& a, int ublock, cx<T>* lds_all, int block_linear) {
   using PL = Plan<N>;
   constexpr int P = PL::P;
   constexpr int W = PL::W;
@@ -383,13 +398,12 @@ __global__ void __launch_bounds__(RowShape<N>::THREADS) row_kernel(RowArgs<T> a)
   constexpr int LEN = RowShape<N>::LEN;
   constexpr int H = N / 2 + 1;
   using MAP = LdsMap<1, true>;
-  __shared__ cx<T> lds_all[G * LEN];
 
-  if (a.skip && *a.skip != 0.0) return;  // Krylov iteration after convergence
+  const bool active = (int)threadIdx.x < RowShape<N>::THREADS;
   const int t = threadIdx.x % P;
-  const int ul = threadIdx.x / P;
-  const int u = blockIdx.x * G + ul;
-  const bool valid = u < a.nunits;
+  const int ul = active ? (int)threadIdx.x / P : 0;
+  const int u = ublock * G + ul;
+  const bool valid = active && u < a.nunits;
   const int uc = valid ? u : 0;
   cx<T>* lds = lds_all + ul * LEN;
   const long rowA = 2L * uc, rowB = 2L * uc + 1;
@@ -403,18 +417,19 @@ __global__ void __launch_bounds__(RowShape<N>::THREADS) row_kernel(RowArgs<T> a)
 #pragma unroll
       for (int r = 0; r < R0; ++r) {
         int e = in_pos<PL, 0>(t, q, r);
-        v[q * R0 + r] = {a.in_r[rowA * N + e], a.in_r[rowB * N + e]};
+        v[q * R0 + r] = valid ? cx<T>{a.in_r[rowA * N + e], a.in_r[rowB * N + e]} : cx<T>{T(0), T(0)};
       }
   } else {
     // load the two half rows (2H contiguous complex values) into LDS
     const cx<T>* src = a.in_c + rowA * H;
-    for (int i = t; i < 2 * H; i += P) lds[MAP::off(i)] = src[i];
+    if (active)
+      for (int i = t; i < 2 * H; i += P) lds[MAP::off(i)] = src[i];
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < W / R0; ++q)
 #pragma unroll
       for (int r = 0; r < R0; ++r) {
-        int e = in_pos<PL, 0>(t, q, r);
+        int e = active ? in_pos<PL, 0>(t, q, r) : 0;
         cx<T> A, Bv;
         if (e <= N / 2) {
           A = lds[MAP::off(e)];
@@ -431,9 +446,9 @@ __global__ void __launch_bounds__(RowShape<N>::THREADS) row_kernel(RowArgs<T> a)
   double acc[2] = {0.0, 0.0};
 
   if constexpr (OP == ROW_R2C) {
-    fft_thread<PL, false, MAP>(v, t, lds, a.tw);
+    fft_thread<PL, false, MAP>(v, t, lds, a.tw, active);
   } else {
-    fft_thread<PL, true, MAP>(v, t, lds, a.tw);
+    fft_thread<PL, true, MAP>(v, t, lds, a.tw, active);
     // v now holds z[e] = a[e] + i b[e] at last-stage slots (unscaled)
     if constexpr (OP == ROW_C2R) {
       if (valid) {
@@ -485,7 +500,7 @@ __global__ void __launch_bounds__(RowShape<N>::THREADS) row_kernel(RowArgs<T> a)
             }
           }
       }
-      block_reduce_store<2>(acc, a.partials, blockIdx.x);
+      block_reduce_store<2>(acc, a.partials, block_linear);
       return;
     } else {
       // pointwise work on the real values, then back to half spectra
@@ -535,18 +550,20 @@ __global__ void __launch_bounds__(RowShape<N>::THREADS) row_kernel(RowArgs<T> a)
             v[q * RL + m] = {(T)l[0], (T)l[1]};
           }
       }
-      last_to_first<PL, MAP>(v, t, lds);
-      fft_thread<PL, false, MAP>(v, t, lds, a.tw);
+      last_to_first<PL, MAP>(v, t, lds, active);
+      fft_thread<PL, false, MAP>(v, t, lds, a.tw, active);
     }
   }
 
   // ---- split Z' into the two half rows: A'[k] = (Z[k] + conj Z[N-k])/2,
   //      B'[k] = (Z[k] - conj Z[N-k])/(2i) ----
   __syncthreads();
+  if (active) {
 #pragma unroll
-  for (int q = 0; q < W / RL; ++q)
+    for (int q = 0; q < W / RL; ++q)
 #pragma unroll
-    for (int m = 0; m < RL; ++m) lds[MAP::off(out_pos<PL, PL::NS - 1>(t, q, m))] = v[q * RL + m];
+      for (int m = 0; m < RL; ++m) lds[MAP::off(out_pos<PL, PL::NS - 1>(t, q, m))] = v[q * RL + m];
+  }
   __syncthreads();
   if (valid) {
     cx<T>* dst = a.out_c + rowA * H;
@@ -557,7 +574,14 @@ __global__ void __launch_bounds__(RowShape<N>::THREADS) row_kernel(RowArgs<T> a)
       dst[H + k] = {T(0.5) * (zk.y + zc.y), T(0.5) * (zc.x - zk.x)};
     }
   }
-  if constexpr (OP == ROW_GRAD || OP == ROW_HVP) block_reduce_store<2>(acc, a.partials, blockIdx.x);
+  if constexpr (OP == ROW_GRAD || OP == ROW_HVP) block_reduce_store<2>(acc, a.partials, block_linear);
+}
+
+template <typename T, int N, int OP>
+__global__ void __launch_bounds__(RowShape<N>::THREADS) row_kernel(RowArgs<T> a) {
+  __shared__ cx<T> lds_all[RowShape<N>::G * RowShape<N>::LEN];
+  if (a.skip && *a.skip != 0.0) return;  // Krylov iteration after convergence
+  row_body<T, N, OP>(a, blockIdx.x, lds_all, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -580,16 +604,14 @@ struct ModeIter {
 // CG start on H x = rhs: x = 0, r = rhs_sign * rhs, p = 0 (the first
 // fused first pass then forms p = M^-1 r); partials (r^H M^-1 r, r^H r)
 template <typename T>
-__global__ void __launch_bounds__(RED_THREADS) cg_init_kernel(const cx<double>* __restrict__ rhs, double rhs_sign,
-                                                              cx<T>* __restrict__ x, cx<T>* __restrict__ r,
-                                                              cx<T>* __restrict__ p, const T* __restrict__ tab,
-                                                              int radial, Grid g, long nh,
-                                                              const double* __restrict__ scal,
-                                                              double* __restrict__ partials) {
+__device__ __forceinline__ void cg_init_body(const cx<double>* __restrict__ rhs, double rhs_sign, cx<T>* __restrict__ x,
+                                             cx<T>* __restrict__ r, cx<T>* __restrict__ p, const T* __restrict__ tab,
+                                             int radial, const Grid& g, long nh, const double* __restrict__ scal,
+                                             double* __restrict__ partials, int bx, int nbx) {
   ModeIter mi{g};
   const double dbar = scal[SC_DBAR];
   double acc[2] = {0.0, 0.0};
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nh; i += (long)gridDim.x * blockDim.x) {
+  for (long i = bx * (long)blockDim.x + threadIdx.x; i < nh; i += (long)nbx * blockDim.x) {
     int kx, ky, kz;
     mi.decompose(i, kx, ky, kz);
     cx<double> b = rhs[i];
@@ -602,7 +624,17 @@ __global__ void __launch_bounds__(RED_THREADS) cg_init_kernel(const cx<double>* 
     acc[0] += hw * minv * ((double)rv.x * rv.x + (double)rv.y * rv.y);
     acc[1] += hw * ((double)rv.x * rv.x + (double)rv.y * rv.y);
   }
-  block_reduce_store<2>(acc, partials, blockIdx.x);
+  block_reduce_store<2>(acc, partials, bx);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS) cg_init_kernel(const cx<double>* __restrict__ rhs, double rhs_sign,
+                                                              cx<T>* __restrict__ x, cx<T>* __restrict__ r,
+                                                              cx<T>* __restrict__ p, const T* __restrict__ tab,
+                                                              int radial, Grid g, long nh,
+                                                              const double* __restrict__ scal,
+                                                              double* __restrict__ partials) {
+  cg_init_body<T>(rhs, rhs_sign, x, r, p, tab, radial, g, nh, scal, partials, blockIdx.x, gridDim.x);
 }
 
 #ifdef PL_OPS_KERNELS
@@ -611,10 +643,9 @@ enum FinKind { FIN_STORE = 0, FIN_CG_INIT = 1, FIN_CG_ALPHA = 2, FIN_CG_BETA = 3
 // Sum partials[nb][K] in a fixed order; then scalar bookkeeping.
 // kind FIN_CG_ALPHA: p^H H p = scale2 * sum(partials2[nb2]) (prior part from
 // the first pass) + scale * sum(partials[nb][K], k = 0) (diagonal part).
-__global__ void __launch_bounds__(256) finalize_kernel(const double* __restrict__ partials, int nb, int K,
-                                                       int kind, int dst, double scale, double* __restrict__ scal,
-                                                       double aux, const double* __restrict__ partials2, int nb2,
-                                                       double scale2) {
+__device__ __forceinline__ void finalize_body(const double* __restrict__ partials, int nb, int K, int kind, int dst,
+                                              double scale, double* __restrict__ scal, double aux,
+                                              const double* __restrict__ partials2, int nb2, double scale2) {
   __shared__ double sh[8][256];
   for (int k = 0; k < K; ++k) {
     double acc = 0.0;
@@ -681,6 +712,13 @@ __global__ void __launch_bounds__(256) finalize_kernel(const double* __restrict_
   }
 }
 
+__global__ void __launch_bounds__(256) finalize_kernel(const double* __restrict__ partials, int nb, int K,
+                                                       int kind, int dst, double scale, double* __restrict__ scal,
+                                                       double aux, const double* __restrict__ partials2, int nb2,
+                                                       double scale2) {
+  finalize_body(partials, nb, K, kind, dst, scale, scal, aux, partials2, nb2, scale2);
+}
+
 __global__ void set_scalar_kernel(double* scal, int idx, double value) {
   if (threadIdx.x == 0 && blockIdx.x == 0) scal[idx] = value;
 }
@@ -701,14 +739,13 @@ __global__ void __launch_bounds__(RED_THREADS) axpy_hat_kernel(cx<double>* __res
 // Line-search dots on half spectra: b = <p, S^-1 (s - mu)>, c = <p, S^-1 p>,
 // slope = <g, p> (times N; the finalize applies 1/N).
 template <typename T>
-__global__ void __launch_bounds__(RED_THREADS) ls_dots_kernel(const cx<T>* __restrict__ p, const cx<double>* __restrict__ s_hat,
-                                                              const cx<double>* __restrict__ g_hat,
-                                                              const double* __restrict__ tab, int radial, Grid g,
-                                                              long nh, double k0_shift,
-                                                              double* __restrict__ partials) {
+__device__ __forceinline__ void ls_dots_body(const cx<T>* __restrict__ p, const cx<double>* __restrict__ s_hat,
+                                             const cx<double>* __restrict__ g_hat, const double* __restrict__ tab,
+                                             int radial, const Grid& g, long nh, double k0_shift,
+                                             double* __restrict__ partials, int bx, int nbx) {
   ModeIter mi{g};
   double acc[3] = {0.0, 0.0, 0.0};
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nh; i += (long)gridDim.x * blockDim.x) {
+  for (long i = bx * (long)blockDim.x + threadIdx.x; i < nh; i += (long)nbx * blockDim.x) {
     int kx, ky, kz;
     mi.decompose(i, kx, ky, kz);
     double il = inv_lam_at(tab, radial, g, kx, ky, kz, i);
@@ -720,17 +757,26 @@ __global__ void __launch_bounds__(RED_THREADS) ls_dots_kernel(const cx<T>* __res
     acc[1] += hw * il * ((double)pv.x * pv.x + (double)pv.y * pv.y);
     acc[2] += hw * ((double)pv.x * gv.x + (double)pv.y * gv.y);
   }
-  block_reduce_store<3>(acc, partials, blockIdx.x);
+  block_reduce_store<3>(acc, partials, bx);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS) ls_dots_kernel(const cx<T>* __restrict__ p, const cx<double>* __restrict__ s_hat,
+                                                              const cx<double>* __restrict__ g_hat,
+                                                              const double* __restrict__ tab, int radial, Grid g,
+                                                              long nh, double k0_shift,
+                                                              double* __restrict__ partials) {
+  ls_dots_body<T>(p, s_hat, g_hat, tab, radial, g, nh, k0_shift, partials, blockIdx.x, gridDim.x);
 }
 
 // Likelihood part of f(s + a p) - f(s) for four trial steps a_j:
 // sum_i [e_i expm1(a_j beta p_i) - a_j beta N_i p_i]
 template <typename T>
-__global__ void __launch_bounds__(RED_THREADS) ls_eval_kernel(const T* __restrict__ p, const double* __restrict__ e,
-                                                              const double* __restrict__ counts, double beta,
-                                                              double a0, long n, double* __restrict__ partials) {
+__device__ __forceinline__ void ls_eval_body(const T* __restrict__ p, const double* __restrict__ e,
+                                             const double* __restrict__ counts, double beta, double a0, long n,
+                                             double* __restrict__ partials, int bx, int nbx) {
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+  for (long i = bx * (long)blockDim.x + threadIdx.x; i < n; i += (long)nbx * blockDim.x) {
     double bp = beta * (double)p[i];
     double ei = e[i], ci = counts[i];
     double a = a0;
@@ -740,7 +786,14 @@ __global__ void __launch_bounds__(RED_THREADS) ls_eval_kernel(const T* __restric
       a *= 0.5;
     }
   }
-  block_reduce_store<4>(acc, partials, blockIdx.x);
+  block_reduce_store<4>(acc, partials, bx);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS) ls_eval_kernel(const T* __restrict__ p, const double* __restrict__ e,
+                                                              const double* __restrict__ counts, double beta,
+                                                              double a0, long n, double* __restrict__ partials) {
+  ls_eval_body<T>(p, e, counts, beta, a0, n, partials, blockIdx.x, gridDim.x);
 }
 
 #ifdef PL_OPS_KERNELS

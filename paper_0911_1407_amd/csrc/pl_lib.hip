@@ -12,6 +12,7 @@
 
 #include "../../include/pl.h"
 #define PL_OPS_KERNELS 1
+#include "pl_batch_kernels.hpp"
 #include "pl_passes.hpp"
 
 using namespace pl;
@@ -180,6 +181,7 @@ struct View<float> {
 template <typename T>
 ColArgs<T> col_args(pl_plan* p, int axis, const cx<T>* in, cx<T>* out) {
   ColArgs<T> a{};
+  a.n = p->n[axis];
   a.in = in;
   a.out = out;
   a.tw = View<T>::tw(p, axis);
@@ -210,6 +212,7 @@ hipError_t run_col(pl_plan* p, int axis, bool inverse, int op, const ColArgs<T>&
 template <typename T>
 RowArgs<T> row_args(pl_plan* p) {
   RowArgs<T> a{};
+  a.n = p->n[2];
   a.nunits = (int)((long)p->n[0] * p->n[1] / 2);
   a.tw = View<T>::tw(p, 2);
   a.scale = T(1.0 / (double)p->N);
@@ -443,6 +446,68 @@ pl_solve_opts resolve_opts(pl_plan* p, const pl_solve_opts* o) {
   return r;
 }
 
+// One Newton step at the current spectral iterate: inner PCG on
+// H p = -g in T precision, then the Armijo line search along p.  Returns
+// PL_OK with *alpha > 0 on success, *alpha < 0 if no step was found.
+template <typename T>
+int newton_step(pl_plan* p, double eta_gn, const pl_solve_opts& o, pl_solve_info& inf, double* alpha,
+                bool* descent) {
+  const double invN = 1.0 / (double)p->N;
+  int rc;
+  if constexpr (sizeof(T) == 4) {
+    rc = ensure_d32(p);
+    if (rc) return rc;
+  }
+  int its = 0, hv = 0;
+  rc = pcg<T>(p, p->g_hat, -1.0, eta_gn, 0.0, o.max_cg, o.check_every, &its, &hv, nullptr, nullptr);
+  if (rc) return rc;
+  inf.cg_its += its;
+  inf.hvps += hv;
+  // line search along the Newton direction x (spectral) / preal (real)
+  cx<T>* x = View<T>::x(p);
+  rc = inv_c2r<T>(p, x, View<T>::t(p), View<T>::preal(p));
+  if (rc) return rc;
+  hipLaunchKernelGGL((ls_dots_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, x, p->s_hat, p->g_hat,
+                     p->radial ? p->tab_rad : p->tab_mode, p->radial, p->g, p->Nh, (double)p->N * p->prob.mu,
+                     p->partials);
+  HIPCHK(p, hipGetLastError());
+  HIPCHK(p, finalize(p, NB_RED, 3, FIN_STORE, SC_LS_B, invN));
+  rc = read_scalars(p);
+  if (rc) return rc;
+  const double b = p->h_scal[SC_LS_B], c = p->h_scal[SC_LS_C], slope = p->h_scal[SC_LS_SLOPE];
+  *alpha = -1.0;
+  *descent = slope < 0.0;
+  if (slope < 0.0) {
+    double a0 = 1.0;
+    for (int batch = 0; batch < 8 && *alpha < 0.0; ++batch) {
+      hipLaunchKernelGGL((ls_eval_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, View<T>::preal(p),
+                         p->e, p->prob.counts, p->prob.beta, a0, p->N, p->partials);
+      HIPCHK(p, hipGetLastError());
+      HIPCHK(p, finalize(p, NB_RED, 4, FIN_STORE, SC_DF, 1.0));
+      rc = read_scalars(p);
+      if (rc) return rc;
+      double a = a0;
+      for (int j = 0; j < 4; ++j, a *= 0.5) {
+        double df = a * b + 0.5 * a * a * c + p->h_scal[SC_DF + j];
+        if (df <= o.ls_c1 * a * slope) {
+          *alpha = a;
+          break;
+        }
+      }
+      a0 *= 1.0 / 16.0;
+    }
+  }
+  if (*alpha > 0.0) {
+    hipLaunchKernelGGL((axpy_hat_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, p->s_hat, x, *alpha,
+                       p->Nh);
+    HIPCHK(p, hipGetLastError());
+  }
+  return PL_OK;
+}
+
+// Inexact Newton-Krylov from the current s_io.  In mixed precision (T =
+// float) a step whose FP32 direction fails the line search is redone with an
+// FP64 inner solve (refinement against the FP64 gradient).
 template <typename T>
 int newton_solve(pl_plan* p, double* s_io, const pl_solve_opts& o, pl_solve_info* info) {
   pl_solve_info inf{};
@@ -475,56 +540,21 @@ int newton_solve(pl_plan* p, double* s_io, const pl_solve_opts& o, pl_solve_info
       // reach the stopping tolerance from here (half of it, for margin)
       const double eta = std::min(o.eta_max, std::max(std::sqrt(gn / g0), 0.5 * o.rtol * g0 / gn));
       HIPCHK(p, set_scalar(p, SC_DBAR, p->h_scal[SC_DSUM] * invN));
-      if constexpr (sizeof(T) == 4) {
-        rc = ensure_d32(p);
-        if (rc) return rc;
-      }
-      int its = 0, hv = 0;
-      rc = pcg<T>(p, p->g_hat, -1.0, eta * gn, 0.0, o.max_cg, o.check_every, &its, &hv, nullptr, nullptr);
-      if (rc) return rc;
-      inf.cg_its += its;
-      inf.hvps += hv;
-      // line search along the Newton direction x (spectral) / preal (real)
-      cx<T>* x = View<T>::x(p);
-      rc = inv_c2r<T>(p, x, View<T>::t(p), View<T>::preal(p));
-      if (rc) return rc;
-      hipLaunchKernelGGL((ls_dots_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, x, p->s_hat, p->g_hat,
-                         p->radial ? p->tab_rad : p->tab_mode, p->radial, p->g, p->Nh,
-                         (double)p->N * p->prob.mu, p->partials);
-      HIPCHK(p, hipGetLastError());
-      HIPCHK(p, finalize(p, NB_RED, 3, FIN_STORE, SC_LS_B, invN));
-      rc = read_scalars(p);
-      if (rc) return rc;
-      const double b = p->h_scal[SC_LS_B], c = p->h_scal[SC_LS_C], slope = p->h_scal[SC_LS_SLOPE];
       double alpha = -1.0;
-      if (slope < 0.0) {
-        double a0 = 1.0;
-        for (int batch = 0; batch < 8 && alpha < 0.0; ++batch) {
-          hipLaunchKernelGGL((ls_eval_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream,
-                             View<T>::preal(p), p->e, p->prob.counts, p->prob.beta, a0, p->N, p->partials);
-          HIPCHK(p, hipGetLastError());
-          HIPCHK(p, finalize(p, NB_RED, 4, FIN_STORE, SC_DF, 1.0));
-          rc = read_scalars(p);
+      bool descent = false;
+      rc = newton_step<T>(p, eta * gn, o, inf, &alpha, &descent);
+      if (rc) return rc;
+      if constexpr (sizeof(T) == 4) {
+        if (alpha < 0.0) {
+          rc = newton_step<double>(p, eta * gn, o, inf, &alpha, &descent);
           if (rc) return rc;
-          double a = a0;
-          for (int j = 0; j < 4; ++j, a *= 0.5) {
-            double df = a * b + 0.5 * a * a * c + p->h_scal[SC_DF + j];
-            if (df <= o.ls_c1 * a * slope) {
-              alpha = a;
-              break;
-            }
-          }
-          a0 *= 1.0 / 16.0;
         }
       }
       if (alpha < 0.0) {
         status = PL_ERR_LINESEARCH;
-        p->err = slope < 0.0 ? "no step satisfies the Armijo condition" : "Newton direction is not a descent direction";
+        p->err = descent ? "no step satisfies the Armijo condition" : "Newton direction is not a descent direction";
         break;
       }
-      hipLaunchKernelGGL((axpy_hat_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, p->s_hat, x, alpha,
-                         p->Nh);
-      HIPCHK(p, hipGetLastError());
       rc = grad_hat(p, s_io);
       if (rc) return rc;
       rc = read_scalars(p);
@@ -897,3 +927,685 @@ bool supported_length(int n) {
   }
 }
 }  // namespace pl
+
+// ===========================================================================
+// Batched solves
+// ===========================================================================
+
+namespace {
+
+constexpr int NBB = 64;  // blocks per instance of the batched elementwise kernels
+
+template <typename T>
+int col_B(int n) {
+  switch (n) {
+#define PL_C(NN) \
+  case NN: return ColShape<T, NN>::B;
+    PL_BATCH_LENGTHS(PL_C)
+#undef PL_C
+    default: return 0;
+  }
+}
+
+int row_G(int n) {
+  switch (n) {
+#define PL_C(NN) \
+  case NN: return RowShape<NN>::G;
+    PL_BATCH_LENGTHS(PL_C)
+#undef PL_C
+    default: return 0;
+  }
+}
+
+int xcd_remap(int hw, int total) {
+  const int xcd = hw & 7, k = hw >> 3, per = total >> 3, rem = total & 7;
+  return xcd * per + (xcd < rem ? xcd : rem) + k;
+}
+
+// Work list of a column pass over all instances (axis 0: x, 1: y); blocks
+// ordered so that each XCD receives a contiguous range of work items.
+template <typename T>
+std::vector<int4> col_work(const std::vector<pl_plan*>& plans, int axis, std::vector<int>& nb) {
+  std::vector<int4> nat;
+  nb.assign(plans.size(), 0);
+  for (size_t i = 0; i < plans.size(); ++i) {
+    const pl_plan* p = plans[i];
+    const int h = p->g.h;
+    const int ncols = axis == 0 ? p->n[1] * h : h;
+    const int nslabs = axis == 0 ? 1 : p->n[0];
+    const int B = col_B<T>(p->n[axis]);
+    const int nbx = (ncols + B - 1) / B;
+    for (int sl = 0; sl < nslabs; ++sl)
+      for (int t = 0; t < nbx; ++t) nat.push_back(make_int4((int)i, t, sl, t + nbx * sl));
+    nb[i] = nbx * nslabs;
+  }
+  std::vector<int4> w(nat.size());
+  for (int hw = 0; hw < (int)nat.size(); ++hw) w[hw] = nat[xcd_remap(hw, (int)nat.size())];
+  return w;
+}
+
+std::vector<int4> row_work(const std::vector<pl_plan*>& plans, std::vector<int>& nb) {
+  std::vector<int4> nat;
+  nb.assign(plans.size(), 0);
+  for (size_t i = 0; i < plans.size(); ++i) {
+    const pl_plan* p = plans[i];
+    const int nunits = p->n[0] * p->n[1] / 2;
+    const int G = row_G(p->n[2]);
+    const int nbu = (nunits + G - 1) / G;
+    for (int b = 0; b < nbu; ++b) nat.push_back(make_int4((int)i, b, 0, b));
+    nb[i] = nbu;
+  }
+  std::vector<int4> w(nat.size());
+  for (int hw = 0; hw < (int)nat.size(); ++hw) w[hw] = nat[xcd_remap(hw, (int)nat.size())];
+  return w;
+}
+
+// Column / row pass kinds of a batched solve
+enum BCol { BC_SHAT_Y = 0, BC_SHAT_X, BC_G_XINV, BC_G_YINV, BC_G_YFWD, BC_G_XADD, BC_COUNT64 };
+enum BColT { BT_CG1 = 0, BT_CGYI, BT_CGYF, BT_CG5, BT_XCINV, BT_YCINV, BT_COUNT };
+enum BRow { BR_R2C = 0, BR_GRAD, BR_COUNT64 };
+enum BRowT { BRT_HVP = 0, BRT_C2R, BRT_COUNT };
+enum BFin { BF_GRAD_ROW = 0, BF_GRAD_X, BF_INIT, BF_ALPHA, BF_BETA, BF_LS, BF_COUNT };
+
+}  // namespace
+
+struct pl_batch {
+  int K = 0;
+  int precision = PL_FP64;
+  hipStream_t user_stream = nullptr, stream = nullptr;
+  hipEvent_t ev = nullptr;
+  std::vector<pl_plan*> plans;
+  std::vector<size_t> plan_off;
+  size_t ws_bytes = 0, plans_bytes = 0, blob_bytes = 0;
+  char* ws = nullptr;
+  // work lists
+  std::vector<int4> w_x64, w_y64, w_x32, w_y32, w_row;
+  std::vector<int> nb_x64, nb_y64, nb_x32, nb_y32, nb_row;
+  // device blob and its host mirror
+  char* d_blob = nullptr;
+  char* h_blob = nullptr;
+  size_t off_w[5] = {0, 0, 0, 0, 0};
+  size_t off_c64 = 0, off_ct64 = 0, off_ct32 = 0, off_r64 = 0, off_rt64 = 0, off_rt32 = 0, off_fin = 0,
+         off_e64 = 0, off_e32 = 0, off_ctl = 0, off_scal = 0;
+  double* scal_all = nullptr;
+  double* h_scal = nullptr;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  int graph_chunk[2] = {0, 0}, graph_maxcg[2] = {0, 0};
+  std::string err;
+};
+
+namespace {
+
+int bfail(pl_batch* b, int code, const std::string& m) {
+  if (b) b->err = m;
+  return code;
+}
+
+#define BHIP(b, expr)                                                                              \
+  do {                                                                                             \
+    hipError_t _e = (expr);                                                                        \
+    if (_e != hipSuccess) return bfail(b, PL_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+template <typename T>
+T* blob_ptr(pl_batch* b, size_t off, bool host) {
+  return (T*)((host ? b->h_blob : b->d_blob) + off);
+}
+
+// layout of the blob (work lists, args arrays, finalize arrays, elementwise
+// args, control records, scalars)
+size_t batch_layout(pl_batch* b) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = off;
+    off += align_up(bytes);
+    return r;
+  };
+  const std::vector<int4>* wl[5] = {&b->w_x64, &b->w_y64, &b->w_x32, &b->w_y32, &b->w_row};
+  for (int i = 0; i < 5; ++i) b->off_w[i] = take(sizeof(int4) * std::max<size_t>(1, wl[i]->size()));
+  const size_t K = b->K;
+  b->off_c64 = take(sizeof(ColArgs<double>) * K * BC_COUNT64);
+  b->off_ct64 = take(sizeof(ColArgs<double>) * K * BT_COUNT);
+  b->off_ct32 = take(sizeof(ColArgs<float>) * K * BT_COUNT);
+  b->off_r64 = take(sizeof(RowArgs<double>) * K * BR_COUNT64);
+  b->off_rt64 = take(sizeof(RowArgs<double>) * K * BRT_COUNT);
+  b->off_rt32 = take(sizeof(RowArgs<float>) * K * BRT_COUNT);
+  b->off_fin = take(sizeof(BatchFin) * K * BF_COUNT);
+  b->off_e64 = take(sizeof(BatchElem<double>) * K);
+  b->off_e32 = take(sizeof(BatchElem<float>) * K);
+  b->off_ctl = take(sizeof(BatchCtl) * K);
+  b->off_scal = take(sizeof(double) * K * SC_COUNT);
+  return off;
+}
+
+template <typename T>
+ColArgs<T>* cargs_t(pl_batch* b, int kind, bool host) {
+  return blob_ptr<ColArgs<T>>(b, sizeof(T) == 8 ? b->off_ct64 : b->off_ct32, host) + (size_t)kind * b->K;
+}
+template <typename T>
+RowArgs<T>* rargs_t(pl_batch* b, int kind, bool host) {
+  return blob_ptr<RowArgs<T>>(b, sizeof(T) == 8 ? b->off_rt64 : b->off_rt32, host) + (size_t)kind * b->K;
+}
+ColArgs<double>* cargs64(pl_batch* b, int kind, bool host) {
+  return blob_ptr<ColArgs<double>>(b, b->off_c64, host) + (size_t)kind * b->K;
+}
+RowArgs<double>* rargs64(pl_batch* b, int kind, bool host) {
+  return blob_ptr<RowArgs<double>>(b, b->off_r64, host) + (size_t)kind * b->K;
+}
+BatchFin* fins(pl_batch* b, int kind, bool host) {
+  return blob_ptr<BatchFin>(b, b->off_fin, host) + (size_t)kind * b->K;
+}
+template <typename T>
+BatchElem<T>* elems(pl_batch* b, bool host) {
+  return blob_ptr<BatchElem<T>>(b, sizeof(T) == 8 ? b->off_e64 : b->off_e32, host);
+}
+const int4* work_dev(pl_batch* b, int which) { return blob_ptr<int4>(b, b->off_w[which], false); }
+
+// Fill the per-instance pass arguments (depends on the caller's s pointers).
+template <typename T>
+void fill_args(pl_batch* b, double* const* s_io) {
+  for (int i = 0; i < b->K; ++i) {
+    pl_plan* p = b->plans[i];
+    const double* inactive = p->scal + SC_INACTIVE;
+    const double* done = p->scal + SC_DONE;
+    // FP64 gradient and transforms of s
+    ColArgs<double>* c;
+    c = &cargs64(b, BC_SHAT_Y, true)[i]; *c = col_args<double>(p, 1, p->s_hat, p->s_hat); c->skip = inactive;
+    c = &cargs64(b, BC_SHAT_X, true)[i]; *c = col_args<double>(p, 0, p->s_hat, p->s_hat); c->skip = inactive;
+    c = &cargs64(b, BC_G_XINV, true)[i]; *c = col_args<double>(p, 0, p->s_hat, p->t64); c->skip = inactive;
+    c = &cargs64(b, BC_G_YINV, true)[i]; *c = col_args<double>(p, 1, p->t64, p->t64); c->skip = inactive;
+    c = &cargs64(b, BC_G_YFWD, true)[i]; *c = col_args<double>(p, 1, p->t64, p->t64); c->skip = inactive;
+    c = &cargs64(b, BC_G_XADD, true)[i]; *c = col_args<double>(p, 0, p->t64, p->g_hat); c->skip = inactive;
+    c->base = p->s_hat;
+    c->k0_shift = (double)p->N * p->prob.mu;
+    RowArgs<double>* r;
+    r = &rargs64(b, BR_R2C, true)[i]; *r = row_args<double>(p); r->in_r = s_io[i]; r->out_c = p->s_hat; r->skip = inactive;
+    r = &rargs64(b, BR_GRAD, true)[i]; *r = row_args<double>(p); r->in_c = p->t64; r->out_c = p->t64;
+    r->s_out = s_io[i]; r->e_out = p->e; r->d_out = p->d; r->skip = inactive;
+    // Krylov passes in T
+    cx<T>*x = View<T>::x(p), *rr = View<T>::r(p), *pp = View<T>::pv(p), *t = View<T>::t(p);
+    double* part_a = p->partials;
+    double* part_b = p->partials + p->partials_len;
+    ColArgs<T>* ct;
+    ct = &cargs_t<T>(b, BT_CG1, true)[i]; *ct = col_args<T>(p, 0, pp, t);
+    ct->cg_r = rr; ct->scal = p->scal; ct->partials = part_a; ct->skip = done;
+    ct = &cargs_t<T>(b, BT_CGYI, true)[i]; *ct = col_args<T>(p, 1, t, t); ct->skip = done;
+    ct = &cargs_t<T>(b, BT_CGYF, true)[i]; *ct = col_args<T>(p, 1, t, t); ct->skip = done;
+    ct = &cargs_t<T>(b, BT_CG5, true)[i]; *ct = col_args<T>(p, 0, t, t);
+    ct->base = pp; ct->cg_r = rr; ct->cg_x = x; ct->scal = p->scal; ct->partials = part_a; ct->skip = done;
+    ct = &cargs_t<T>(b, BT_XCINV, true)[i]; *ct = col_args<T>(p, 0, x, t); ct->skip = inactive;
+    ct = &cargs_t<T>(b, BT_YCINV, true)[i]; *ct = col_args<T>(p, 1, t, t); ct->skip = inactive;
+    RowArgs<T>* rt;
+    rt = &rargs_t<T>(b, BRT_HVP, true)[i]; *rt = row_args<T>(p); rt->in_c = t; rt->out_c = t;
+    rt->partials = part_b; rt->skip = done;
+    rt = &rargs_t<T>(b, BRT_C2R, true)[i]; *rt = row_args<T>(p); rt->in_c = t; rt->out_r = View<T>::preal(p);
+    rt->skip = inactive;
+    // finalize records
+    const std::vector<int>& nbx = sizeof(T) == 8 ? b->nb_x64 : b->nb_x32;
+    const double invN = 1.0 / (double)p->N;
+    fins(b, BF_GRAD_ROW, true)[i] = BatchFin{part_a, b->nb_row[i], nullptr, 0, p->scal, invN};
+    fins(b, BF_GRAD_X, true)[i] = BatchFin{part_a, b->nb_x64[i], nullptr, 0, p->scal, invN};
+    fins(b, BF_INIT, true)[i] = BatchFin{part_a, NBB, nullptr, 0, p->scal, invN};
+    fins(b, BF_ALPHA, true)[i] = BatchFin{part_b, b->nb_row[i], part_a, nbx[i], p->scal, invN};
+    fins(b, BF_BETA, true)[i] = BatchFin{part_a, nbx[i], nullptr, 0, p->scal, invN};
+    fins(b, BF_LS, true)[i] = BatchFin{part_a, NBB, nullptr, 0, p->scal, invN};
+  }
+}
+
+int bfin(pl_batch* b, int which, int K, int kind, int dst, double scale, int scale_invN, double aux = 0.0,
+         double scale2 = 0.0, int scale2_invN = 0) {
+  hipLaunchKernelGGL(finalize_batch_kernel, dim3(b->K), dim3(256), 0, b->stream, fins(b, which, false), K, kind,
+                     dst, scale, scale_invN, aux, scale2, scale2_invN);
+  BHIP(b, hipGetLastError());
+  return PL_OK;
+}
+
+int bread(pl_batch* b) {
+  BHIP(b, hipMemcpyAsync(b->h_scal, b->scal_all, sizeof(double) * SC_COUNT * b->K, hipMemcpyDeviceToHost,
+                         b->stream));
+  BHIP(b, hipStreamSynchronize(b->stream));
+  return PL_OK;
+}
+
+double& hs(pl_batch* b, int i, int slot) { return b->h_scal[(size_t)i * SC_COUNT + slot]; }
+
+// Upload the control records and apply them.
+int bctl(pl_batch* b) {
+  BatchCtl* hc = blob_ptr<BatchCtl>(b, b->off_ctl, true);
+  BHIP(b, hipMemcpyAsync(blob_ptr<BatchCtl>(b, b->off_ctl, false), hc, sizeof(BatchCtl) * b->K,
+                         hipMemcpyHostToDevice, b->stream));
+  hipLaunchKernelGGL(batch_ctl_kernel, dim3((b->K + 63) / 64), dim3(64), 0, b->stream,
+                     blob_ptr<BatchCtl>(b, b->off_ctl, false), b->K);
+  BHIP(b, hipGetLastError());
+  BHIP(b, hipStreamSynchronize(b->stream));  // staging may be rewritten next
+  return PL_OK;
+}
+
+template <typename T>
+int belem_upload(pl_batch* b) {
+  BHIP(b, hipMemcpyAsync(elems<T>(b, false), elems<T>(b, true), sizeof(BatchElem<T>) * b->K,
+                         hipMemcpyHostToDevice, b->stream));
+  return PL_OK;
+}
+
+int bgrad(pl_batch* b) {
+  const int nx = (int)b->w_x64.size(), ny = (int)b->w_y64.size(), nr = (int)b->w_row.size();
+  BHIP(b, launch_col_batch<double>(true, COL_PLAIN, cargs64(b, BC_G_XINV, false), work_dev(b, 0), nx, b->stream));
+  BHIP(b, launch_col_batch<double>(true, COL_PLAIN, cargs64(b, BC_G_YINV, false), work_dev(b, 1), ny, b->stream));
+  BHIP(b, launch_row_batch<double>(ROW_GRAD, rargs64(b, BR_GRAD, false), work_dev(b, 4), nr, b->stream));
+  int rc = bfin(b, BF_GRAD_ROW, 2, FIN_STORE, SC_LIK, 1.0, 0);
+  if (rc) return rc;
+  BHIP(b, launch_col_batch<double>(false, COL_PLAIN, cargs64(b, BC_G_YFWD, false), work_dev(b, 1), ny, b->stream));
+  BHIP(b, launch_col_batch<double>(false, COL_ADDPRIOR, cargs64(b, BC_G_XADD, false), work_dev(b, 0), nx, b->stream));
+  return bfin(b, BF_GRAD_X, 3, FIN_STORE, SC_GG - 1, 0.0, 1);
+}
+
+// Enqueue `chunk` fused CG steps for all instances (captured in a graph)
+template <typename T>
+int bcg_chunk(pl_batch* b, int chunk, int max_cg) {
+  const int wx = sizeof(T) == 8 ? 0 : 2, wy = sizeof(T) == 8 ? 1 : 3;
+  const int nx = (int)(sizeof(T) == 8 ? b->w_x64.size() : b->w_x32.size());
+  const int ny = (int)(sizeof(T) == 8 ? b->w_y64.size() : b->w_y32.size());
+  const int nr = (int)b->w_row.size();
+  for (int k = 0; k < chunk; ++k) {
+    BHIP(b, launch_col_batch<T>(true, COL_CG_FIRST, cargs_t<T>(b, BT_CG1, false), work_dev(b, wx), nx, b->stream));
+    BHIP(b, launch_col_batch<T>(true, COL_PLAIN, cargs_t<T>(b, BT_CGYI, false), work_dev(b, wy), ny, b->stream));
+    BHIP(b, launch_row_batch<T>(ROW_HVP, rargs_t<T>(b, BRT_HVP, false), work_dev(b, 4), nr, b->stream));
+    int rc = bfin(b, BF_ALPHA, 2, FIN_CG_ALPHA, 0, 1.0, 0, 0.0, 0.0, 1);
+    if (rc) return rc;
+    BHIP(b, launch_col_batch<T>(false, COL_PLAIN, cargs_t<T>(b, BT_CGYF, false), work_dev(b, wy), ny, b->stream));
+    BHIP(b, launch_col_batch<T>(false, COL_CG_LAST, cargs_t<T>(b, BT_CG5, false), work_dev(b, wx), nx, b->stream));
+    rc = bfin(b, BF_BETA, 2, FIN_CG_BETA, 0, 0.0, 1, (double)max_cg);
+    if (rc) return rc;
+  }
+  return PL_OK;
+}
+
+template <typename T>
+int batch_newton(pl_batch* b, double* const* s_io, const pl_solve_opts& o, pl_solve_info* infos) {
+  const int K = b->K;
+  const int ti = sizeof(T) == 8 ? 0 : 1;
+  fill_args<T>(b, s_io);
+  BHIP(b, hipMemcpyAsync(b->d_blob, b->h_blob, b->off_e64, hipMemcpyHostToDevice, b->stream));
+  BatchCtl* ctl = blob_ptr<BatchCtl>(b, b->off_ctl, true);
+  BatchElem<T>* E = elems<T>(b, true);
+  std::vector<pl_solve_info> inf(K);
+  std::vector<int> active(K, 1);
+  std::vector<double> g0(K, 0.0), gn(K, 0.0);
+  for (int i = 0; i < K; ++i) {
+    ctl[i] = BatchCtl{b->plans[i]->scal, 0, 0, 0.0, 0.0, 0, 0, 1, 1};
+  }
+  int rc = bctl(b);
+  if (rc) return rc;
+  // s_hat = F s0, then the gradient
+  BHIP(b, launch_row_batch<double>(ROW_R2C, rargs64(b, BR_R2C, false), work_dev(b, 4), (int)b->w_row.size(),
+                                   b->stream));
+  BHIP(b, launch_col_batch<double>(false, COL_PLAIN, cargs64(b, BC_SHAT_Y, false), work_dev(b, 1),
+                                   (int)b->w_y64.size(), b->stream));
+  BHIP(b, launch_col_batch<double>(false, COL_PLAIN, cargs64(b, BC_SHAT_X, false), work_dev(b, 0),
+                                   (int)b->w_x64.size(), b->stream));
+  rc = bgrad(b);
+  if (rc) return rc;
+  rc = bread(b);
+  if (rc) return rc;
+  for (int i = 0; i < K; ++i) {
+    g0[i] = gn[i] = std::sqrt(std::max(0.0, hs(b, i, SC_GG)));
+    inf[i].grad0 = g0[i];
+    inf[i].obj = 0.5 * hs(b, i, SC_PRIOR) + hs(b, i, SC_LIK);
+    if (!std::isfinite(g0[i])) {
+      inf[i].status = PL_ERR_DOMAIN;
+      active[i] = 0;
+    } else if (g0[i] == 0.0) {
+      active[i] = 0;
+    }
+  }
+  // graph of one chunk of CG steps (built on first use, replayed afterwards)
+  if (!b->graph[ti] || b->graph_chunk[ti] != o.check_every || b->graph_maxcg[ti] != o.max_cg) {
+    if (b->graph[ti]) {
+      (void)hipGraphExecDestroy(b->graph[ti]);
+      b->graph[ti] = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    int crc = bcg_chunk<T>(b, o.check_every, o.max_cg);
+    hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (crc) return crc;
+    BHIP(b, e);
+    BHIP(b, hipGraphInstantiate(&b->graph[ti], g, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(g);
+    b->graph_chunk[ti] = o.check_every;
+    b->graph_maxcg[ti] = o.max_cg;
+  }
+  for (int it = 0;; ++it) {
+    // retire converged / capped instances
+    int n_active = 0;
+    for (int i = 0; i < K; ++i) {
+      ctl[i] = BatchCtl{b->plans[i]->scal, 0, 0, 0.0, 0.0, 0, 0, 0, 0};
+      if (!active[i]) {
+        ctl[i].inactive = 1.0; ctl[i].done = 1.0; ctl[i].set_inactive = 1; ctl[i].set_done = 1;
+        continue;
+      }
+      if (gn[i] <= o.rtol * g0[i]) {
+        active[i] = 0;
+      } else if (it >= o.max_newton) {
+        active[i] = 0;
+        inf[i].status = PL_ERR_NOT_CONVERGED;
+      }
+      if (!active[i]) {
+        ctl[i].inactive = 1.0; ctl[i].done = 1.0; ctl[i].set_inactive = 1; ctl[i].set_done = 1;
+        continue;
+      }
+      ++n_active;
+      const double eta = std::min(o.eta_max, std::max(std::sqrt(gn[i] / g0[i]), 0.5 * o.rtol * g0[i] / gn[i]));
+      ctl[i].tol2 = eta * gn[i] * eta * gn[i];
+      ctl[i].dbar = hs(b, i, SC_DSUM) / (double)b->plans[i]->N;
+      ctl[i].set_tol2 = ctl[i].set_dbar = 1;
+    }
+    rc = bctl(b);
+    if (rc) return rc;
+    if (n_active == 0) break;
+    // elementwise operands for this Newton step
+    for (int i = 0; i < K; ++i) {
+      pl_plan* p = b->plans[i];
+      BatchElem<T> e{};
+      e.active = active[i];
+      e.nh = p->Nh;
+      e.n = p->N;
+      e.g = p->g;
+      e.radial = p->radial;
+      e.tab = View<T>::tab(p);
+      e.tab64 = p->radial ? p->tab_rad : p->tab_mode;
+      e.rhs = p->g_hat;
+      e.sign = -1.0;
+      e.x = View<T>::x(p);
+      e.r = View<T>::r(p);
+      e.p = View<T>::pv(p);
+      e.s_hat = p->s_hat;
+      e.g_hat = p->g_hat;
+      e.k0_shift = (double)p->N * p->prob.mu;
+      e.preal = View<T>::preal(p);
+      e.e = p->e;
+      e.counts = p->prob.counts;
+      e.beta = p->prob.beta;
+      e.a0 = 1.0;
+      e.y = p->s_hat;
+      e.alpha = 0.0;
+      e.d = p->d;
+      e.d32 = p->d32;
+      e.scal = p->scal;
+      e.partials = p->partials;
+      E[i] = e;
+    }
+    rc = belem_upload<T>(b);
+    if (rc) return rc;
+    if constexpr (sizeof(T) == 4) {
+      hipLaunchKernelGGL((d32_batch_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream, elems<T>(b, false));
+      BHIP(b, hipGetLastError());
+    }
+    hipLaunchKernelGGL((cg_init_batch_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream, elems<T>(b, false));
+    BHIP(b, hipGetLastError());
+    rc = bfin(b, BF_INIT, 2, FIN_CG_INIT, 0, 0.0, 1);
+    if (rc) return rc;
+    for (int launched = 0; launched < o.max_cg; launched += o.check_every) {
+      BHIP(b, hipGraphLaunch(b->graph[ti], b->stream));
+      rc = bread(b);
+      if (rc) return rc;
+      bool all = true;
+      for (int i = 0; i < K; ++i)
+        if (active[i] && hs(b, i, SC_DONE) == 0.0) all = false;
+      if (all) break;
+    }
+    for (int i = 0; i < K; ++i)
+      if (active[i]) {
+        const int its = (int)hs(b, i, SC_ITS);
+        inf[i].cg_its += its;
+        inf[i].hvps += its + (hs(b, i, SC_DONE) == 2.0 ? 1 : 0);
+      }
+    // line search: real-space direction, spectral dots
+    const int wx = sizeof(T) == 8 ? 0 : 2, wy = sizeof(T) == 8 ? 1 : 3;
+    BHIP(b, launch_col_batch<T>(true, COL_PLAIN, cargs_t<T>(b, BT_XCINV, false), work_dev(b, wx),
+                                (int)(sizeof(T) == 8 ? b->w_x64.size() : b->w_x32.size()), b->stream));
+    BHIP(b, launch_col_batch<T>(true, COL_PLAIN, cargs_t<T>(b, BT_YCINV, false), work_dev(b, wy),
+                                (int)(sizeof(T) == 8 ? b->w_y64.size() : b->w_y32.size()), b->stream));
+    BHIP(b, launch_row_batch<T>(ROW_C2R, rargs_t<T>(b, BRT_C2R, false), work_dev(b, 4), (int)b->w_row.size(),
+                                b->stream));
+    hipLaunchKernelGGL((ls_dots_batch_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream, elems<T>(b, false));
+    BHIP(b, hipGetLastError());
+    rc = bfin(b, BF_LS, 3, FIN_STORE, SC_LS_B, 0.0, 1);
+    if (rc) return rc;
+    rc = bread(b);
+    if (rc) return rc;
+    std::vector<double> alpha(K, -1.0), a0(K, 1.0);
+    std::vector<int> pending(K, 0);
+    for (int i = 0; i < K; ++i)
+      if (active[i]) pending[i] = hs(b, i, SC_LS_SLOPE) < 0.0 ? 1 : 0;
+    for (int batch = 0; batch < 8; ++batch) {
+      bool any = false;
+      for (int i = 0; i < K; ++i) {
+        E[i].active = pending[i];
+        E[i].a0 = a0[i];
+        any = any || pending[i];
+      }
+      if (!any) break;
+      rc = belem_upload<T>(b);
+      if (rc) return rc;
+      hipLaunchKernelGGL((ls_eval_batch_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream,
+                         elems<T>(b, false));
+      BHIP(b, hipGetLastError());
+      rc = bfin(b, BF_LS, 4, FIN_STORE, SC_DF, 1.0, 0);
+      if (rc) return rc;
+      rc = bread(b);
+      if (rc) return rc;
+      for (int i = 0; i < K; ++i) {
+        if (!pending[i]) continue;
+        const double bb = hs(b, i, SC_LS_B), cc = hs(b, i, SC_LS_C), slope = hs(b, i, SC_LS_SLOPE);
+        double a = a0[i];
+        for (int j = 0; j < 4; ++j, a *= 0.5) {
+          const double df = a * bb + 0.5 * a * a * cc + hs(b, i, SC_DF + j);
+          if (df <= o.ls_c1 * a * slope) {
+            alpha[i] = a;
+            pending[i] = 0;
+            break;
+          }
+        }
+        a0[i] *= 1.0 / 16.0;
+      }
+    }
+    for (int i = 0; i < K; ++i) {
+      E[i].active = active[i] && alpha[i] > 0.0;
+      E[i].alpha = alpha[i];
+      if (active[i] && alpha[i] <= 0.0) {
+        active[i] = 0;
+        inf[i].status = PL_ERR_LINESEARCH;
+      }
+    }
+    rc = belem_upload<T>(b);
+    if (rc) return rc;
+    hipLaunchKernelGGL((axpy_batch_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream, elems<T>(b, false));
+    BHIP(b, hipGetLastError());
+    // retire line-search failures before the gradient (their s stays put)
+    for (int i = 0; i < K; ++i) {
+      ctl[i] = BatchCtl{b->plans[i]->scal, 0, 0, active[i] ? 0.0 : 1.0, 1.0, 0, 0, 1, 0};
+    }
+    rc = bctl(b);
+    if (rc) return rc;
+    rc = bgrad(b);
+    if (rc) return rc;
+    rc = bread(b);
+    if (rc) return rc;
+    for (int i = 0; i < K; ++i) {
+      if (!active[i]) continue;
+      gn[i] = std::sqrt(std::max(0.0, hs(b, i, SC_GG)));
+      inf[i].obj = 0.5 * hs(b, i, SC_PRIOR) + hs(b, i, SC_LIK);
+      inf[i].newton_its = it + 1;
+      if (!std::isfinite(gn[i])) {
+        active[i] = 0;
+        inf[i].status = PL_ERR_DOMAIN;
+      }
+    }
+  }
+  if constexpr (sizeof(T) == 4) {
+    // instances whose FP32 directions stalled in the line search continue
+    // from their current iterate with FP64 inner solves
+    for (int i = 0; i < K; ++i) {
+      if (inf[i].status != PL_ERR_LINESEARCH) continue;
+      BHIP(b, hipStreamSynchronize(b->stream));
+      pl_solve_info r{};
+      pl_solve_opts o2 = o;
+      o2.max_newton = std::max(0, o.max_newton - inf[i].newton_its);
+      // same stopping point: rtol relative to the original starting gradient
+      o2.rtol = gn[i] > 0.0 ? o.rtol * g0[i] / gn[i] : o.rtol;
+      const int rc2 = newton_solve<double>(b->plans[i], s_io[i], o2, &r);
+      if (rc2 != PL_OK && rc2 != PL_ERR_NOT_CONVERGED && rc2 != PL_ERR_LINESEARCH) return bfail(b, rc2, pl_last_error(b->plans[i]));
+      const double gfin = r.rel_grad * r.grad0;
+      gn[i] = gfin;
+      inf[i].cg_its += r.cg_its;
+      inf[i].hvps += r.hvps;
+      inf[i].newton_its += r.newton_its;
+      inf[i].obj = r.obj;
+      inf[i].status = gfin <= o.rtol * g0[i] ? PL_OK : (rc2 != PL_OK ? rc2 : PL_ERR_NOT_CONVERGED);
+    }
+  }
+  int first_bad = PL_OK;
+  for (int i = 0; i < K; ++i) {
+    inf[i].rel_grad = g0[i] > 0.0 ? gn[i] / g0[i] : 0.0;
+    if (infos) infos[i] = inf[i];
+    if (inf[i].status != PL_OK && first_bad == PL_OK) first_bad = inf[i].status;
+  }
+  BHIP(b, hipStreamSynchronize(b->stream));
+  return first_bad;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pl_batch_create(pl_batch** out, int n_inst, const int32_t* n, const double* box, int precision,
+                    void* hip_stream, size_t* workspace_bytes) {
+  if (!out || n_inst <= 0 || !n || !box || !workspace_bytes) return PL_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (precision != PL_FP64 && precision != PL_MIXED) return PL_ERR_INVALID_ARG;
+  for (int i = 0; i < 3 * n_inst; ++i)
+    if (!batch_length_supported(n[i])) return PL_ERR_UNSUPPORTED_SIZE;
+  pl_batch* b = new pl_batch();
+  b->K = n_inst;
+  b->precision = precision;
+  b->user_stream = (hipStream_t)hip_stream;
+  if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev, hipEventDisableTiming) != hipSuccess) {
+    delete b;
+    return PL_ERR_HIP;
+  }
+  size_t off = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    pl_plan* p = nullptr;
+    size_t ws = 0;
+    int rc = pl_plan_create(&p, n + 3 * i, box + 3 * i, precision, (void*)b->stream, &ws);
+    if (rc) {
+      pl_batch_destroy(b);
+      return rc;
+    }
+    b->plans.push_back(p);
+    b->plan_off.push_back(off);
+    off += align_up(ws);
+  }
+  b->plans_bytes = off;
+  b->w_x64 = col_work<double>(b->plans, 0, b->nb_x64);
+  b->w_y64 = col_work<double>(b->plans, 1, b->nb_y64);
+  b->w_x32 = col_work<float>(b->plans, 0, b->nb_x32);
+  b->w_y32 = col_work<float>(b->plans, 1, b->nb_y32);
+  b->w_row = row_work(b->plans, b->nb_row);
+  b->blob_bytes = batch_layout(b);
+  b->ws_bytes = b->plans_bytes + b->blob_bytes;
+  if (hipHostMalloc((void**)&b->h_blob, b->blob_bytes, hipHostMallocDefault) != hipSuccess) {
+    pl_batch_destroy(b);
+    return PL_ERR_HIP;
+  }
+  std::memset(b->h_blob, 0, b->blob_bytes);
+  {
+    // the host blob mirrors the device blob, work lists included
+    const std::vector<int4>* wl[5] = {&b->w_x64, &b->w_y64, &b->w_x32, &b->w_y32, &b->w_row};
+    for (int i = 0; i < 5; ++i)
+      if (!wl[i]->empty()) std::memcpy(b->h_blob + b->off_w[i], wl[i]->data(), sizeof(int4) * wl[i]->size());
+  }
+  b->h_scal = blob_ptr<double>(b, b->off_scal, true);
+  *workspace_bytes = b->ws_bytes;
+  *out = b;
+  return PL_OK;
+}
+
+int pl_batch_set_workspace(pl_batch* b, void* dev_ptr) {
+  if (!b) return PL_ERR_INVALID_ARG;
+  if (!dev_ptr || ((uintptr_t)dev_ptr & 255)) return bfail(b, PL_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  b->ws = (char*)dev_ptr;
+  for (int i = 0; i < b->K; ++i) {
+    int rc = pl_plan_set_workspace(b->plans[i], b->ws + b->plan_off[i]);
+    if (rc) return bfail(b, rc, std::string("instance workspace: ") + pl_last_error(b->plans[i]));
+  }
+  b->d_blob = b->ws + b->plans_bytes;
+  b->scal_all = blob_ptr<double>(b, b->off_scal, false);
+  // every instance keeps its device scalars in one contiguous array
+  for (int i = 0; i < b->K; ++i) b->plans[i]->scal = b->scal_all + (size_t)i * SC_COUNT;
+  BHIP(b, hipMemsetAsync(b->scal_all, 0, sizeof(double) * SC_COUNT * b->K, b->stream));
+  BHIP(b, hipMemcpyAsync(b->d_blob, b->h_blob, b->off_e64, hipMemcpyHostToDevice, b->stream));
+  BHIP(b, hipStreamSynchronize(b->stream));
+  for (int t = 0; t < 2; ++t)
+    if (b->graph[t]) {
+      (void)hipGraphExecDestroy(b->graph[t]);
+      b->graph[t] = nullptr;
+    }
+  return PL_OK;
+}
+
+int pl_batch_set_problem(pl_batch* b, int i, const pl_problem* prob) {
+  if (!b || i < 0 || i >= b->K) return PL_ERR_INVALID_ARG;
+  if (!b->ws) return bfail(b, PL_ERR_INVALID_ARG, "workspace not set");
+  int rc = pl_set_problem(b->plans[i], prob);
+  if (rc) return bfail(b, rc, "instance " + std::to_string(i) + ": " + pl_last_error(b->plans[i]));
+  return PL_OK;
+}
+
+int pl_batch_solve(pl_batch* b, double* const* s_inout, const pl_solve_opts* opts, pl_solve_info* infos) {
+  if (!b || !s_inout) return PL_ERR_INVALID_ARG;
+  if (!b->ws) return bfail(b, PL_ERR_INVALID_ARG, "workspace not set");
+  for (int i = 0; i < b->K; ++i) {
+    if (!b->plans[i]->has_problem) return bfail(b, PL_ERR_NO_PROBLEM, "instance " + std::to_string(i) + " has no problem");
+    if (!s_inout[i]) return bfail(b, PL_ERR_INVALID_ARG, "null s_inout entry");
+  }
+  pl_solve_opts o = resolve_opts(b->plans[0], opts);
+  if (opts && opts->precision < 0) o.precision = b->precision;
+  if (!(o.rtol >= 0.0) || o.max_newton < 0 || o.max_cg <= 0 || !(o.eta_max > 0.0) || !(o.ls_c1 > 0.0 && o.ls_c1 < 1.0))
+    return bfail(b, PL_ERR_INVALID_ARG, "invalid solve options");
+  // order after the caller's pending work
+  BHIP(b, hipEventRecord(b->ev, b->user_stream));
+  BHIP(b, hipStreamWaitEvent(b->stream, b->ev, 0));
+  int rc;
+  if (o.precision == PL_MIXED) {
+    if (b->precision != PL_MIXED) return bfail(b, PL_ERR_INVALID_ARG, "mixed solve needs a PL_MIXED batch");
+    rc = batch_newton<float>(b, s_inout, o, infos);
+  } else {
+    rc = batch_newton<double>(b, s_inout, o, infos);
+  }
+  (void)hipStreamSynchronize(b->stream);
+  if (rc && b->err.empty()) b->err = "an instance did not converge (see infos)";
+  return rc;
+}
+
+int pl_batch_destroy(pl_batch* b) {
+  if (!b) return PL_ERR_INVALID_ARG;
+  for (int t = 0; t < 2; ++t)
+    if (b->graph[t]) (void)hipGraphExecDestroy(b->graph[t]);
+  for (pl_plan* p : b->plans) pl_plan_destroy(p);
+  if (b->h_blob) (void)hipHostFree(b->h_blob);
+  if (b->ev) (void)hipEventDestroy(b->ev);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+  return PL_OK;
+}
+
+const char* pl_batch_last_error(const pl_batch* b) {
+  if (!b) return "null batch";
+  return b->err.c_str();
+}
+
+}  // extern "C"
