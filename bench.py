@@ -16,6 +16,9 @@ Also reported (not part of `value`):
                    with HIP events on the plan's stream, against 8 TB/s
   mixed         -- the same solve with FP32 FFTs/HVPs and FP64 reductions
   adjoint       -- adjoint solve of L = sum (s* - s_true)^2 at the MAP
+  batched       -- 64 independent reconstructions, n in {32, 48, 64, 96},
+                   solved together (mixed precision) vs one after another
+                   (plain FP64)
   cpu_baseline  -- the CPU oracle's spectral HVP on the host cores
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
@@ -53,6 +56,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--hvp-reps", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--only-hvp", action="store_true", help="profiling aid: only the isolated HVP loop")
     ap.add_argument("--n", type=int, default=256, help="grid (default: the 256^3 workload)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -176,6 +180,42 @@ def main():
     print(f"# adjoint fp64 {1e3 * t_adj:.1f} ms {ainfo}; mixed {1e3 * t_adj32:.1f} ms",
           file=sys.stderr, flush=True)
 
+    # ---------------- batched workload ----------------
+    batch = None
+    if not args.no_batch:
+        from paper_0911_1407_amd.binding import Batch
+        t0 = time.time()
+        insts = synth.batch_instances(count=64)
+        print(f"# generated 64 batch instances in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+        bt = Batch(insts, precision="mixed", device=dev)
+        bt.solve(rtol=rtol)  # warm-up (also builds the CG graph)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, binfos = bt.solve(rtol=rtol)
+        torch.cuda.synchronize()
+        t_batch = time.perf_counter() - t0
+        nconv = sum(1 for i in binfos if i["status"] == 0)
+        # sequential plain FP64 single-grid solves of the same instances
+        t_seq = 0.0
+        for it in insts:
+            pp = Plan(it["n"], it["box"], precision="fp64", device=dev)
+            pp.set_instance(it)
+            s0 = torch.full(it["n"], float(it["mu"]), dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            from paper_0911_1407_amd.binding import make_opts, pl_newton_krylov_solve
+            pl_newton_krylov_solve(pp.h, s0, make_opts(rtol=rtol))
+            torch.cuda.synchronize()
+            t_seq += time.perf_counter() - t0
+            pp.close()
+        batch = {"instances": len(insts), "converged": nconv, "ms_batched_mixed": 1e3 * t_batch,
+                 "instances_per_s_batched": len(insts) / t_batch,
+                 "ms_sequential_fp64": 1e3 * t_seq, "instances_per_s_sequential_fp64": len(insts) / t_seq,
+                 "speedup": t_seq / t_batch,
+                 "cg_its_total": sum(i["cg_its"] for i in binfos)}
+        print(f"# batch: {1e3 * t_batch:.0f} ms batched mixed vs {1e3 * t_seq:.0f} ms sequential fp64 "
+              f"({nconv}/64 converged)", file=sys.stderr, flush=True)
+
     # ---------------- CPU oracle baseline ----------------
     cpu = None
     if not args.no_cpu:
@@ -236,6 +276,7 @@ def main():
         "adjoint": {"ms_fp64": 1e3 * t_adj, "ms_mixed": 1e3 * t_adj32, "cg_its_fp64": ainfo["cg_its"],
                     "cg_its_mixed": ainfo32["cg_its"], "dL_dA": grads["A"], "dL_dbeta": grads["beta"],
                     "dL_dnbar": grads["nbar"]},
+        "batched": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(result))

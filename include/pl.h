@@ -170,6 +170,21 @@ int pl_solve_adjoint(pl_plan* plan, const double* s_star, const double* dL_ds, d
 /* Message for the last failing call on plan (never NULL). */
 const char* pl_last_error(const pl_plan* plan);
 
+/* FFT schedule autotuner.  Each column (x, y) and row (z) pass has two tile
+   variants (default: 256 threads, <= 64 KB LDS; wide: 512 threads, <= 128 KB
+   LDS, longer contiguous row segments) for lengths 128, 192, 256 and 512.
+   Times one spectral Hessian-vector product per combination on the plan's
+   workspace (after pl_set_problem; it overwrites the cached Hessian
+   diagonal) and keeps the fastest, per precision.  cache_path (nullable): a
+   text file of earlier results keyed by arch, grid and precision; entries
+   found there are used without timing, new ones are appended. */
+int pl_plan_autotune(pl_plan* plan, const char* cache_path);
+/* Current variants: out = {x, y, z} for FP64 then {x, y, z} for FP32
+   (0 default, 1 wide; a length without a wide variant runs the default). */
+int pl_plan_get_variants(const pl_plan* plan, int32_t out[6]);
+/* Force the variants (same order); each entry 0 or 1. */
+int pl_plan_set_variants(pl_plan* plan, const int32_t v[6]);
+
 /* ---------------------------------------------------------------------------
  * Batched MAP solves: many independent reconstructions (each its own grid,
  * box and posterior) solved together.  Every pass of every Newton / CG step

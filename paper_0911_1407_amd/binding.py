@@ -32,7 +32,8 @@ EXPORTED = ("pl_default_opts", "pl_plan_create", "pl_plan_set_workspace", "pl_pl
             "pl_plan_destroy", "pl_set_problem", "pl_grad", "pl_hessvec", "pl_hessvec_f32",
             "pl_hessvec_hat", "pl_hessvec_hat_f32", "pl_newton_krylov_solve", "pl_solve_adjoint",
             "pl_last_error", "pl_batch_create", "pl_batch_set_workspace", "pl_batch_set_problem",
-            "pl_batch_solve", "pl_batch_destroy", "pl_batch_last_error")
+            "pl_batch_solve", "pl_batch_destroy", "pl_batch_last_error", "pl_plan_autotune",
+            "pl_plan_get_variants", "pl_plan_set_variants")
 
 BATCH_LENGTHS = (32, 48, 64, 96, 128)
 
@@ -103,6 +104,9 @@ def load(path=LIB_PATH):
     lib.pl_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(pl_solve_opts),
                                    ctypes.POINTER(pl_solve_info)]
     lib.pl_batch_destroy.argtypes = [vp]
+    lib.pl_plan_autotune.argtypes = [vp, ctypes.c_char_p]
+    lib.pl_plan_get_variants.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.pl_plan_set_variants.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     lib.pl_batch_last_error.argtypes = [vp]
     lib.pl_batch_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -206,6 +210,21 @@ def pl_solve_adjoint(h, s_star, dL_ds, lambda_out=None, dL_dN=None, dL_dw=None, 
 
 def pl_last_error(h):
     return load().pl_last_error(h).decode()
+
+
+def pl_plan_autotune(h, cache_path=None):
+    return _check(h, load().pl_plan_autotune(h, cache_path.encode() if cache_path else None))
+
+
+def pl_plan_get_variants(h):
+    out = (ctypes.c_int32 * 6)()
+    _check(h, load().pl_plan_get_variants(h, out))
+    return {"fp64": tuple(out[0:3]), "fp32": tuple(out[3:6])}
+
+
+def pl_plan_set_variants(h, fp64=(0, 0, 0), fp32=(0, 0, 0)):
+    v = (ctypes.c_int32 * 6)(*[int(x) for x in tuple(fp64) + tuple(fp32)])
+    return _check(h, load().pl_plan_set_variants(h, v))
 
 
 def pl_batch_create(ns, boxes, precision=PL_FP64, stream=None):
@@ -351,6 +370,11 @@ class Plan:
         dw = self.torch.empty_like(s_star) if want_fields else None
         scal, info = pl_solve_adjoint(self.h, s_star, dL_ds, lam, dN, dw, make_opts(**kw))
         return dict(scal, N=dN, w=dw, lam=lam), info.as_dict()
+
+    def autotune(self, cache_path=None):
+        """Pick the fastest tile variants for this grid (needs set_problem)."""
+        pl_plan_autotune(self.h, cache_path)
+        return pl_plan_get_variants(self.h)
 
     def close(self):
         if self.h:

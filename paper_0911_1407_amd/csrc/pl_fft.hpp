@@ -231,11 +231,29 @@ __device__ __forceinline__ void stage_compute(cx<T>* v, int t, const cx<T>* __re
     cx<T>* b = v + q * R;
     if constexpr (Ns > 1) {
       int k = (t + PL::P * q) % Ns;
+      // powers w^r, r = 1..R-1, of w = exp(-2 pi i k / (Ns R)): w^1, w^2,
+      // w^4, w^8 from the table, the rest as products of at most three of
+      // them (a few ulp, instead of one table load per power)
+      cx<T> w[R];
+      w[1] = tw[k * STEP];
+      if constexpr (R > 2) w[2] = tw[2 * k * STEP];
+      if constexpr (R == 3) {
+      } else {
+        if constexpr (R > 3) w[3] = cmul(w[1], w[2]);
+        if constexpr (R > 4) {
+          w[4] = tw[4 * k * STEP];
+          w[5] = cmul(w[4], w[1]);
+          w[6] = cmul(w[4], w[2]);
+          w[7] = cmul(w[4], w[3]);
+        }
+        if constexpr (R > 8) {
+          w[8] = tw[8 * k * STEP];
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        cx<T> w = tw[r * k * STEP];
-        b[r] = INV ? cmulc(b[r], w) : cmul(b[r], w);
+          for (int r = 9; r < R; ++r) w[r] = cmul(w[8], w[r - 8]);
+        }
       }
+#pragma unroll
+      for (int r = 1; r < R; ++r) b[r] = INV ? cmulc(b[r], w[r]) : cmul(b[r], w[r]);
     }
     dft_r<R, INV>(b);
   }

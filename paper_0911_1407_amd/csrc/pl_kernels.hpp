@@ -144,37 +144,44 @@ struct ColArgs {
 
 // Column tile width B: 256 threads per block where possible, at most 64 KB
 // of LDS for the stage exchanges, at least 8 columns (128-byte segments).
-constexpr int col_tile(int P, int N, int elem_bytes) {
-  int b = 256 / P;
+// Tile variants: V = 0 aims at 256 threads and at most 64 KB of LDS; V = 1
+// ("wide") at 512 threads and at most 128 KB, i.e. longer contiguous row
+// segments per tile at lower occupancy.  Which wins depends on the length
+// and precision; the plan picks one per pass (see pl_plan_autotune).
+constexpr int col_tile(int P, int N, int elem_bytes, int threads, int lds_cap) {
+  int b = threads / P;
   if (b > 64) b = 64;
   if (b < 8) b = 8;
-  while (b > 8 && P > 1 && b * N * elem_bytes > 65536) b /= 2;
+  while (b > 8 && P > 1 && b * N * elem_bytes > lds_cap) b /= 2;
   return b;
 }
 
-template <typename T, int N>
+template <typename T, int N, int V = 0>
 struct ColShape {
   static constexpr int P = Plan<N>::P;
-  static constexpr int B = col_tile(P, N, (int)sizeof(cx<T>));
+  static constexpr int B = col_tile(P, N, (int)sizeof(cx<T>), V ? 512 : 256, V ? 131072 : 65536);
   static constexpr int THREADS = B * P;
   static constexpr int LDS = P > 1 ? N * B : 1;  // complex elements
 };
 
+// lengths with a wide variant
+constexpr bool has_wide_variant(int n) { return n == 128 || n == 192 || n == 256 || n == 512; }
+
 // One workgroup's share of a column pass: tile `tile` of slab `slab`.
 // Threads beyond ColShape::THREADS (when a batched launch uses a larger
 // block) only take part in the barriers.
-template <typename T, int N, bool INV, int OP>
+template <typename T, int N, bool INV, int OP, int V = 0>
 __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab, cx<T>* lds_all,
                                          int block_linear) {
   using PL = Plan<N>;
-  constexpr int B = ColShape<T, N>::B;
+  constexpr int B = ColShape<T, N, V>::B;
   constexpr int P = PL::P;
   constexpr int W = PL::W;
   constexpr int R0 = PL::R0;
   constexpr int RL = LastStage<PL>::R;
   using MAP = LdsMap<B, false>;
 
-  const bool active = (int)threadIdx.x < ColShape<T, N>::THREADS;
+  const bool active = (int)threadIdx.x < ColShape<T, N, V>::THREADS;
   const int cl = threadIdx.x % B;
   const int t = active ? (int)threadIdx.x / B : 0;
   const int c = tile * B + cl;
@@ -319,16 +326,18 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
 }
 
 
-template <typename T, int N, bool INV, int OP>
-__global__ void __launch_bounds__((ColShape<T, N>::THREADS)) col_kernel(ColArgs<T> a) {
-  __shared__ cx<T> lds_all[ColShape<T, N>::LDS];
+template <typename T, int N, bool INV, int OP, int V>
+__global__ void __launch_bounds__((ColShape<T, N, V>::THREADS)) col_kernel(ColArgs<T> a) {
+  __shared__ cx<T> lds_all[ColShape<T, N, V>::LDS];
   if (a.skip && *a.skip != 0.0) return;  // Krylov iteration after convergence
   // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
   // L2).  Give every XCD a contiguous range of (tile, slab) work items so
   // that neighbouring column tiles, whose row segments share cache lines
-  // when the row pitch is not a multiple of 128 bytes, meet in one L2.
+  // when the row pitch is not a multiple of 128 bytes, meet in one L2, and
+  // so that the 1/lambda table entries gathered by neighbouring x-pass tiles
+  // (similar ky) are reused from that L2.
   int tile = blockIdx.x, slab = blockIdx.y;
-  if (gridDim.y > 1) {
+  {
     const int total = gridDim.x * gridDim.y;
     const int hw = blockIdx.x + gridDim.x * blockIdx.y;
     const int xcd = hw & 7, k = hw >> 3;
@@ -337,7 +346,7 @@ __global__ void __launch_bounds__((ColShape<T, N>::THREADS)) col_kernel(ColArgs<
     tile = logical % gridDim.x;
     slab = logical / gridDim.x;
   }
-  col_body<T, N, INV, OP>(a, tile, slab, lds_all, blockIdx.x + gridDim.x * blockIdx.y);
+  col_body<T, N, INV, OP, V>(a, tile, slab, lds_all, blockIdx.x + gridDim.x * blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -379,27 +388,28 @@ struct RowArgs {
   const double* skip;  // if non-null and *skip != 0 the launch does nothing
 };
 
-template <int N>
+template <int N, int V = 0>
 struct RowShape {
   static constexpr int P = Plan<N>::P;
-  static constexpr int G = (256 / P) > 32 ? 32 : 256 / P;  // row pairs per block
+  static constexpr int TH = V ? 512 : 256;
+  static constexpr int G = (TH / P) > 32 ? 32 : (TH / P < 1 ? 1 : TH / P);  // row pairs per block
   static constexpr int THREADS = G * P;
   static constexpr int LEN = PaddedLen<N + 2, true>::value;  // LDS slots per pair
 };
 
-template <typename T, int N, int OP>
+template <typename T, int N, int OP, int V = 0>
 __device__ __forceinline__ void row_body(const RowArgs<T>& a, int ublock, cx<T>* lds_all, int block_linear) {
   using PL = Plan<N>;
   constexpr int P = PL::P;
   constexpr int W = PL::W;
   constexpr int R0 = PL::R0;
   constexpr int RL = LastStage<PL>::R;
-  constexpr int G = RowShape<N>::G;
-  constexpr int LEN = RowShape<N>::LEN;
+  constexpr int G = RowShape<N, V>::G;
+  constexpr int LEN = RowShape<N, V>::LEN;
   constexpr int H = N / 2 + 1;
   using MAP = LdsMap<1, true>;
 
-  const bool active = (int)threadIdx.x < RowShape<N>::THREADS;
+  const bool active = (int)threadIdx.x < RowShape<N, V>::THREADS;
   const int t = threadIdx.x % P;
   const int ul = active ? (int)threadIdx.x / P : 0;
   const int u = ublock * G + ul;
@@ -577,11 +587,11 @@ __device__ __forceinline__ void row_body(const RowArgs<T>& a, int ublock, cx<T>*
   if constexpr (OP == ROW_GRAD || OP == ROW_HVP) block_reduce_store<2>(acc, a.partials, block_linear);
 }
 
-template <typename T, int N, int OP>
-__global__ void __launch_bounds__(RowShape<N>::THREADS) row_kernel(RowArgs<T> a) {
-  __shared__ cx<T> lds_all[RowShape<N>::G * RowShape<N>::LEN];
+template <typename T, int N, int OP, int V>
+__global__ void __launch_bounds__((RowShape<N, V>::THREADS)) row_kernel(RowArgs<T> a) {
+  __shared__ cx<T> lds_all[RowShape<N, V>::G * RowShape<N, V>::LEN];
   if (a.skip && *a.skip != 0.0) return;  // Krylov iteration after convergence
-  row_body<T, N, OP>(a, blockIdx.x, lds_all, blockIdx.x);
+  row_body<T, N, OP, V>(a, blockIdx.x, lds_all, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------

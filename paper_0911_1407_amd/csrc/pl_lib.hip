@@ -63,6 +63,9 @@ struct pl_plan {
   pl_problem prob{};
   bool d_valid = false;    // d holds the diagonal of the last linearisation
   bool d32_valid = false;  // d32 mirrors d
+  // tile variants per pass: cvar[axis x/y][FP64/FP32], rvar[FP64/FP32]
+  int cvar[2][2] = {{0, 0}, {0, 0}};
+  int rvar[2] = {0, 0};
   std::string err;
 };
 
@@ -206,7 +209,8 @@ ColArgs<T> col_args(pl_plan* p, int axis, const cx<T>* in, cx<T>* out) {
 template <typename T>
 hipError_t run_col(pl_plan* p, int axis, bool inverse, int op, const ColArgs<T>& a, int* nb) {
   int dummy;
-  return launch_col<T>(p->n[axis], inverse, op, a, axis == 0 ? 1 : p->n[0], p->stream, nb ? nb : &dummy);
+  return launch_col<T>(p->n[axis], inverse, op, a, axis == 0 ? 1 : p->n[0], p->stream, nb ? nb : &dummy,
+                       p->cvar[axis][sizeof(T) == 4 ? 1 : 0]);
 }
 
 template <typename T>
@@ -229,7 +233,7 @@ RowArgs<T> row_args(pl_plan* p) {
 template <typename T>
 hipError_t run_row(pl_plan* p, int op, const RowArgs<T>& a, int* nb) {
   int dummy;
-  return launch_row<T>(p->n[2], op, a, p->stream, nb ? nb : &dummy);
+  return launch_row<T>(p->n[2], op, a, p->stream, nb ? nb : &dummy, p->rvar[sizeof(T) == 4 ? 1 : 0]);
 }
 
 hipError_t finalize(pl_plan* p, int nb, int K, int kind, int dst, double scale, double aux = 0.0,
@@ -675,6 +679,10 @@ int pl_plan_create(pl_plan** out, const int32_t n[3], const double box[3], int p
   p->Nh = (long)n[0] * n[1] * (n[2] / 2 + 1);
   p->g = Grid{n[0], n[1], n[2], n[2] / 2 + 1, (long)n[1] * (n[2] / 2 + 1)};
   p->ws_bytes = carve(p, nullptr);
+  // default tile variants (measured on MI355X): wide tiles for 512-point
+  // FP64 transforms, the default tiles elsewhere; pl_plan_autotune refines
+  for (int a = 0; a < 2; ++a) p->cvar[a][0] = (n[a] == 512) ? 1 : 0;
+  p->rvar[0] = (n[2] == 512) ? 1 : 0;
   if (hipHostMalloc((void**)&p->h_scal, sizeof(double) * SC_COUNT, hipHostMallocDefault) != hipSuccess) {
     delete p;
     return PL_ERR_HIP;
@@ -927,6 +935,157 @@ bool supported_length(int n) {
   }
 }
 }  // namespace pl
+
+// ===========================================================================
+// Tile-variant autotuner
+// ===========================================================================
+
+namespace {
+
+std::string arch_name() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+// Time one spectral HVP (average of `reps`) with the plan's current variants.
+template <typename T>
+int time_hvp(pl_plan* p, int reps, float* ms) {
+  hipEvent_t e0, e1;
+  HIPCHK(p, hipEventCreate(&e0));
+  HIPCHK(p, hipEventCreate(&e1));
+  int nb = 0, rc = PL_OK;
+  for (int i = 0; i < 2 && !rc; ++i) rc = hvp_hat<T>(p, View<T>::x(p), View<T>::r(p), &nb);
+  if (!rc) {
+    (void)hipEventRecord(e0, p->stream);
+    for (int i = 0; i < reps && !rc; ++i) rc = hvp_hat<T>(p, View<T>::x(p), View<T>::r(p), &nb);
+    (void)hipEventRecord(e1, p->stream);
+    (void)hipEventSynchronize(e1);
+    (void)hipEventElapsedTime(ms, e0, e1);
+    *ms /= (float)reps;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
+template <typename T>
+int tune_precision(pl_plan* p, const std::string& key, std::vector<std::string>& cache_lines, bool* added) {
+  const int pi = sizeof(T) == 4 ? 1 : 0;
+  for (const std::string& line : cache_lines) {
+    if (line.compare(0, key.size() + 1, key + " ") == 0) {
+      int cx, cy, rv;
+      if (std::sscanf(line.c_str() + key.size(), "%d %d %d", &cx, &cy, &rv) == 3) {
+        p->cvar[0][pi] = cx;
+        p->cvar[1][pi] = cy;
+        p->rvar[pi] = rv;
+        return PL_OK;
+      }
+    }
+  }
+  HIPCHK(p, hipMemsetAsync(View<T>::x(p), 0, sizeof(cx<T>) * p->Nh, p->stream));
+  float best = 1e30f;
+  int bx = 0, by = 0, br = 0;
+  const int mx = has_wide_variant(p->n[0]) ? 1 : 0, my = has_wide_variant(p->n[1]) ? 1 : 0,
+            mr = has_wide_variant(p->n[2]) ? 1 : 0;
+  const int reps = p->N >= (1L << 24) ? 5 : 20;
+  for (int cx = 0; cx <= mx; ++cx)
+    for (int cy = 0; cy <= my; ++cy)
+      for (int rv = 0; rv <= mr; ++rv) {
+        p->cvar[0][pi] = cx;
+        p->cvar[1][pi] = cy;
+        p->rvar[pi] = rv;
+        float ms = 0.f;
+        int rc = time_hvp<T>(p, reps, &ms);
+        if (rc) return rc;
+        if (ms < best) {
+          best = ms;
+          bx = cx;
+          by = cy;
+          br = rv;
+        }
+      }
+  p->cvar[0][pi] = bx;
+  p->cvar[1][pi] = by;
+  p->rvar[pi] = br;
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s %d %d %d %.4f", key.c_str(), bx, by, br, (double)best);
+  cache_lines.push_back(buf);
+  *added = true;
+  return PL_OK;
+}
+
+}  // namespace
+
+extern "C" int pl_plan_autotune(pl_plan* p, const char* cache_path) {
+  int rc = check_ready(p);
+  if (rc) return rc;
+  std::vector<std::string> lines;
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "r")) {
+      char buf[512];
+      while (std::fgets(buf, sizeof(buf), f)) {
+        std::string l(buf);
+        while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+        if (!l.empty() && l[0] != '#') lines.push_back(l);
+      }
+      std::fclose(f);
+    }
+  }
+  // a valid Hessian diagonal for the timing runs: linearise at s = mu
+  hipLaunchKernelGGL(linearize_kernel, dim3(grid_blocks(p->N)), dim3(RED_THREADS), 0, p->stream, p->prob.w,
+                     p->prob.w, p->prob.nbar, 0.0, p->e, p->d, p->N);  // beta = 0: d = 0, e = nbar w
+  HIPCHK(p, hipGetLastError());
+  p->d_valid = true;
+  p->d32_valid = false;
+  const std::string base = arch_name() + " " + std::to_string(p->n[0]) + "x" + std::to_string(p->n[1]) + "x" +
+                           std::to_string(p->n[2]);
+  bool added = false;
+  rc = tune_precision<double>(p, base + " fp64", lines, &added);
+  if (rc) return rc;
+  if (p->precision == PL_MIXED) {
+    rc = ensure_d32(p);
+    if (rc) return rc;
+    rc = tune_precision<float>(p, base + " fp32", lines, &added);
+    if (rc) return rc;
+  }
+  p->d_valid = false;  // the timing diagonal is not a linearisation of the posterior
+  if (cache_path && added) {
+    if (FILE* f = std::fopen(cache_path, "w")) {
+      std::fprintf(f, "# pl_plan_autotune cache: arch grid precision x-variant y-variant z-variant ms/HVP\n");
+      for (const std::string& l : lines) std::fprintf(f, "%s\n", l.c_str());
+      std::fclose(f);
+    }
+  }
+  return PL_OK;
+}
+
+extern "C" int pl_plan_set_variants(pl_plan* p, const int32_t v[6]) {
+  if (!p || !v) return PL_ERR_INVALID_ARG;
+  for (int i = 0; i < 6; ++i)
+    if (v[i] != 0 && v[i] != 1) return fail(p, PL_ERR_INVALID_ARG, "tile variants are 0 or 1");
+  p->cvar[0][0] = v[0];
+  p->cvar[1][0] = v[1];
+  p->rvar[0] = v[2];
+  p->cvar[0][1] = v[3];
+  p->cvar[1][1] = v[4];
+  p->rvar[1] = v[5];
+  return PL_OK;
+}
+
+extern "C" int pl_plan_get_variants(const pl_plan* p, int32_t out[6]) {
+  if (!p || !out) return PL_ERR_INVALID_ARG;
+  out[0] = p->cvar[0][0];
+  out[1] = p->cvar[1][0];
+  out[2] = p->rvar[0];
+  out[3] = p->cvar[0][1];
+  out[4] = p->cvar[1][1];
+  out[5] = p->rvar[1];
+  return PL_OK;
+}
 
 // ===========================================================================
 // Batched solves

@@ -1,0 +1,61 @@
+"""Tile variants and the FFT schedule autotuner."""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+from conftest import oracle_problem
+from oracle import model as o_model
+from oracle import newton as o_newton
+from paper_0911_1407_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.mark.parametrize("n", [(128, 128, 128), (256, 192, 512)])
+def test_every_variant_matches_oracle(n):
+    from paper_0911_1407_amd import binding
+    box = tuple(8.0 * v for v in n)
+    inst = synth.make_instance(n, box, 1.2, 1.1, 1.3, radius=0.4 * box[0], mask_frac=0.2, seed=2)
+    P = oracle_problem(inst)
+    plan = binding.Plan(n, box, precision="mixed")
+    plan.set_instance(inst)
+    rng = np.random.default_rng(4)
+    s = inst["s_true"]
+    v = rng.standard_normal(n)
+    v_hat = np.fft.rfftn(v)
+    ref_hat = o_newton.SpectralOps(P).hessvec(o_model.hess_diag(P, s), v_hat)
+    ref = o_model.hessvec(P, s, v)
+    vt = torch.from_numpy(v_hat).cuda()
+    for combo in itertools.product((0, 1), repeat=3):
+        binding.pl_plan_set_variants(plan.h, fp64=combo, fp32=combo)
+        plan.grad(s)
+        out = plan.hessvec_hat(vt).cpu().numpy()
+        assert np.linalg.norm(out - ref_hat) <= 1e-11 * np.linalg.norm(ref_hat), combo
+        out32 = plan.hessvec_hat(vt.to(torch.complex64)).cpu().numpy()
+        assert np.linalg.norm(out32 - ref_hat) <= 2e-5 * np.linalg.norm(ref_hat), combo
+        hv = plan.hessvec(v, s=s).cpu().numpy()
+        assert np.linalg.norm(hv - ref) <= 1e-11 * np.linalg.norm(ref), combo
+
+
+def test_autotune_picks_and_caches(tmp_path):
+    from paper_0911_1407_amd import binding
+    inst = synth.config_instance("sel256", n=128)
+    plan = binding.Plan(inst["n"], inst["box"], precision="mixed")
+    plan.set_instance(inst)
+    cache = str(tmp_path / "tune.txt")
+    v1 = plan.autotune(cache)
+    assert os.path.exists(cache)
+    lines = [l for l in open(cache) if not l.startswith("#")]
+    assert len(lines) == 2  # fp64 and fp32
+    # a second plan reads the cache instead of timing
+    plan2 = binding.Plan(inst["n"], inst["box"], precision="mixed")
+    plan2.set_instance(inst)
+    assert plan2.autotune(cache) == v1
+    # the tuned plan still solves to the same MAP
+    s, info = plan.solve(rtol=1e-8)
+    s2, info2 = plan2.solve(rtol=1e-8)
+    assert info["status"] == 0 and np.array_equal(s.cpu().numpy(), s2.cpu().numpy())
