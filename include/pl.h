@@ -173,9 +173,10 @@ const char* pl_last_error(const pl_plan* plan);
 /* FFT schedule autotuner.  Each column (x, y) and row (z) pass has two tile
    variants (default: 256 threads, <= 64 KB LDS; wide: 512 threads, <= 128 KB
    LDS, longer contiguous row segments) for lengths 128, 192, 256 and 512.
-   Times one spectral Hessian-vector product per combination on the plan's
-   workspace (after pl_set_problem; it overwrites the cached Hessian
-   diagonal) and keeps the fastest, per precision.  cache_path (nullable): a
+   Times the solver's fused CG step (five passes) per combination on the
+   plan's workspace (after pl_set_problem; it overwrites the cached Hessian
+   diagonal and the solver's Krylov vectors) and keeps the fastest, per
+   precision.  cache_path (nullable): a
    text file of earlier results keyed by arch, grid and precision; entries
    found there are used without timing, new ones are appended. */
 int pl_plan_autotune(pl_plan* plan, const char* cache_path);

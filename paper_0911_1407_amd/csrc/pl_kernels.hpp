@@ -258,8 +258,21 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
   } else if constexpr (OP == COL_CG_LAST) {
     // forward transform; q = X + p/lambda (= H p); r -= alpha q and
     // x += alpha p in place; partials (r^H r, r^H M^-1 r).  q is not stored.
-    fft_thread<PL, false, MAP>(v, t, lds, a.tw, active);
+    // p and 1/lambda at the output positions are loaded before the
+    // transform so that their latency overlaps it.
     const int ky = c / a.g.h, kz = c % a.g.h;
+    cx<T> pre_p[W];
+    T pre_il[W];
+#pragma unroll
+    for (int q = 0; q < W / RL; ++q)
+#pragma unroll
+      for (int m = 0; m < RL; ++m) {
+        int kx = out_pos<PL, PL::NS - 1>(t, q, m);
+        long mode = (long)kx * a.g.nyh + c;
+        pre_p[q * RL + m] = valid ? a.base[mode] : cx<T>{T(0), T(0)};
+        pre_il[q * RL + m] = valid ? inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode) : T(0);
+      }
+    fft_thread<PL, false, MAP>(v, t, lds, a.tw, active);
     const double hw = herm_w(kz, a.g);
     const double alpha = a.scal[SC_ALPHA], dbar = a.scal[SC_DBAR];
     double acc[2] = {0.0, 0.0};
@@ -270,8 +283,8 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
         int kx = out_pos<PL, PL::NS - 1>(t, q, m);
         long mode = (long)kx * a.g.nyh + c;
         if (valid) {
-          cx<T> pv = a.base[mode];
-          T il = inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode);
+          cx<T> pv = pre_p[q * RL + m];
+          T il = pre_il[q * RL + m];
           cx<T> x = v[q * RL + m];
           double qx = (double)x.x + (double)il * pv.x, qy = (double)x.y + (double)il * pv.y;
           cx<T> rv = a.cg_r[mode], xv = a.cg_x[mode];
@@ -287,9 +300,21 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
     block_reduce_store<2>(acc, a.partials, block_linear);
     return;
   } else {
-    // forward transform; out = scale * X + (1/lambda) (base - shift at mode 0)
-    fft_thread<PL, false, MAP>(v, t, lds, a.tw, active);
+    // forward transform; out = scale * X + (1/lambda) (base - shift at mode 0);
+    // base and 1/lambda are loaded before the transform (latency overlap)
     const int ky = c / a.g.h, kz = c % a.g.h;
+    cx<T> pre_b[W];
+    T pre_il[W];
+#pragma unroll
+    for (int q = 0; q < W / RL; ++q)
+#pragma unroll
+      for (int m = 0; m < RL; ++m) {
+        int kx = out_pos<PL, PL::NS - 1>(t, q, m);
+        long mode = (long)kx * a.g.nyh + c;
+        pre_b[q * RL + m] = valid ? a.base[mode] : cx<T>{T(0), T(0)};
+        pre_il[q * RL + m] = valid ? inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode) : T(0);
+      }
+    fft_thread<PL, false, MAP>(v, t, lds, a.tw, active);
     double acc[3] = {0.0, 0.0, 0.0};
     const double hw = herm_w(kz, a.g);
 #pragma unroll
@@ -299,10 +324,10 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
         int kx = out_pos<PL, PL::NS - 1>(t, q, m);
         long mode = (long)kx * a.g.nyh + c;
         if (valid) {
-          cx<T> b = a.base[mode];
+          cx<T> b = pre_b[q * RL + m];
           cx<T> bs = b;
           if (mode == 0) bs.x -= (T)a.k0_shift;
-          T il = inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode);
+          T il = pre_il[q * RL + m];
           cx<T> x = v[q * RL + m];
           cx<T> o = {x.x * a.out_scale + il * bs.x, x.y * a.out_scale + il * bs.y};
           v[q * RL + m] = o;
@@ -455,6 +480,25 @@ __device__ __forceinline__ void row_body(const RowArgs<T>& a, int ublock, cx<T>*
 
   double acc[2] = {0.0, 0.0};
 
+  // ROW_HVP: the Hessian diagonal at the positions this thread multiplies,
+  // loaded before the transforms so that its latency overlaps them
+  T pre_dA[ROW_HVP == OP ? W : 1], pre_dB[ROW_HVP == OP ? W : 1];
+  if constexpr (OP == ROW_HVP) {
+#pragma unroll
+    for (int q = 0; q < W / RL; ++q)
+#pragma unroll
+      for (int m = 0; m < RL; ++m) {
+        int e = out_pos<PL, PL::NS - 1>(t, q, m);
+        if constexpr (sizeof(T) == 8) {
+          pre_dA[q * RL + m] = valid ? (T)a.d[rowA * N + e] : T(0);
+          pre_dB[q * RL + m] = valid ? (T)a.d[rowB * N + e] : T(0);
+        } else {
+          pre_dA[q * RL + m] = valid ? a.d32[rowA * N + e] : T(0);
+          pre_dB[q * RL + m] = valid ? a.d32[rowB * N + e] : T(0);
+        }
+      }
+  }
+
   if constexpr (OP == ROW_R2C) {
     fft_thread<PL, false, MAP>(v, t, lds, a.tw, active);
   } else {
@@ -519,15 +563,7 @@ __device__ __forceinline__ void row_body(const RowArgs<T>& a, int ublock, cx<T>*
         for (int q = 0; q < W / RL; ++q)
 #pragma unroll
           for (int m = 0; m < RL; ++m) {
-            int e = out_pos<PL, PL::NS - 1>(t, q, m);
-            T dA, dB;
-            if constexpr (sizeof(T) == 8) {
-              dA = valid ? (T)a.d[rowA * N + e] : T(0);
-              dB = valid ? (T)a.d[rowB * N + e] : T(0);
-            } else {
-              dA = valid ? a.d32[rowA * N + e] : T(0);
-              dB = valid ? a.d32[rowB * N + e] : T(0);
-            }
+            const T dA = pre_dA[q * RL + m], dB = pre_dB[q * RL + m];
             cx<T> z = v[q * RL + m];
             T va = z.x * a.scale, vb = z.y * a.scale;
             acc[0] += (double)dA * va * va + (double)dB * vb * vb;

@@ -26,7 +26,12 @@ The spectrum shape is pk(k) = k^-1.5 exp(-(2 k)^2) (k in h/Mpc, pk(0) = 0) and
 A is set so that the ensemble cell variance (1/V) sum_{k != 0} A pk(k) over
 all grid modes equals sigma^2.
 """
+import os
+
 import numpy as np
+import scipy.fft
+
+_WORKERS = os.cpu_count() or 1
 
 __all__ = ["power_shape_half", "amplitude_for_sigma", "make_instance", "CONFIGS",
            "config_instance", "batch_instances", "hermitian_multiplicity"]
@@ -77,9 +82,10 @@ def make_instance(n, box, sigma, nbar, beta=1.0, radius=None, mask_frac=0.0,
     amp = amplitude_for_sigma(pk, n, box, sigma)
     white = np.random.default_rng([seed, 0]).standard_normal(n)
     lam = amp * pk * ncell / vol
-    g_hat = np.fft.rfftn(white) * np.sqrt(lam)
+    g_hat = scipy.fft.rfftn(white, workers=_WORKERS)
+    g_hat *= np.sqrt(lam)
     g_hat[0, 0, 0] = 0.0
-    G = np.fft.irfftn(g_hat, s=n, axes=(0, 1, 2))
+    G = scipy.fft.irfftn(g_hat, s=n, axes=(0, 1, 2), workers=_WORKERS)
     del white, g_hat, lam
     mu = -0.5 * sigma * sigma
     s_true = G - 0.5 * sigma * sigma

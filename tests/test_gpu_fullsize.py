@@ -1,0 +1,167 @@
+"""Parity at the full workload sizes (256^3 and 512^3), in the launch
+configuration the benchmark uses.
+
+A full oracle solve at 256^3 takes tens of minutes of host CPU, and the MAP
+cannot be computed cell by cell, so at 256^3 and 512^3 the checks use
+properties that hold at any size: the white-prior Lambert-W closed form cell
+by cell, the sum of expected counts equal to the sum of counts at the MAP
+(the k = 0 component of the gradient), mixed vs FP64 agreement, and adjoint
+derivatives against central differences through GPU solves.  Oracle parity
+of the MAP on the selection workload runs at 128^3 (same cells, selection
+radius and mask scaled with the box).
+"""
+import numpy as np
+import pytest
+
+from conftest import oracle_problem
+from oracle import closed_form
+from oracle import newton as o_newton
+from paper_0911_1407_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_map_selection_workload_128_matches_oracle():
+    from paper_0911_1407_amd.binding import Plan
+    inst = synth.config_instance("sel256", n=128)
+    ref, info = o_newton.newton_krylov(oracle_problem(inst), rtol=1e-10)
+    print("oracle", info["newton_its"], info["cg_its"], flush=True)
+    assert info["status"] == "ok"
+    plan = Plan(inst["n"], inst["box"], precision="mixed")
+    plan.set_instance(inst)
+    for prec, rtol, tol in (("fp64", 1e-10, 1e-6), ("mixed", 1e-8, 1e-4)):
+        s, info = plan.solve(rtol=rtol, precision=0 if prec == "fp64" else 1, max_cg=2000)
+        assert info["status"] == 0 and info["rel_grad"] <= rtol, info
+        assert _rel(s.cpu().numpy(), ref) <= tol, prec
+
+
+def _ksum_bound(info, inst, got):
+    e_sum = float(np.sum(inst["nbar"] * inst["w"] * np.exp(inst["beta"] * got)))
+    n_sum = float(np.sum(inst["counts"]))
+    # the k = 0 component of the gradient is beta (sum e - sum N), bounded by
+    # sqrt(N) ||g|| <= sqrt(N) rel_grad ||g0||
+    bound = np.sqrt(got.size) * info["rel_grad"] * info["grad0"] / inst["beta"]
+    return abs(e_sum - n_sum), bound + 1e-9 * n_sum
+
+
+def test_map_256_selection_workload_properties():
+    from paper_0911_1407_amd.binding import Plan
+    inst = synth.config_instance("sel256")
+    plan = Plan(inst["n"], inst["box"], precision="mixed")
+    plan.set_instance(inst)
+    s64, info64 = plan.solve(rtol=1e-10, precision=0, max_cg=2000)
+    print("fp64", info64, flush=True)
+    assert info64["status"] == 0 and info64["rel_grad"] <= 1e-10
+    got = s64.cpu().numpy()
+    diff, bound = _ksum_bound(info64, inst, got)
+    assert diff <= bound
+    s32, info32 = plan.solve(rtol=1e-8, precision=1, max_cg=2000)
+    print("mixed", info32, flush=True)
+    assert info32["status"] == 0 and _rel(s32.cpu().numpy(), got) <= 1e-4
+
+
+def test_white_prior_closed_form_256():
+    from paper_0911_1407_amd.binding import Plan
+    n, box, sigma2 = (256, 256, 256), (500.0,) * 3, 1.3
+    inst = synth.config_instance("sel256")
+    pk = np.full((256, 256, 129), sigma2 * np.prod(box) / np.prod(n))
+    plan = Plan(n, box, precision="fp64")
+    plan.set_problem(inst["w"], inst["counts"], pk, 1.0, -0.3, 0.5, 1.0, 1.0 / sigma2)
+    s, info = plan.solve(rtol=1e-12)
+    ref = closed_form.white_prior_map(mu=-0.3, sigma2=sigma2, beta=1.0, nbar=0.5, w=inst["w"],
+                                      counts=inst["counts"])
+    assert info["status"] == 0 and _rel(s.cpu().numpy(), ref) <= 1e-10
+
+
+@pytest.fixture(scope="module")
+def big512():
+    inst = synth.config_instance("big512")
+    print("generated the 512^3 workload", flush=True)
+    return inst
+
+
+def test_white_prior_closed_form_512():
+    n, box, sigma2 = (512, 512, 512), (1000.0,) * 3, 0.9
+    rng = np.random.default_rng(7)
+    w = rng.uniform(0.0, 1.0, n)
+    counts = rng.poisson(0.2 * w * np.exp(1.2 * rng.normal(0.0, 1.0, n))).astype(np.float64)
+    pk = np.full((512, 512, 257), sigma2 * np.prod(box) / np.prod(n))
+    from paper_0911_1407_amd.binding import Plan
+    plan = Plan(n, box, precision="mixed")
+    plan.set_problem(w, counts, pk, 1.0, -0.5, 0.2, 1.2, 1.0 / sigma2)
+    ref = closed_form.white_prior_map(mu=-0.5, sigma2=sigma2, beta=1.2, nbar=0.2, w=w, counts=counts)
+    s, info = plan.solve(rtol=1e-12, precision=0)
+    assert info["status"] == 0
+    got = s.cpu().numpy()
+    assert _rel(got, ref) <= 1e-10
+    # sampled cells, one by one
+    idx = rng.integers(0, 512, size=(64, 3))
+    for i, j, k in idx:
+        assert abs(got[i, j, k] - ref[i, j, k]) <= 1e-9 * max(1.0, abs(ref[i, j, k]))
+    s, info = plan.solve(rtol=1e-6, precision=1)
+    assert info["status"] == 0 and _rel(s.cpu().numpy(), ref) <= 1e-4
+
+
+def test_map_512_bias_workload_mixed(big512):
+    # 512^3, box 1000 Mpc/h, sigma_G = 2 (1 + delta up to ~1e4), nbar = 0.2,
+    # beta = 1.2, radial selection R = 400; mixed precision to 1e-6
+    from paper_0911_1407_amd.binding import Plan
+    inst = big512
+    plan = Plan(inst["n"], inst["box"], precision="mixed")
+    plan.set_instance(inst)
+    plan.autotune()
+    s, info = plan.solve(rtol=1e-6, precision=1)
+    print("mixed", info, flush=True)
+    assert info["status"] == 0 and info["rel_grad"] <= 1e-6, info
+    got = s.cpu().numpy()
+    assert np.all(np.isfinite(got))
+    diff, bound = _ksum_bound(info, inst, got)
+    assert diff <= bound
+    s64, info64 = plan.solve(rtol=1e-6, precision=0)
+    print("fp64", info64, flush=True)
+    assert info64["status"] == 0
+    assert _rel(got, s64.cpu().numpy()) <= 1e-4
+
+
+def test_adjoint_512_matches_central_fd_beta(big512):
+    # adjoint dL/dbeta and dL/dA of L = sum (s* - s_true)^2 at 512^3 against
+    # central differences (relative step 1e-5) through FP64 GPU solves
+    from paper_0911_1407_amd.binding import Plan
+    inst = big512
+    plan = Plan(inst["n"], inst["box"], precision="mixed")
+    plan.set_instance(inst)
+    plan.autotune()
+    st = torch.from_numpy(inst["s_true"]).cuda()
+
+    def solve(**over):
+        prm = dict(w=inst["w"], counts=inst["counts"], pk=inst["pk"], amp=inst["amp"], mu=inst["mu"],
+                   nbar=inst["nbar"], beta=inst["beta"])
+        prm.update(over)
+        plan.set_problem(**prm)
+        s, info = plan.solve(rtol=1e-10, precision=0, max_newton=200, max_cg=5000)
+        print("solve", over, info["newton_its"], info["cg_its"], flush=True)
+        assert info["status"] == 0, info
+        return s
+
+    s = solve()
+    L = lambda x: float(torch.sum((x - st) ** 2))
+    grads, ainfo = plan.adjoint(s, 2.0 * (s - st), want_fields=False, rtol=1e-8, precision=0, max_cg=20000)
+    print("adjoint", ainfo, flush=True)
+    assert ainfo["status"] == 0, ainfo
+    for key, name in (("beta", "beta"), ("amp", "A")):
+        h = 1e-5 * inst[key]
+        fd = (L(solve(**{key: inst[key] + h})) - L(solve(**{key: inst[key] - h}))) / (2 * h)
+        print(name, grads[name], fd, flush=True)
+        assert abs(grads[name] - fd) <= 1e-3 * abs(fd), (name, grads[name], fd)
+    # the mixed adjoint agrees with the FP64 one to the mixed tolerance
+    plan.set_instance(inst)
+    g32, a32 = plan.adjoint(s, 2.0 * (s - st), want_fields=False, rtol=1e-6, precision=1, max_cg=20000)
+    print("adjoint mixed", a32, flush=True)
+    for name in ("A", "beta"):
+        assert abs(g32[name] - grads[name]) <= 1e-3 * abs(grads[name]), name
