@@ -67,6 +67,8 @@ struct BatchElem {
   float* d32;
   const double* scal;
   double* partials;
+  int* hist;           // preconditioner-constant histogram
+  double* scal_rw;     // same as scal, writable
 };
 
 struct BatchFin {
@@ -129,6 +131,20 @@ __global__ void __launch_bounds__(RED_THREADS) d32_batch_kernel(const BatchElem<
 }
 
 #ifdef PL_OPS_KERNELS
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS) dquant_hist_batch_kernel(const BatchElem<T>* __restrict__ E) {
+  const BatchElem<T> a = E[blockIdx.y];
+  if (!a.active) return;
+  dquant_hist_body(a.d, a.n, a.scal, a.hist, blockIdx.x, gridDim.x);
+}
+
+template <typename T>
+__global__ void dquant_select_batch_kernel(const BatchElem<T>* __restrict__ E) {
+  const BatchElem<T> a = E[blockIdx.x];
+  if (!a.active) return;
+  dquant_select_body(a.hist, a.n, a.scal_rw);
+}
+
 // One block per instance; instances marked inactive are left untouched.
 __global__ void __launch_bounds__(256) finalize_batch_kernel(const BatchFin* __restrict__ F, int K, int kind, int dst,
                                                              double scale, int scale_invN, double aux,

@@ -844,6 +844,55 @@ __global__ void __launch_bounds__(RED_THREADS) ls_eval_kernel(const T* __restric
 
 #ifdef PL_OPS_KERNELS
 // Non-template kernels are defined in one translation unit only.
+// Preconditioner constant.  M_k = 1/lambda_k + c is the Fourier-diagonal
+// preconditioner of H = S_L^-1 + diag(d); it is exact when d is uniform.
+// When d spans many decades (masked holes, selection falling to zero,
+// peaks of 1 + delta ~ 1e4), the slow CG modes are the many large-scale
+// modes living where d is small, while the few peaks only add isolated
+// large eigenvalues; c is therefore taken at the low end of the bulk of d:
+// its 25th percentile over all cells, floored at 1e-3 mean(d).  The
+// percentile is read from a histogram of log2(d / mean(d)).
+constexpr int DQ_BINS = 2048;
+constexpr float DQ_LO = -24.0f, DQ_HI = 24.0f;
+
+__device__ __forceinline__ void dquant_hist_body(const double* __restrict__ d, long n, const double* __restrict__ scal,
+                                                 int* __restrict__ hist, int bx, int nbx) {
+  __shared__ int h[DQ_BINS];
+  for (int i = threadIdx.x; i < DQ_BINS; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  const double mean = scal[SC_DSUM] / (double)n;
+  const float scale = (float)DQ_BINS / (DQ_HI - DQ_LO);
+  for (long i = bx * (long)blockDim.x + threadIdx.x; i < n; i += (long)nbx * blockDim.x) {
+    const double r = mean > 0.0 ? d[i] / mean : 0.0;
+    int b = 0;
+    if (r > 0.0) {
+      float x = (log2f((float)r) - DQ_LO) * scale;
+      b = x < 0.0f ? 0 : (x >= (float)(DQ_BINS - 1) ? DQ_BINS - 1 : (int)x);
+    }
+    atomicAdd(&h[b], 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < DQ_BINS; i += blockDim.x)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+__device__ __forceinline__ void dquant_select_body(int* __restrict__ hist, long n, double* __restrict__ scal) {
+  if (threadIdx.x != 0) return;
+  const double mean = scal[SC_DSUM] / (double)n;
+  const long target = (long)(0.25 * (double)n);
+  long acc = 0;
+  int b = 0;
+  for (; b < DQ_BINS; ++b) {
+    acc += hist[b];
+    if (acc > target) break;
+  }
+  double c = 0.0;
+  if (b > 0 && b < DQ_BINS) c = mean * exp2((double)DQ_LO + ((double)b + 0.5) * (double)(DQ_HI - DQ_LO) / DQ_BINS);
+  if (c < 1e-3 * mean) c = 1e-3 * mean;
+  scal[SC_DBAR] = c;
+  for (int i = 0; i < DQ_BINS; ++i) hist[i] = 0;  // ready for the next use
+}
+
 // d = beta^2 nbar w e^{beta s}, e = nbar w e^{beta s} (real-space input s)
 __global__ void __launch_bounds__(RED_THREADS) linearize_kernel(const double* __restrict__ s, const double* __restrict__ w,
                                                                 double nbar, double beta, double* __restrict__ e,
@@ -861,7 +910,17 @@ __global__ void __launch_bounds__(RED_THREADS) d_to_f32_kernel(const double* __r
     d32[i] = (float)d[i];
 }
 
-// Sum of d (for the preconditioner's mean diagonal)
+__global__ void __launch_bounds__(RED_THREADS) dquant_hist_kernel(const double* __restrict__ d, long n,
+                                                                  const double* __restrict__ scal,
+                                                                  int* __restrict__ hist) {
+  dquant_hist_body(d, n, scal, hist, blockIdx.x, gridDim.x);
+}
+
+__global__ void dquant_select_kernel(int* __restrict__ hist, long n, double* __restrict__ scal) {
+  dquant_select_body(hist, n, scal);
+}
+
+// Sum of d
 __global__ void __launch_bounds__(RED_THREADS) sum_kernel(const double* __restrict__ x, long n,
                                                           double* __restrict__ partials) {
   double acc[1] = {0.0};

@@ -57,6 +57,7 @@ struct pl_plan {
   long partials_len = 0;
   double* scal = nullptr;
   int* flags = nullptr;
+  int* hist = nullptr;       // preconditioner-constant histogram (zeroed after use)
   double* h_scal = nullptr;  // pinned host mirror of scal
   // problem
   bool has_problem = false;
@@ -135,6 +136,7 @@ size_t carve(pl_plan* p, char* base) {
   p->partials = (double*)take(sizeof(double) * p->partials_len * 2);
   p->scal = (double*)take(sizeof(double) * SC_COUNT);
   p->flags = (int*)take(sizeof(int) * 4);
+  p->hist = (int*)take(sizeof(int) * DQ_BINS);
   return off;
 }
 
@@ -321,6 +323,15 @@ int grad_hat(pl_plan* p, double* s_out) {
   HIPCHK(p, finalize(p, nb, 3, FIN_STORE, SC_GG - 1, 1.0 / (double)p->N));
   p->d_valid = true;
   p->d32_valid = false;
+  return PL_OK;
+}
+
+// Preconditioner constant from the current d (device only; see dquant_*).
+int set_precond_constant(pl_plan* p) {
+  hipLaunchKernelGGL(dquant_hist_kernel, dim3(256), dim3(RED_THREADS), 0, p->stream, p->d, p->N, p->scal, p->hist);
+  HIPCHK(p, hipGetLastError());
+  hipLaunchKernelGGL(dquant_select_kernel, dim3(1), dim3(64), 0, p->stream, p->hist, p->N, p->scal);
+  HIPCHK(p, hipGetLastError());
   return PL_OK;
 }
 
@@ -543,7 +554,8 @@ int newton_solve(pl_plan* p, double* s_io, const pl_solve_opts& o, pl_solve_info
       // forcing term: sqrt(||g||/||g0||), but no tighter than needed to
       // reach the stopping tolerance from here (half of it, for margin)
       const double eta = std::min(o.eta_max, std::max(std::sqrt(gn / g0), 0.5 * o.rtol * g0 / gn));
-      HIPCHK(p, set_scalar(p, SC_DBAR, p->h_scal[SC_DSUM] * invN));
+      rc = set_precond_constant(p);
+      if (rc) return rc;
       double alpha = -1.0;
       bool descent = false;
       rc = newton_step<T>(p, eta * gn, o, inf, &alpha, &descent);
@@ -593,7 +605,8 @@ int adjoint_solve(pl_plan* p, const double* s_star, const double* dL_ds, double*
   if (rc) return rc;
   rc = read_scalars(p);
   if (rc) return rc;
-  HIPCHK(p, set_scalar(p, SC_DBAR, p->h_scal[SC_DSUM] * invN));
+  rc = set_precond_constant(p);
+  if (rc) return rc;
   if constexpr (sizeof(T) == 4) {
     rc = ensure_d32(p);
     if (rc) return rc;
@@ -708,6 +721,7 @@ int pl_plan_set_workspace(pl_plan* p, void* dev_ptr) {
     HIPCHK(p, hipStreamSynchronize(p->stream));
   }
   HIPCHK(p, hipMemsetAsync(p->scal, 0, sizeof(double) * SC_COUNT, p->stream));
+  HIPCHK(p, hipMemsetAsync(p->hist, 0, sizeof(int) * DQ_BINS, p->stream));
   HIPCHK(p, hipStreamSynchronize(p->stream));
   p->has_problem = false;
   p->d_valid = false;
@@ -1487,8 +1501,7 @@ int batch_newton(pl_batch* b, double* const* s_io, const pl_solve_opts& o, pl_so
       ++n_active;
       const double eta = std::min(o.eta_max, std::max(std::sqrt(gn[i] / g0[i]), 0.5 * o.rtol * g0[i] / gn[i]));
       ctl[i].tol2 = eta * gn[i] * eta * gn[i];
-      ctl[i].dbar = hs(b, i, SC_DSUM) / (double)b->plans[i]->N;
-      ctl[i].set_tol2 = ctl[i].set_dbar = 1;
+      ctl[i].set_tol2 = 1;
     }
     rc = bctl(b);
     if (rc) return rc;
@@ -1522,11 +1535,18 @@ int batch_newton(pl_batch* b, double* const* s_io, const pl_solve_opts& o, pl_so
       e.d = p->d;
       e.d32 = p->d32;
       e.scal = p->scal;
+      e.scal_rw = p->scal;
       e.partials = p->partials;
+      e.hist = p->hist;
       E[i] = e;
     }
     rc = belem_upload<T>(b);
     if (rc) return rc;
+    hipLaunchKernelGGL((dquant_hist_batch_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream,
+                       elems<T>(b, false));
+    BHIP(b, hipGetLastError());
+    hipLaunchKernelGGL((dquant_select_batch_kernel<T>), dim3(K), dim3(64), 0, b->stream, elems<T>(b, false));
+    BHIP(b, hipGetLastError());
     if constexpr (sizeof(T) == 4) {
       hipLaunchKernelGGL((d32_batch_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream, elems<T>(b, false));
       BHIP(b, hipGetLastError());
