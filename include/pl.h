@@ -123,7 +123,9 @@ int pl_plan_set_stream(pl_plan* plan, void* hip_stream);
 int pl_plan_destroy(pl_plan* plan);
 
 /* Set the posterior (sections 2.1-2.4).  Validates the inputs (PL_ERR_DOMAIN)
-   and builds the 1/lambda tables.  The w / counts arrays are read by later
+   and builds the 1/lambda tables: a radial table indexed by
+   mx^2 + my^2 + mz^2 when every mode's 1/lambda agrees with its shell's to
+   8 ulp (isotropic spectra on cubic boxes), else one entry per mode.  The w / counts arrays are read by later
    calls, so they must stay valid while the plan uses them; pk is read only
    here.  Synchronises the stream. */
 int pl_set_problem(pl_plan* plan, const pl_problem* prob);
@@ -173,18 +175,20 @@ const char* pl_last_error(const pl_plan* plan);
 /* FFT schedule autotuner.  Each column (x, y) and row (z) pass has two tile
    variants (default: 256 threads, <= 64 KB LDS; wide: 512 threads, <= 128 KB
    LDS, longer contiguous row segments) for lengths 128, 192, 256 and 512.
-   Times the solver's fused CG step (five passes) per combination on the
-   plan's workspace (after pl_set_problem; it overwrites the cached Hessian
-   diagonal and the solver's Krylov vectors) and keeps the fastest, per
-   precision.  cache_path (nullable): a
+   Times the solver's fused CG step (five passes) per combination of the x
+   (Krylov-carrying), y and z variants, then the isolated operator
+   (pl_hessvec_hat) per variant of its own x passes, on the plan's workspace
+   (after pl_set_problem; it overwrites the cached Hessian diagonal and the
+   solver's Krylov vectors), and keeps the fastest, per precision.  cache_path (nullable): a
    text file of earlier results keyed by arch, grid and precision; entries
    found there are used without timing, new ones are appended. */
 int pl_plan_autotune(pl_plan* plan, const char* cache_path);
-/* Current variants: out = {x, y, z} for FP64 then {x, y, z} for FP32
-   (0 default, 1 wide; a length without a wide variant runs the default). */
-int pl_plan_get_variants(const pl_plan* plan, int32_t out[6]);
+/* Current variants: out = {x Krylov passes, y, z, x operator passes} for
+   FP64, then the same four for FP32 (0 default, 1 wide; a length without a
+   wide variant runs the default). */
+int pl_plan_get_variants(const pl_plan* plan, int32_t out[8]);
 /* Force the variants (same order); each entry 0 or 1. */
-int pl_plan_set_variants(pl_plan* plan, const int32_t v[6]);
+int pl_plan_set_variants(pl_plan* plan, const int32_t v[8]);
 
 /* ---------------------------------------------------------------------------
  * Batched MAP solves: many independent reconstructions (each its own grid,

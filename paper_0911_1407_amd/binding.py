@@ -217,13 +217,19 @@ def pl_plan_autotune(h, cache_path=None):
 
 
 def pl_plan_get_variants(h):
-    out = (ctypes.c_int32 * 6)()
+    """{precision: (x Krylov passes, y, z, x operator passes)}"""
+    out = (ctypes.c_int32 * 8)()
     _check(h, load().pl_plan_get_variants(h, out))
-    return {"fp64": tuple(out[0:3]), "fp32": tuple(out[3:6])}
+    return {"fp64": tuple(out[0:4]), "fp32": tuple(out[4:8])}
 
 
-def pl_plan_set_variants(h, fp64=(0, 0, 0), fp32=(0, 0, 0)):
-    v = (ctypes.c_int32 * 6)(*[int(x) for x in tuple(fp64) + tuple(fp32)])
+def pl_plan_set_variants(h, fp64=(0, 0, 0, 0), fp32=(0, 0, 0, 0)):
+    """Per precision: (x Krylov passes, y, z, x operator passes); 3-tuples
+    set the operator x passes like the Krylov ones."""
+    def four(t):
+        t = tuple(int(x) for x in t)
+        return t if len(t) == 4 else t + (t[0],)
+    v = (ctypes.c_int32 * 8)(*(four(fp64) + four(fp32)))
     return _check(h, load().pl_plan_set_variants(h, v))
 
 

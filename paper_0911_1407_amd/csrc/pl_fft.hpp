@@ -259,18 +259,22 @@ __device__ __forceinline__ void stage_compute(cx<T>* v, int t, const cx<T>* __re
   }
 }
 
-// LDS accessor: element e of the transform lives at base[e * STRIDE + pad]
+// LDS accessor: element e of the transform lives at base[e * STRIDE + pad],
+// with one padding slot every 2^PL_ROW_PAD_SHIFT elements when PAD is set.
+#ifndef PL_ROW_PAD_SHIFT
+#define PL_ROW_PAD_SHIFT 4
+#endif
 template <int STRIDE, bool PAD>
 struct LdsMap {
   __device__ __forceinline__ static int off(int e) {
-    if constexpr (PAD) return (e + (e >> 4)) * STRIDE;
+    if constexpr (PAD && PL_ROW_PAD_SHIFT < 16) return (e + (e >> PL_ROW_PAD_SHIFT)) * STRIDE;
     else return e * STRIDE;
   }
 };
 
 template <int N, bool PAD>
 struct PaddedLen {
-  static constexpr int value = PAD ? (N + (N >> 4) + 1) : N;
+  static constexpr int value = (PAD && PL_ROW_PAD_SHIFT < 16) ? (N + (N >> PL_ROW_PAD_SHIFT) + 1) : N + 1;
 };
 
 // Exchange between stage S-1 (outputs) and stage S (inputs).  Threads with

@@ -64,9 +64,11 @@ struct pl_plan {
   pl_problem prob{};
   bool d_valid = false;    // d holds the diagonal of the last linearisation
   bool d32_valid = false;  // d32 mirrors d
-  // tile variants per pass: cvar[axis x/y][FP64/FP32], rvar[FP64/FP32]
+  // tile variants per pass: cvar[axis x/y][FP64/FP32], rvar[FP64/FP32];
+  // xcg[FP64/FP32] for the x passes that carry the Krylov updates
   int cvar[2][2] = {{0, 0}, {0, 0}};
   int rvar[2] = {0, 0};
+  int xcg[2] = {0, 0};
   std::string err;
 };
 
@@ -211,8 +213,9 @@ ColArgs<T> col_args(pl_plan* p, int axis, const cx<T>* in, cx<T>* out) {
 template <typename T>
 hipError_t run_col(pl_plan* p, int axis, bool inverse, int op, const ColArgs<T>& a, int* nb) {
   int dummy;
-  return launch_col<T>(p->n[axis], inverse, op, a, axis == 0 ? 1 : p->n[0], p->stream, nb ? nb : &dummy,
-                       p->cvar[axis][sizeof(T) == 4 ? 1 : 0]);
+  const int pi = sizeof(T) == 4 ? 1 : 0;
+  const int v = (axis == 0 && (op == COL_CG_FIRST || op == COL_CG_LAST)) ? p->xcg[pi] : p->cvar[axis][pi];
+  return launch_col<T>(p->n[axis], inverse, op, a, axis == 0 ? 1 : p->n[0], p->stream, nb ? nb : &dummy, v);
 }
 
 template <typename T>
@@ -695,6 +698,7 @@ int pl_plan_create(pl_plan** out, const int32_t n[3], const double box[3], int p
   // default tile variants (measured on MI355X): wide tiles for 512-point
   // FP64 transforms, the default tiles elsewhere; pl_plan_autotune refines
   for (int a = 0; a < 2; ++a) p->cvar[a][0] = (n[a] == 512) ? 1 : 0;
+  p->xcg[0] = p->cvar[0][0];
   p->rvar[0] = (n[2] == 512) ? 1 : 0;
   if (hipHostMalloc((void**)&p->h_scal, sizeof(double) * SC_COUNT, hipHostMallocDefault) != hipSuccess) {
     delete p;
@@ -1017,29 +1021,56 @@ int time_cg_step(pl_plan* p, int reps, float* ms) {
   return PL_OK;
 }
 
+// Time one spectral Hessian-vector product (the isolated operator,
+// pl_hessvec_hat), average of `reps`.
+template <typename T>
+int time_hvp(pl_plan* p, int reps, float* ms) {
+  HIPCHK(p, hipMemsetAsync(View<T>::x(p), 0, sizeof(cx<T>) * p->Nh, p->stream));
+  hipEvent_t e0, e1;
+  HIPCHK(p, hipEventCreate(&e0));
+  HIPCHK(p, hipEventCreate(&e1));
+  int nb = 0, rc = PL_OK;
+  for (int i = 0; i < 2 && !rc; ++i) rc = hvp_hat<T>(p, View<T>::x(p), View<T>::r(p), &nb);
+  if (!rc) {
+    (void)hipEventRecord(e0, p->stream);
+    for (int i = 0; i < reps && !rc; ++i) rc = hvp_hat<T>(p, View<T>::x(p), View<T>::r(p), &nb);
+    (void)hipEventRecord(e1, p->stream);
+    (void)hipEventSynchronize(e1);
+    (void)hipEventElapsedTime(ms, e0, e1);
+    *ms /= (float)reps;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
 template <typename T>
 int tune_precision(pl_plan* p, const std::string& key, std::vector<std::string>& cache_lines, bool* added) {
   const int pi = sizeof(T) == 4 ? 1 : 0;
   for (const std::string& line : cache_lines) {
     if (line.compare(0, key.size() + 1, key + " ") == 0) {
-      int cx, cy, rv;
-      if (std::sscanf(line.c_str() + key.size(), "%d %d %d", &cx, &cy, &rv) == 3) {
-        p->cvar[0][pi] = cx;
+      int xc, cy, rv, xp;
+      float t_cg, t_hvp;  // a line of the older three-variant format has one time only
+      if (std::sscanf(line.c_str() + key.size(), "%d %d %d %d %f %f", &xc, &cy, &rv, &xp, &t_cg, &t_hvp) == 6 &&
+          ((xc | cy | rv | xp) & ~1) == 0) {
+        p->xcg[pi] = xc;
         p->cvar[1][pi] = cy;
         p->rvar[pi] = rv;
+        p->cvar[0][pi] = xp;
         return PL_OK;
       }
     }
   }
-  float best = 1e30f;
-  int bx = 0, by = 0, br = 0;
   const int mx = has_wide_variant(p->n[0]) ? 1 : 0, my = has_wide_variant(p->n[1]) ? 1 : 0,
             mr = has_wide_variant(p->n[2]) ? 1 : 0;
   const int reps = p->N >= (1L << 24) ? 5 : 20;
+  // the solver's CG step: x (Krylov passes), y, z variants
+  float best = 1e30f;
+  int bx = 0, by = 0, br = 0;
   for (int cx = 0; cx <= mx; ++cx)
     for (int cy = 0; cy <= my; ++cy)
       for (int rv = 0; rv <= mr; ++rv) {
-        p->cvar[0][pi] = cx;
+        p->xcg[pi] = cx;
         p->cvar[1][pi] = cy;
         p->rvar[pi] = rv;
         float ms = 0.f;
@@ -1052,11 +1083,26 @@ int tune_precision(pl_plan* p, const std::string& key, std::vector<std::string>&
           br = rv;
         }
       }
-  p->cvar[0][pi] = bx;
+  p->xcg[pi] = bx;
   p->cvar[1][pi] = by;
   p->rvar[pi] = br;
+  // the isolated operator's x passes (plain inverse, forward + prior)
+  float best_h = 1e30f;
+  int bp = 0;
+  for (int xp = 0; xp <= mx; ++xp) {
+    p->cvar[0][pi] = xp;
+    float ms = 0.f;
+    int rc = time_hvp<T>(p, reps, &ms);
+    if (rc) return rc;
+    if (ms < best_h) {
+      best_h = ms;
+      bp = xp;
+    }
+  }
+  p->cvar[0][pi] = bp;
   char buf[256];
-  std::snprintf(buf, sizeof(buf), "%s %d %d %d %.4f", key.c_str(), bx, by, br, (double)best);
+  std::snprintf(buf, sizeof(buf), "%s %d %d %d %d %.4f %.4f", key.c_str(), bx, by, br, bp, (double)best,
+                (double)best_h);
   cache_lines.push_back(buf);
   *added = true;
   return PL_OK;
@@ -1099,7 +1145,9 @@ extern "C" int pl_plan_autotune(pl_plan* p, const char* cache_path) {
   p->d_valid = false;  // the timing diagonal is not a linearisation of the posterior
   if (cache_path && added) {
     if (FILE* f = std::fopen(cache_path, "w")) {
-      std::fprintf(f, "# pl_plan_autotune cache: arch grid precision x-variant y-variant z-variant ms/CG-step\n");
+      std::fprintf(f,
+                   "# pl_plan_autotune cache: arch grid precision x(Krylov passes) y z x(operator passes) "
+                   "ms/CG-step ms/HVP\n");
       for (const std::string& l : lines) std::fprintf(f, "%s\n", l.c_str());
       std::fclose(f);
     }
@@ -1107,27 +1155,27 @@ extern "C" int pl_plan_autotune(pl_plan* p, const char* cache_path) {
   return PL_OK;
 }
 
-extern "C" int pl_plan_set_variants(pl_plan* p, const int32_t v[6]) {
+extern "C" int pl_plan_set_variants(pl_plan* p, const int32_t v[8]) {
   if (!p || !v) return PL_ERR_INVALID_ARG;
-  for (int i = 0; i < 6; ++i)
+  for (int i = 0; i < 8; ++i)
     if (v[i] != 0 && v[i] != 1) return fail(p, PL_ERR_INVALID_ARG, "tile variants are 0 or 1");
-  p->cvar[0][0] = v[0];
-  p->cvar[1][0] = v[1];
-  p->rvar[0] = v[2];
-  p->cvar[0][1] = v[3];
-  p->cvar[1][1] = v[4];
-  p->rvar[1] = v[5];
+  for (int pi = 0; pi < 2; ++pi) {
+    p->xcg[pi] = v[4 * pi + 0];
+    p->cvar[1][pi] = v[4 * pi + 1];
+    p->rvar[pi] = v[4 * pi + 2];
+    p->cvar[0][pi] = v[4 * pi + 3];
+  }
   return PL_OK;
 }
 
-extern "C" int pl_plan_get_variants(const pl_plan* p, int32_t out[6]) {
+extern "C" int pl_plan_get_variants(const pl_plan* p, int32_t out[8]) {
   if (!p || !out) return PL_ERR_INVALID_ARG;
-  out[0] = p->cvar[0][0];
-  out[1] = p->cvar[1][0];
-  out[2] = p->rvar[0];
-  out[3] = p->cvar[0][1];
-  out[4] = p->cvar[1][1];
-  out[5] = p->rvar[1];
+  for (int pi = 0; pi < 2; ++pi) {
+    out[4 * pi + 0] = p->xcg[pi];
+    out[4 * pi + 1] = p->cvar[1][pi];
+    out[4 * pi + 2] = p->rvar[pi];
+    out[4 * pi + 3] = p->cvar[0][pi];
+  }
   return PL_OK;
 }
 

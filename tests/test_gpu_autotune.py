@@ -30,7 +30,7 @@ def test_every_variant_matches_oracle(n):
     ref_hat = o_newton.SpectralOps(P).hessvec(o_model.hess_diag(P, s), v_hat)
     ref = o_model.hessvec(P, s, v)
     vt = torch.from_numpy(v_hat).cuda()
-    for combo in itertools.product((0, 1), repeat=3):
+    for combo in itertools.product((0, 1), repeat=4):
         binding.pl_plan_set_variants(plan.h, fp64=combo, fp32=combo)
         plan.grad(s)
         out = plan.hessvec_hat(vt).cpu().numpy()
