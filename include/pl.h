@@ -123,12 +123,19 @@ int pl_plan_set_stream(pl_plan* plan, void* hip_stream);
 int pl_plan_destroy(pl_plan* plan);
 
 /* Set the posterior (sections 2.1-2.4).  Validates the inputs (PL_ERR_DOMAIN)
-   and builds the 1/lambda tables: a radial table indexed by
-   mx^2 + my^2 + mz^2 when every mode's 1/lambda agrees with its shell's to
-   8 ulp (isotropic spectra on cubic boxes), else one entry per mode.  The w / counts arrays are read by later
+   and builds the 1/lambda tables: one entry per mode, and a radial table
+   indexed by mx^2 + my^2 + mz^2, valid when every mode's 1/lambda agrees
+   with its shell's to 8 ulp (isotropic spectra on cubic boxes).  The w / counts arrays are read by later
    calls, so they must stay valid while the plan uses them; pk is read only
    here.  Synchronises the stream. */
 int pl_set_problem(pl_plan* plan, const pl_problem* prob);
+
+/* Whether the last pl_set_problem found the spectrum radial (every mode's
+   1/lambda equal to its shell's to 8 ulp, which needs a cubic box): then
+   *radial_out (host) receives 1 and the shell table may stand in for the
+   per-mode one (see PL_NUM_VARIANTS), else 0.  PL_ERR_NO_PROBLEM before a
+   problem is set. */
+int pl_plan_prior_is_radial(const pl_plan* plan, int32_t* radial_out);
 
 /* Gradient of f at the real field s (section 3.1.2): grad_out (device, N).
    obj_out (host, nullable) receives f(s).  Caches the Hessian diagonal for
@@ -175,20 +182,31 @@ const char* pl_last_error(const pl_plan* plan);
 /* FFT schedule autotuner.  Each column (x, y) and row (z) pass has two tile
    variants (default: 256 threads, <= 64 KB LDS; wide: 512 threads, <= 128 KB
    LDS, longer contiguous row segments) for lengths 128, 192, 256 and 512.
-   Times the solver's fused CG step (five passes) per combination of the x
-   (Krylov-carrying), y and z variants, then the isolated operator
-   (pl_hessvec_hat) per variant of its own x passes, on the plan's workspace
-   (after pl_set_problem; it overwrites the cached Hessian diagonal and the
-   solver's Krylov vectors), and keeps the fastest, per precision.  cache_path (nullable): a
-   text file of earlier results keyed by arch, grid and precision; entries
-   found there are used without timing, new ones are appended. */
+   The x passes that apply 1/lambda can also read it from the radial shell
+   table (when pl_plan_prior_is_radial) or from the per-mode table: the
+   shell table saves a streaming read, the per-mode table avoids a
+   scattered lookup.  Times the solver's fused CG step (five passes) per
+   combination of the Krylov-carrying x variant, the y and z variants and
+   the Krylov passes' table, then the isolated operator (pl_hessvec_hat) per
+   combination of its own x variant and table, on the plan's workspace (after
+   pl_set_problem; it overwrites the cached Hessian diagonal and the solver's
+   Krylov vectors), and keeps the fastest, per precision.  Every choice
+   gives the same result up to rounding.  cache_path (nullable): a text file
+   of earlier results keyed by arch, grid, table availability and precision;
+   entries found there are used without timing, new ones are appended. */
 int pl_plan_autotune(pl_plan* plan, const char* cache_path);
-/* Current variants: out = {x Krylov passes, y, z, x operator passes} for
-   FP64, then the same four for FP32 (0 default, 1 wide; a length without a
-   wide variant runs the default). */
-int pl_plan_get_variants(const pl_plan* plan, int32_t out[8]);
-/* Force the variants (same order); each entry 0 or 1. */
-int pl_plan_set_variants(pl_plan* plan, const int32_t v[8]);
+
+/* Number of schedule choices per precision.  In order: x variant of the
+   Krylov-carrying passes, y variant, z variant, x variant of the operator's
+   passes, table of the Krylov passes (1 shell, 0 per mode), table of the
+   operator's passes.  Variants: 0 default, 1 wide (a length without a wide
+   variant runs the default); a shell-table choice runs the per-mode table
+   when the spectrum is not radial. */
+#define PL_NUM_VARIANTS 6
+/* Current choices: out = the PL_NUM_VARIANTS choices for FP64, then FP32. */
+int pl_plan_get_variants(const pl_plan* plan, int32_t out[2 * PL_NUM_VARIANTS]);
+/* Force the choices (same order); each entry 0 or 1. */
+int pl_plan_set_variants(pl_plan* plan, const int32_t v[2 * PL_NUM_VARIANTS]);
 
 /* ---------------------------------------------------------------------------
  * Batched MAP solves: many independent reconstructions (each its own grid,

@@ -33,7 +33,7 @@ EXPORTED = ("pl_default_opts", "pl_plan_create", "pl_plan_set_workspace", "pl_pl
             "pl_hessvec_hat", "pl_hessvec_hat_f32", "pl_newton_krylov_solve", "pl_solve_adjoint",
             "pl_last_error", "pl_batch_create", "pl_batch_set_workspace", "pl_batch_set_problem",
             "pl_batch_solve", "pl_batch_destroy", "pl_batch_last_error", "pl_plan_autotune",
-            "pl_plan_get_variants", "pl_plan_set_variants")
+            "pl_plan_get_variants", "pl_plan_set_variants", "pl_plan_prior_is_radial")
 
 BATCH_LENGTHS = (32, 48, 64, 96, 128)
 
@@ -106,6 +106,7 @@ def load(path=LIB_PATH):
     lib.pl_batch_destroy.argtypes = [vp]
     lib.pl_plan_autotune.argtypes = [vp, ctypes.c_char_p]
     lib.pl_plan_get_variants.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.pl_plan_prior_is_radial.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     lib.pl_plan_set_variants.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     lib.pl_batch_last_error.argtypes = [vp]
     lib.pl_batch_last_error.restype = ctypes.c_char_p
@@ -216,20 +217,31 @@ def pl_plan_autotune(h, cache_path=None):
     return _check(h, load().pl_plan_autotune(h, cache_path.encode() if cache_path else None))
 
 
+def pl_plan_prior_is_radial(h):
+    out = ctypes.c_int32(0)
+    _check(h, load().pl_plan_prior_is_radial(h, ctypes.byref(out)))
+    return bool(out.value)
+
+
+VARIANT_SLOTS = ("x_krylov", "y", "z", "x_operator", "table_krylov", "table_operator")
+
+
 def pl_plan_get_variants(h):
-    """{precision: (x Krylov passes, y, z, x operator passes)}"""
-    out = (ctypes.c_int32 * 8)()
+    """{precision: (x Krylov passes, y, z, x operator passes, table of the
+    Krylov passes, table of the operator passes)}"""
+    k = len(VARIANT_SLOTS)
+    out = (ctypes.c_int32 * (2 * k))()
     _check(h, load().pl_plan_get_variants(h, out))
-    return {"fp64": tuple(out[0:4]), "fp32": tuple(out[4:8])}
+    return {"fp64": tuple(out[0:k]), "fp32": tuple(out[k:2 * k])}
 
 
-def pl_plan_set_variants(h, fp64=(0, 0, 0, 0), fp32=(0, 0, 0, 0)):
-    """Per precision: (x Krylov passes, y, z, x operator passes); 3-tuples
-    set the operator x passes like the Krylov ones."""
-    def four(t):
-        t = tuple(int(x) for x in t)
-        return t if len(t) == 4 else t + (t[0],)
-    v = (ctypes.c_int32 * 8)(*(four(fp64) + four(fp32)))
+def pl_plan_set_variants(h, fp64=(0, 0, 0, 0, 0, 0), fp32=(0, 0, 0, 0, 1, 1)):
+    """Per precision, the choices in VARIANT_SLOTS order."""
+    k = len(VARIANT_SLOTS)
+    vals = tuple(int(x) for x in fp64) + tuple(int(x) for x in fp32)
+    if len(vals) != 2 * k:
+        raise ValueError(f"expected {k} choices per precision")
+    v = (ctypes.c_int32 * (2 * k))(*vals)
     return _check(h, load().pl_plan_set_variants(h, v))
 
 

@@ -26,6 +26,10 @@ struct Status {
   std::string msg;
 };
 
+// Schedule choices per precision, in the order of pl_plan_get_variants.
+enum VarSlot { V_XCG = 0, V_Y, V_Z, V_XOP, V_TAB_CG, V_TAB_OP, V_COUNT };
+static_assert(V_COUNT == PL_NUM_VARIANTS, "schedule slots");
+
 }  // namespace
 
 struct pl_plan {
@@ -64,11 +68,9 @@ struct pl_plan {
   pl_problem prob{};
   bool d_valid = false;    // d holds the diagonal of the last linearisation
   bool d32_valid = false;  // d32 mirrors d
-  // tile variants per pass: cvar[axis x/y][FP64/FP32], rvar[FP64/FP32];
-  // xcg[FP64/FP32] for the x passes that carry the Krylov updates
-  int cvar[2][2] = {{0, 0}, {0, 0}};
-  int rvar[2] = {0, 0};
-  int xcg[2] = {0, 0};
+  // schedule choices per precision [FP64/FP32] (see VarSlot); the table
+  // choices apply only when the radial table is valid
+  int var[2][V_COUNT] = {{0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 1, 1}};
   std::string err;
 };
 
@@ -168,6 +170,7 @@ struct View<double> {
   static cx<double>* t(pl_plan* p) { return p->t64; }
   static double* preal(pl_plan* p) { return p->preal; }
   static const double* tab(pl_plan* p) { return p->radial ? p->tab_rad : p->tab_mode; }
+  static const double* tab(pl_plan* p, int radial) { return radial ? p->tab_rad : p->tab_mode; }
   static const cx<double>* tw(pl_plan* p, int a) { return p->tw64[a]; }
 };
 template <>
@@ -178,6 +181,7 @@ struct View<float> {
   static cx<float>* t(pl_plan* p) { return p->t32; }
   static float* preal(pl_plan* p) { return p->preal32; }
   static const float* tab(pl_plan* p) { return p->radial ? p->tab_rad32 : p->tab_mode32; }
+  static const float* tab(pl_plan* p, int radial) { return radial ? p->tab_rad32 : p->tab_mode32; }
   static const cx<float>* tw(pl_plan* p, int a) { return p->tw32[a]; }
 };
 
@@ -214,8 +218,14 @@ template <typename T>
 hipError_t run_col(pl_plan* p, int axis, bool inverse, int op, const ColArgs<T>& a, int* nb) {
   int dummy;
   const int pi = sizeof(T) == 4 ? 1 : 0;
-  const int v = (axis == 0 && (op == COL_CG_FIRST || op == COL_CG_LAST)) ? p->xcg[pi] : p->cvar[axis][pi];
-  return launch_col<T>(p->n[axis], inverse, op, a, axis == 0 ? 1 : p->n[0], p->stream, nb ? nb : &dummy, v);
+  const bool krylov = op == COL_CG_FIRST || op == COL_CG_LAST;
+  const int v = axis == 1 ? p->var[pi][V_Y] : p->var[pi][krylov ? V_XCG : V_XOP];
+  if (op == COL_PLAIN)
+    return launch_col<T>(p->n[axis], inverse, op, a, axis == 0 ? 1 : p->n[0], p->stream, nb ? nb : &dummy, v);
+  ColArgs<T> b = a;  // the 1/lambda table this pass reads
+  b.radial = p->radial && p->var[pi][krylov ? V_TAB_CG : V_TAB_OP];
+  b.inv_lam = View<T>::tab(p, b.radial);
+  return launch_col<T>(p->n[axis], inverse, op, b, axis == 0 ? 1 : p->n[0], p->stream, nb ? nb : &dummy, v);
 }
 
 template <typename T>
@@ -238,7 +248,7 @@ RowArgs<T> row_args(pl_plan* p) {
 template <typename T>
 hipError_t run_row(pl_plan* p, int op, const RowArgs<T>& a, int* nb) {
   int dummy;
-  return launch_row<T>(p->n[2], op, a, p->stream, nb ? nb : &dummy, p->rvar[sizeof(T) == 4 ? 1 : 0]);
+  return launch_row<T>(p->n[2], op, a, p->stream, nb ? nb : &dummy, p->var[sizeof(T) == 4 ? 1 : 0][V_Z]);
 }
 
 hipError_t finalize(pl_plan* p, int nb, int K, int kind, int dst, double scale, double aux = 0.0,
@@ -697,9 +707,9 @@ int pl_plan_create(pl_plan** out, const int32_t n[3], const double box[3], int p
   p->ws_bytes = carve(p, nullptr);
   // default tile variants (measured on MI355X): wide tiles for 512-point
   // FP64 transforms, the default tiles elsewhere; pl_plan_autotune refines
-  for (int a = 0; a < 2; ++a) p->cvar[a][0] = (n[a] == 512) ? 1 : 0;
-  p->xcg[0] = p->cvar[0][0];
-  p->rvar[0] = (n[2] == 512) ? 1 : 0;
+  p->var[0][V_XCG] = p->var[0][V_XOP] = (n[0] == 512) ? 1 : 0;
+  p->var[0][V_Y] = (n[1] == 512) ? 1 : 0;
+  p->var[0][V_Z] = (n[2] == 512) ? 1 : 0;
   if (hipHostMalloc((void**)&p->h_scal, sizeof(double) * SC_COUNT, hipHostMallocDefault) != hipSuccess) {
     delete p;
     return PL_ERR_HIP;
@@ -1044,65 +1054,62 @@ int time_hvp(pl_plan* p, int reps, float* ms) {
   return rc;
 }
 
+// Try every combination of the choices in `slots` (each 0..max), timing
+// with `timer`; keep the fastest.  Returns its time in *best.
+template <typename Timer>
+int tune_slots(pl_plan* p, int pi, const int* slots, const int* maxv, int ns, Timer timer, float* best) {
+  int cur[V_COUNT] = {}, keep[V_COUNT] = {};
+  *best = 1e30f;
+  for (;;) {
+    for (int i = 0; i < ns; ++i) p->var[pi][slots[i]] = cur[i];
+    float ms = 0.f;
+    int rc = timer(&ms);
+    if (rc) return rc;
+    if (ms < *best) {
+      *best = ms;
+      for (int i = 0; i < ns; ++i) keep[i] = cur[i];
+    }
+    int i = 0;
+    while (i < ns && cur[i] == maxv[i]) cur[i++] = 0;
+    if (i == ns) break;
+    ++cur[i];
+  }
+  for (int i = 0; i < ns; ++i) p->var[pi][slots[i]] = keep[i];
+  return PL_OK;
+}
+
 template <typename T>
 int tune_precision(pl_plan* p, const std::string& key, std::vector<std::string>& cache_lines, bool* added) {
   const int pi = sizeof(T) == 4 ? 1 : 0;
   for (const std::string& line : cache_lines) {
     if (line.compare(0, key.size() + 1, key + " ") == 0) {
-      int xc, cy, rv, xp;
-      float t_cg, t_hvp;  // a line of the older three-variant format has one time only
-      if (std::sscanf(line.c_str() + key.size(), "%d %d %d %d %f %f", &xc, &cy, &rv, &xp, &t_cg, &t_hvp) == 6 &&
-          ((xc | cy | rv | xp) & ~1) == 0) {
-        p->xcg[pi] = xc;
-        p->cvar[1][pi] = cy;
-        p->rvar[pi] = rv;
-        p->cvar[0][pi] = xp;
+      int v[V_COUNT];
+      float t_cg, t_hvp;
+      if (std::sscanf(line.c_str() + key.size(), "%d %d %d %d %d %d %f %f", &v[0], &v[1], &v[2], &v[3], &v[4],
+                      &v[5], &t_cg, &t_hvp) == V_COUNT + 2 &&
+          ((v[0] | v[1] | v[2] | v[3] | v[4] | v[5]) & ~1) == 0) {
+        for (int i = 0; i < V_COUNT; ++i) p->var[pi][i] = v[i];
         return PL_OK;
       }
     }
   }
   const int mx = has_wide_variant(p->n[0]) ? 1 : 0, my = has_wide_variant(p->n[1]) ? 1 : 0,
-            mr = has_wide_variant(p->n[2]) ? 1 : 0;
+            mr = has_wide_variant(p->n[2]) ? 1 : 0, mt = p->radial ? 1 : 0;
   const int reps = p->N >= (1L << 24) ? 5 : 20;
-  // the solver's CG step: x (Krylov passes), y, z variants
-  float best = 1e30f;
-  int bx = 0, by = 0, br = 0;
-  for (int cx = 0; cx <= mx; ++cx)
-    for (int cy = 0; cy <= my; ++cy)
-      for (int rv = 0; rv <= mr; ++rv) {
-        p->xcg[pi] = cx;
-        p->cvar[1][pi] = cy;
-        p->rvar[pi] = rv;
-        float ms = 0.f;
-        int rc = time_cg_step<T>(p, reps, &ms);
-        if (rc) return rc;
-        if (ms < best) {
-          best = ms;
-          bx = cx;
-          by = cy;
-          br = rv;
-        }
-      }
-  p->xcg[pi] = bx;
-  p->cvar[1][pi] = by;
-  p->rvar[pi] = br;
-  // the isolated operator's x passes (plain inverse, forward + prior)
-  float best_h = 1e30f;
-  int bp = 0;
-  for (int xp = 0; xp <= mx; ++xp) {
-    p->cvar[0][pi] = xp;
-    float ms = 0.f;
-    int rc = time_hvp<T>(p, reps, &ms);
-    if (rc) return rc;
-    if (ms < best_h) {
-      best_h = ms;
-      bp = xp;
-    }
-  }
-  p->cvar[0][pi] = bp;
+  // the solver's CG step: x passes carrying the Krylov updates, y, z, and
+  // the table those x passes read
+  const int cg_slots[4] = {V_XCG, V_Y, V_Z, V_TAB_CG}, cg_max[4] = {mx, my, mr, mt};
+  float best_cg = 0.f, best_hvp = 0.f;
+  int rc = tune_slots(p, pi, cg_slots, cg_max, 4, [&](float* ms) { return time_cg_step<T>(p, reps, ms); }, &best_cg);
+  if (rc) return rc;
+  // the isolated operator's x passes and their table
+  const int op_slots[2] = {V_XOP, V_TAB_OP}, op_max[2] = {mx, mt};
+  rc = tune_slots(p, pi, op_slots, op_max, 2, [&](float* ms) { return time_hvp<T>(p, reps, ms); }, &best_hvp);
+  if (rc) return rc;
+  const int* v = p->var[pi];
   char buf[256];
-  std::snprintf(buf, sizeof(buf), "%s %d %d %d %d %.4f %.4f", key.c_str(), bx, by, br, bp, (double)best,
-                (double)best_h);
+  std::snprintf(buf, sizeof(buf), "%s %d %d %d %d %d %d %.4f %.4f", key.c_str(), v[0], v[1], v[2], v[3], v[4], v[5],
+                (double)best_cg, (double)best_hvp);
   cache_lines.push_back(buf);
   *added = true;
   return PL_OK;
@@ -1131,8 +1138,9 @@ extern "C" int pl_plan_autotune(pl_plan* p, const char* cache_path) {
   HIPCHK(p, hipGetLastError());
   p->d_valid = true;
   p->d32_valid = false;
+  // keyed by whether the problem's spectrum allows the radial table
   const std::string base = arch_name() + " " + std::to_string(p->n[0]) + "x" + std::to_string(p->n[1]) + "x" +
-                           std::to_string(p->n[2]);
+                           std::to_string(p->n[2]) + (p->radial ? " shell" : " mode");
   bool added = false;
   rc = tune_precision<double>(p, base + " fp64", lines, &added);
   if (rc) return rc;
@@ -1146,8 +1154,8 @@ extern "C" int pl_plan_autotune(pl_plan* p, const char* cache_path) {
   if (cache_path && added) {
     if (FILE* f = std::fopen(cache_path, "w")) {
       std::fprintf(f,
-                   "# pl_plan_autotune cache: arch grid precision x(Krylov passes) y z x(operator passes) "
-                   "ms/CG-step ms/HVP\n");
+                   "# pl_plan_autotune cache: arch grid table precision x(Krylov passes) y z x(operator passes) "
+                   "table(Krylov) table(operator) ms/CG-step ms/HVP\n");
       for (const std::string& l : lines) std::fprintf(f, "%s\n", l.c_str());
       std::fclose(f);
     }
@@ -1155,27 +1163,26 @@ extern "C" int pl_plan_autotune(pl_plan* p, const char* cache_path) {
   return PL_OK;
 }
 
-extern "C" int pl_plan_set_variants(pl_plan* p, const int32_t v[8]) {
+extern "C" int pl_plan_set_variants(pl_plan* p, const int32_t v[2 * PL_NUM_VARIANTS]) {
   if (!p || !v) return PL_ERR_INVALID_ARG;
-  for (int i = 0; i < 8; ++i)
-    if (v[i] != 0 && v[i] != 1) return fail(p, PL_ERR_INVALID_ARG, "tile variants are 0 or 1");
-  for (int pi = 0; pi < 2; ++pi) {
-    p->xcg[pi] = v[4 * pi + 0];
-    p->cvar[1][pi] = v[4 * pi + 1];
-    p->rvar[pi] = v[4 * pi + 2];
-    p->cvar[0][pi] = v[4 * pi + 3];
-  }
+  for (int i = 0; i < 2 * V_COUNT; ++i)
+    if (v[i] != 0 && v[i] != 1) return fail(p, PL_ERR_INVALID_ARG, "schedule choices are 0 or 1");
+  for (int pi = 0; pi < 2; ++pi)
+    for (int i = 0; i < V_COUNT; ++i) p->var[pi][i] = v[V_COUNT * pi + i];
   return PL_OK;
 }
 
-extern "C" int pl_plan_get_variants(const pl_plan* p, int32_t out[8]) {
+extern "C" int pl_plan_get_variants(const pl_plan* p, int32_t out[2 * PL_NUM_VARIANTS]) {
   if (!p || !out) return PL_ERR_INVALID_ARG;
-  for (int pi = 0; pi < 2; ++pi) {
-    out[4 * pi + 0] = p->xcg[pi];
-    out[4 * pi + 1] = p->cvar[1][pi];
-    out[4 * pi + 2] = p->rvar[pi];
-    out[4 * pi + 3] = p->cvar[0][pi];
-  }
+  for (int pi = 0; pi < 2; ++pi)
+    for (int i = 0; i < V_COUNT; ++i) out[V_COUNT * pi + i] = p->var[pi][i];
+  return PL_OK;
+}
+
+extern "C" int pl_plan_prior_is_radial(const pl_plan* p, int32_t* radial_out) {
+  if (!p || !radial_out) return PL_ERR_INVALID_ARG;
+  if (!p->has_problem) return fail(const_cast<pl_plan*>(p), PL_ERR_NO_PROBLEM, "pl_set_problem has not been called");
+  *radial_out = p->radial;
   return PL_OK;
 }
 

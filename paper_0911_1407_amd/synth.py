@@ -43,6 +43,13 @@ def _fold(n):
 
 
 def _kmag_half(n, box):
+    if box[0] == box[1] == box[2]:
+        # |k| from the exact integer m^2 = mx^2 + my^2 + mz^2: every mode of
+        # a shell gets a bitwise identical |k|, so the spectrum is exactly
+        # isotropic (no rounding differences between permuted components)
+        m2 = (_fold(n[0])[:, None, None] ** 2 + _fold(n[1])[None, :, None] ** 2
+              + np.arange(n[2] // 2 + 1)[None, None, :] ** 2)
+        return (2 * np.pi / box[0]) * np.sqrt(m2.astype(np.float64))
     kx = (2 * np.pi / box[0]) * _fold(n[0]).astype(np.float64)
     ky = (2 * np.pi / box[1]) * _fold(n[1]).astype(np.float64)
     kz = (2 * np.pi / box[2]) * np.arange(n[2] // 2 + 1, dtype=np.float64)

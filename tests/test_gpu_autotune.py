@@ -30,7 +30,11 @@ def test_every_variant_matches_oracle(n):
     ref_hat = o_newton.SpectralOps(P).hessvec(o_model.hess_diag(P, s), v_hat)
     ref = o_model.hessvec(P, s, v)
     vt = torch.from_numpy(v_hat).cuda()
-    for combo in itertools.product((0, 1), repeat=4):
+    radial = binding.pl_plan_prior_is_radial(plan.h)
+    assert radial == (len(set(n)) == 1)
+    # the operator's passes: x (operator), y, z variants and its table
+    for xo, y, z, tab in itertools.product((0, 1), repeat=4):
+        combo = (0, y, z, xo, 0, tab)
         binding.pl_plan_set_variants(plan.h, fp64=combo, fp32=combo)
         plan.grad(s)
         out = plan.hessvec_hat(vt).cpu().numpy()
@@ -39,6 +43,20 @@ def test_every_variant_matches_oracle(n):
         assert np.linalg.norm(out32 - ref_hat) <= 2e-5 * np.linalg.norm(ref_hat), combo
         hv = plan.hessvec(v, s=s).cpu().numpy()
         assert np.linalg.norm(hv - ref) <= 1e-11 * np.linalg.norm(ref), combo
+    if len(set(n)) == 1:
+        # the Krylov-carrying passes: every x variant and table choice
+        # reaches the same MAP (FP64 and mixed)
+        ref_s = None
+        for xk, tab in itertools.product((0, 1), repeat=2):
+            combo = (xk, 0, 0, 0, tab, 0)
+            binding.pl_plan_set_variants(plan.h, fp64=combo, fp32=combo)
+            for prec in (binding.PL_FP64, binding.PL_MIXED):
+                sm, info = plan.solve(rtol=1e-10, precision=prec)
+                assert info["status"] == 0, (combo, prec, info)
+                sm = sm.cpu().numpy()
+                if ref_s is None:
+                    ref_s = sm
+                assert np.linalg.norm(sm - ref_s) <= 1e-7 * np.linalg.norm(ref_s), (combo, prec)
 
 
 def test_autotune_picks_and_caches(tmp_path):
