@@ -83,8 +83,11 @@ def newton_dense(prob, s0=None, rtol=1e-13, max_newton=60):
         slope = float(np.sum(g * p))
 
         def delta_f(a):
-            return a * b + 0.5 * a * a * c + float(
-                np.sum(e * np.expm1(a * beta * p) - a * beta * prob.counts * p))
+            # a trial step too long for exp overflows to +inf, which the
+            # Armijo test rejects like any other increase of f
+            with np.errstate(over="ignore"):
+                return a * b + 0.5 * a * a * c + float(
+                    np.sum(e * np.expm1(a * beta * p) - a * beta * prob.counts * p))
 
         a = _armijo(delta_f, slope)
         if a is None:
@@ -204,8 +207,11 @@ def newton_krylov(prob, s0=None, rtol=1e-8, max_newton=100, max_cg=500,
         c = ops.dot(p_hat, ops.inv_lam * p_hat)
 
         def delta_f(a):
-            return a * b + 0.5 * a * a * c + float(
-                np.sum(e * np.expm1(a * beta * p) - a * beta * prob.counts * p))
+            # a trial step too long for exp overflows to +inf, which the
+            # Armijo test rejects like any other increase of f
+            with np.errstate(over="ignore"):
+                return a * b + 0.5 * a * a * c + float(
+                    np.sum(e * np.expm1(a * beta * p) - a * beta * prob.counts * p))
 
         a = _armijo(delta_f, slope) if slope < 0 else None
         if a is None:

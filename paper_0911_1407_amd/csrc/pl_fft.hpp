@@ -277,6 +277,27 @@ struct PaddedLen {
   static constexpr int value = (PAD && PL_ROW_PAD_SHIFT < 16) ? (N + (N >> PL_ROW_PAD_SHIFT) + 1) : N + 1;
 };
 
+// Permute the block's data through LDS: slot (q, m) of every thread (QA
+// groups of RA) goes to element POS_A(t, q, m), then slot (q, r) (QB groups
+// of RB) is read back from element POS_B(t, q, r).
+template <int RA, int QA, int RB, int QB, class MAP, typename T, typename PA, typename PB>
+__device__ __forceinline__ void lds_permute(cx<T>* v, cx<T>* lds, bool active, PA pos_a, PB pos_b) {
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int q = 0; q < QA; ++q)
+#pragma unroll
+      for (int m = 0; m < RA; ++m) lds[MAP::off(pos_a(q, m))] = v[q * RA + m];
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int q = 0; q < QB; ++q)
+#pragma unroll
+      for (int r = 0; r < RB; ++r) v[q * RB + r] = lds[MAP::off(pos_b(q, r))];
+  }
+}
+
 // Exchange between stage S-1 (outputs) and stage S (inputs).  Threads with
 // active == false take part in the barriers only.
 template <class PL, int S, class MAP, typename T>
@@ -294,20 +315,9 @@ __device__ __forceinline__ void stage_exchange(cx<T>* v, int t, cx<T>* lds, bool
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q * R + r] = tmp[in_pos<PL, S>(0, q, r)];
   } else {
-    __syncthreads();
-    if (active) {
-#pragma unroll
-      for (int q = 0; q < PL::W / RP; ++q)
-#pragma unroll
-        for (int m = 0; m < RP; ++m) lds[MAP::off(out_pos<PL, S - 1>(t, q, m))] = v[q * RP + m];
-    }
-    __syncthreads();
-    if (active) {
-#pragma unroll
-      for (int q = 0; q < PL::W / R; ++q)
-#pragma unroll
-        for (int r = 0; r < R; ++r) v[q * R + r] = lds[MAP::off(in_pos<PL, S>(t, q, r))];
-    }
+    lds_permute<RP, PL::W / RP, R, PL::W / R, MAP>(
+        v, lds, active, [t](int q, int m) { return out_pos<PL, S - 1>(t, q, m); },
+        [t](int q, int r) { return in_pos<PL, S>(t, q, r); });
   }
 }
 
@@ -348,20 +358,9 @@ __device__ __forceinline__ void last_to_first(cx<T>* v, int t, cx<T>* lds, bool 
 #pragma unroll
       for (int r = 0; r < R0; ++r) v[q * R0 + r] = tmp[in_pos<PL, 0>(0, q, r)];
   } else {
-    __syncthreads();
-    if (active) {
-#pragma unroll
-      for (int q = 0; q < PL::W / RL; ++q)
-#pragma unroll
-        for (int m = 0; m < RL; ++m) lds[MAP::off(out_pos<PL, PL::NS - 1>(t, q, m))] = v[q * RL + m];
-    }
-    __syncthreads();
-    if (active) {
-#pragma unroll
-      for (int q = 0; q < PL::W / R0; ++q)
-#pragma unroll
-        for (int r = 0; r < R0; ++r) v[q * R0 + r] = lds[MAP::off(in_pos<PL, 0>(t, q, r))];
-    }
+    lds_permute<RL, PL::W / RL, R0, PL::W / R0, MAP>(
+        v, lds, active, [t](int q, int m) { return out_pos<PL, PL::NS - 1>(t, q, m); },
+        [t](int q, int r) { return in_pos<PL, 0>(t, q, r); });
   }
 }
 

@@ -97,13 +97,19 @@ enum Scal {
   SC_COUNT = 32
 };
 
-// Inverse of the preconditioner M_k = 1/lambda_k + mean(d), the exact
-// diagonal of H in the Fourier basis.
+// Inverse of the preconditioner M_k = 1/lambda_k + dbar (dbar a constant
+// taken from the Hessian diagonal d), in the Krylov vectors' precision:
+// FP64 vectors take the IEEE quotient, FP32 vectors the hardware
+// reciprocal.  Every pass that applies M^-1 calls this one function, so M
+// is the same operator throughout a solve.
 template <typename T>
-__device__ __forceinline__ double precond_inv(const T* tab, int radial, const Grid& g, int kx, int ky,
-                                              int kz, long i, double dbar) {
-  double m = (double)inv_lam_at(tab, radial, g, kx, ky, kz, i) + dbar;
-  return m > 0.0 ? 1.0 / m : 0.0;
+__device__ __forceinline__ T precond_inv(T il, double dbar) {
+  const T m = il + (T)dbar;
+  if constexpr (sizeof(T) == 4) {
+    return m > 0.0f ? __builtin_amdgcn_rcpf(m) : 0.0f;
+  } else {
+    return m > 0.0 ? 1.0 / m : 0.0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -171,8 +177,8 @@ constexpr bool has_wide_variant(int n) { return n == 128 || n == 192 || n == 256
 // Threads beyond ColShape::THREADS (when a batched launch uses a larger
 // block) only take part in the barriers.
 template <typename T, int N, bool INV, int OP, int V = 0>
-__device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab, cx<T>* lds_all,
-                                         int block_linear) {
+__device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab,
+                                         cx<T>* lds_all, int block_linear) {
   using PL = Plan<N>;
   constexpr int B = ColShape<T, N, V>::B;
   constexpr int P = PL::P;
@@ -209,11 +215,11 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
         if (valid) {
           cx<T> po = pio[idx], rv = a.cg_r[idx];
           long mode = (long)kx * a.g.nyh + c;
-          double il = (double)inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode);
-          double mi = (il + dbar) > 0.0 ? 1.0 / (il + dbar) : 0.0;
-          pn = {(T)(mi * rv.x + beta * po.x), (T)(mi * rv.y + beta * po.y)};
+          const T il = inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode);
+          const T mi = precond_inv<T>(il, dbar), bt = (T)beta;
+          pn = {mi * rv.x + bt * po.x, mi * rv.y + bt * po.y};
           pio[idx] = pn;
-          acc[0] += hw * il * ((double)pn.x * pn.x + (double)pn.y * pn.y);
+          acc[0] += hw * (double)(il * (pn.x * pn.x + pn.y * pn.y));
         }
         v[q * R0 + r] = pn;
       }
@@ -283,18 +289,18 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
         int kx = out_pos<PL, PL::NS - 1>(t, q, m);
         long mode = (long)kx * a.g.nyh + c;
         if (valid) {
+          // vector arithmetic in the Krylov vectors' precision, sums in FP64
           cx<T> pv = pre_p[q * RL + m];
           T il = pre_il[q * RL + m];
           cx<T> x = v[q * RL + m];
-          double qx = (double)x.x + (double)il * pv.x, qy = (double)x.y + (double)il * pv.y;
+          const T qx = x.x + il * pv.x, qy = x.y + il * pv.y, al = (T)alpha;
           cx<T> rv = a.cg_r[mode], xv = a.cg_x[mode];
-          cx<T> rn = {(T)(rv.x - alpha * qx), (T)(rv.y - alpha * qy)};
+          cx<T> rn = {rv.x - al * qx, rv.y - al * qy};
           a.cg_r[mode] = rn;
-          a.cg_x[mode] = {(T)(xv.x + alpha * pv.x), (T)(xv.y + alpha * pv.y)};
-          double rr = (double)rn.x * rn.x + (double)rn.y * rn.y;
-          double mi = ((double)il + dbar) > 0.0 ? 1.0 / ((double)il + dbar) : 0.0;
-          acc[0] += hw * rr;
-          acc[1] += hw * mi * rr;
+          a.cg_x[mode] = {xv.x + al * pv.x, xv.y + al * pv.y};
+          const T rr = rn.x * rn.x + rn.y * rn.y;
+          acc[0] += hw * (double)rr;
+          acc[1] += hw * (double)(precond_inv<T>(il, dbar) * rr);
         }
       }
     block_reduce_store<2>(acc, a.partials, block_linear);
@@ -662,7 +668,7 @@ __device__ __forceinline__ void cg_init_body(const cx<double>* __restrict__ rhs,
     mi.decompose(i, kx, ky, kz);
     cx<double> b = rhs[i];
     cx<T> rv = {(T)(rhs_sign * b.x), (T)(rhs_sign * b.y)};
-    double minv = precond_inv(tab, radial, g, kx, ky, kz, i, dbar);
+    const double minv = (double)precond_inv<T>(inv_lam_at(tab, radial, g, kx, ky, kz, i), dbar);
     x[i] = {T(0), T(0)};
     r[i] = rv;
     p[i] = {T(0), T(0)};
@@ -689,37 +695,65 @@ enum FinKind { FIN_STORE = 0, FIN_CG_INIT = 1, FIN_CG_ALPHA = 2, FIN_CG_BETA = 3
 // Sum partials[nb][K] in a fixed order; then scalar bookkeeping.
 // kind FIN_CG_ALPHA: p^H H p = scale2 * sum(partials2[nb2]) (prior part from
 // the first pass) + scale * sum(partials[nb][K], k = 0) (diagonal part).
+// Sum K interleaved per-block partials (src[i * K + k], i < n) over the
+// block: every thread keeps 4 K loads in flight per round over a fixed
+// partition, then a fixed-order wave and cross-wave reduction, so the result
+// is the same on every run.  Returns the sums in out[] (every thread).
+template <int NT, int K>
+__device__ __forceinline__ void fin_sums(const double* __restrict__ src, int n, double* out) {
+  __shared__ double sh[K][NT / 64];
+  double acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+  for (int base = 0; base < n; base += 4 * NT) {
+    double x[4][K];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = base + u * NT + (int)threadIdx.x;
+#pragma unroll
+      for (int k = 0; k < K; ++k) x[u][k] = i < n ? src[(size_t)i * K + k] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] += (x[0][k] + x[1][k]) + (x[2][k] + x[3][k]);
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_down(acc[k], off, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) sh[k][threadIdx.x >> 6] = acc[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double t = 0.0;
+    for (int w = 0; w < NT / 64; ++w) t += sh[k][w];
+    out[k] = t;
+  }
+}
+
+// Device-side reduction of per-block partials and the scalar bookkeeping
+// of the Krylov / Newton loops (kind: FinKind).  One block of NT threads.
+template <int NT>
 __device__ __forceinline__ void finalize_body(const double* __restrict__ partials, int nb, int K, int kind, int dst,
                                               double scale, double* __restrict__ scal, double aux,
                                               const double* __restrict__ partials2, int nb2, double scale2) {
-  __shared__ double sh[8][256];
-  for (int k = 0; k < K; ++k) {
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < nb; i += 256) acc += partials[(size_t)i * K + k];
-    sh[k][threadIdx.x] = acc;
-  }
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s)
-      for (int k = 0; k < K; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
-    __syncthreads();
+  double v[8];
+  switch (K) {
+    case 1: fin_sums<NT, 1>(partials, nb, v); break;
+    case 2: fin_sums<NT, 2>(partials, nb, v); break;
+    case 3: fin_sums<NT, 3>(partials, nb, v); break;
+    default: fin_sums<NT, 4>(partials, nb, v); break;
   }
   double extra = 0.0;
   if (partials2) {
-    __syncthreads();
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < nb2; i += 256) acc += partials2[i];
-    sh[7][threadIdx.x] = acc;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-      if (threadIdx.x < st) sh[7][threadIdx.x] += sh[7][threadIdx.x + st];
-      __syncthreads();
-    }
-    extra = sh[7][0] * scale2;
+    double e[1];
+    fin_sums<NT, 1>(partials2, nb2, e);
+    extra = e[0] * scale2;
   }
   if (threadIdx.x != 0) return;
-  double v[8];
-  for (int k = 0; k < K; ++k) v[k] = sh[k][0] * scale;
+  for (int k = 0; k < K; ++k) v[k] *= scale;
   switch (kind) {
     case FIN_STORE:
       for (int k = 0; k < K; ++k) scal[dst + k] = v[k];
@@ -758,11 +792,13 @@ __device__ __forceinline__ void finalize_body(const double* __restrict__ partial
   }
 }
 
-__global__ void __launch_bounds__(256) finalize_kernel(const double* __restrict__ partials, int nb, int K,
-                                                       int kind, int dst, double scale, double* __restrict__ scal,
-                                                       double aux, const double* __restrict__ partials2, int nb2,
-                                                       double scale2) {
-  finalize_body(partials, nb, K, kind, dst, scale, scal, aux, partials2, nb2, scale2);
+constexpr int FIN_THREADS = 1024;
+__global__ void __launch_bounds__(FIN_THREADS) finalize_kernel(const double* __restrict__ partials, int nb, int K,
+                                                               int kind, int dst, double scale,
+                                                               double* __restrict__ scal, double aux,
+                                                               const double* __restrict__ partials2, int nb2,
+                                                               double scale2) {
+  finalize_body<FIN_THREADS>(partials, nb, K, kind, dst, scale, scal, aux, partials2, nb2, scale2);
 }
 
 __global__ void set_scalar_kernel(double* scal, int idx, double value) {
@@ -1019,6 +1055,20 @@ __global__ void __launch_bounds__(RED_THREADS) radial_check_kernel(const double*
     if (!(fabs(r - v) <= 8.0 * 2.220446049250313e-16 * fabs(v))) bad = 1;
   }
   if (bad) atomicOr(mismatch, 1);
+}
+
+// Timing operands for the autotuner: x[i] in [lo, lo + span) from an
+// integer hash of (i, seed), so timed passes stream realistic, non-zero data.
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS) fill_hash_kernel(T* __restrict__ x, long n, unsigned seed, double lo,
+                                                                double span) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    unsigned long long h = (unsigned long long)i * 0x9E3779B97F4A7C15ull + seed;
+    h ^= h >> 31;
+    h *= 0xBF58476D1CE4E5B9ull;
+    h ^= h >> 29;
+    x[i] = (T)(lo + span * (double)(h >> 11) * (1.0 / 9007199254740992.0));
+  }
 }
 
 __global__ void __launch_bounds__(RED_THREADS) to_f32_kernel(const double* __restrict__ x, float* __restrict__ y, long n) {

@@ -254,7 +254,8 @@ hipError_t run_row(pl_plan* p, int op, const RowArgs<T>& a, int* nb) {
 hipError_t finalize(pl_plan* p, int nb, int K, int kind, int dst, double scale, double aux = 0.0,
                     const double* partials = nullptr, const double* partials2 = nullptr, int nb2 = 0,
                     double scale2 = 0.0) {
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, p->stream, partials ? partials : p->partials, nb, K,
+  if (K < 1 || K > 4) return hipErrorInvalidValue;  // finalize_body sums at most 4 partials per block
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(FIN_THREADS), 0, p->stream, partials ? partials : p->partials, nb, K,
                      kind, dst, scale, p->scal, aux, partials2, nb2, scale2);
   return hipGetLastError();
 }
@@ -984,12 +985,20 @@ std::string arch_name() {
 // of `reps`, with the plan's current variants.  Runs on zeroed vectors with
 // zero step lengths, so nothing is left in a meaningful state.
 template <typename T>
+int fill_hash(pl_plan* p, T* x, long n, unsigned seed, double lo = -1.0, double span = 2.0) {
+  hipLaunchKernelGGL((fill_hash_kernel<T>), dim3(grid_blocks(n)), dim3(RED_THREADS), 0, p->stream, x, n, seed, lo,
+                     span);
+  HIPCHK(p, hipGetLastError());
+  return PL_OK;
+}
+
+template <typename T>
 int time_cg_step(pl_plan* p, int reps, float* ms) {
   cx<T>*x = View<T>::x(p), *r = View<T>::r(p), *pp = View<T>::pv(p), *t = View<T>::t(p);
-  HIPCHK(p, hipMemsetAsync(x, 0, sizeof(cx<T>) * p->Nh, p->stream));
-  HIPCHK(p, hipMemsetAsync(r, 0, sizeof(cx<T>) * p->Nh, p->stream));
-  HIPCHK(p, hipMemsetAsync(pp, 0, sizeof(cx<T>) * p->Nh, p->stream));
-  HIPCHK(p, hipMemsetAsync(p->scal, 0, sizeof(double) * SC_COUNT, p->stream));
+  if (int frc = fill_hash<T>(p, (T*)x, 2 * p->Nh, 1)) return frc;
+  if (int frc = fill_hash<T>(p, (T*)r, 2 * p->Nh, 2)) return frc;
+  if (int frc = fill_hash<T>(p, (T*)pp, 2 * p->Nh, 3)) return frc;
+  HIPCHK(p, hipMemsetAsync(p->scal, 0, sizeof(double) * SC_COUNT, p->stream));  // alpha = beta = 0
   auto step = [&]() -> hipError_t {
     ColArgs<T> c1 = col_args<T>(p, 0, pp, t);
     c1.cg_r = r;
@@ -1035,7 +1044,7 @@ int time_cg_step(pl_plan* p, int reps, float* ms) {
 // pl_hessvec_hat), average of `reps`.
 template <typename T>
 int time_hvp(pl_plan* p, int reps, float* ms) {
-  HIPCHK(p, hipMemsetAsync(View<T>::x(p), 0, sizeof(cx<T>) * p->Nh, p->stream));
+  if (int frc = fill_hash<T>(p, (T*)View<T>::x(p), 2 * p->Nh, 4)) return frc;
   hipEvent_t e0, e1;
   HIPCHK(p, hipEventCreate(&e0));
   HIPCHK(p, hipEventCreate(&e1));
@@ -1132,10 +1141,9 @@ extern "C" int pl_plan_autotune(pl_plan* p, const char* cache_path) {
       std::fclose(f);
     }
   }
-  // a valid Hessian diagonal for the timing runs: linearise at s = mu
-  hipLaunchKernelGGL(linearize_kernel, dim3(grid_blocks(p->N)), dim3(RED_THREADS), 0, p->stream, p->prob.w,
-                     p->prob.w, p->prob.nbar, 0.0, p->e, p->d, p->N);  // beta = 0: d = 0, e = nbar w
-  HIPCHK(p, hipGetLastError());
+  // a positive Hessian diagonal for the timing runs
+  rc = fill_hash<double>(p, p->d, p->N, 5, 0.0, 1.0);
+  if (rc) return rc;
   p->d_valid = true;
   p->d32_valid = false;
   // keyed by whether the problem's spectrum allows the radial table
