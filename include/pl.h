@@ -185,9 +185,13 @@ const char* pl_last_error(const pl_plan* plan);
    The x passes that apply 1/lambda can also read it from the radial shell
    table (when pl_plan_prior_is_radial) or from the per-mode table: the
    shell table saves a streaming read, the per-mode table avoids a
-   scattered lookup.  Times the solver's fused CG step (five passes) per
-   combination of the Krylov-carrying x variant, the y and z variants and
-   the Krylov passes' table, then the isolated operator (pl_hessvec_hat) per
+   scattered lookup.  Operands that a pass reads once (Krylov vectors, the
+   Hessian diagonal, the per-mode table) can be loaded non-temporally so
+   that the pass-to-pass intermediate stays in the memory-side cache, which
+   pays when that intermediate fits there.  Times the solver's fused CG step
+   (five passes) per combination of the Krylov-carrying x variant, the y and
+   z variants, the Krylov passes' table and the load policy, then the
+   isolated operator (pl_hessvec_hat) per
    combination of its own x variant and table, on the plan's workspace (after
    pl_set_problem; it overwrites the cached Hessian diagonal and the solver's
    Krylov vectors), and keeps the fastest, per precision.  Every choice
@@ -199,10 +203,11 @@ int pl_plan_autotune(pl_plan* plan, const char* cache_path);
 /* Number of schedule choices per precision.  In order: x variant of the
    Krylov-carrying passes, y variant, z variant, x variant of the operator's
    passes, table of the Krylov passes (1 shell, 0 per mode), table of the
-   operator's passes.  Variants: 0 default, 1 wide (a length without a wide
-   variant runs the default); a shell-table choice runs the per-mode table
-   when the spectrum is not radial. */
-#define PL_NUM_VARIANTS 6
+   operator's passes, streaming loads (1 non-temporal, 0 default policy).
+   Variants: 0 default, 1 wide (a length without a wide variant runs the
+   default); a shell-table choice runs the per-mode table when the spectrum
+   is not radial. */
+#define PL_NUM_VARIANTS 7
 /* Current choices: out = the PL_NUM_VARIANTS choices for FP64, then FP32. */
 int pl_plan_get_variants(const pl_plan* plan, int32_t out[2 * PL_NUM_VARIANTS]);
 /* Force the choices (same order); each entry 0 or 1. */

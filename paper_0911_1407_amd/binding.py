@@ -223,19 +223,19 @@ def pl_plan_prior_is_radial(h):
     return bool(out.value)
 
 
-VARIANT_SLOTS = ("x_krylov", "y", "z", "x_operator", "table_krylov", "table_operator")
+VARIANT_SLOTS = ("x_krylov", "y", "z", "x_operator", "table_krylov", "table_operator", "stream_nt")
 
 
 def pl_plan_get_variants(h):
     """{precision: (x Krylov passes, y, z, x operator passes, table of the
-    Krylov passes, table of the operator passes)}"""
+    Krylov passes, table of the operator passes, streaming loads)}"""
     k = len(VARIANT_SLOTS)
     out = (ctypes.c_int32 * (2 * k))()
     _check(h, load().pl_plan_get_variants(h, out))
     return {"fp64": tuple(out[0:k]), "fp32": tuple(out[k:2 * k])}
 
 
-def pl_plan_set_variants(h, fp64=(0, 0, 0, 0, 0, 0), fp32=(0, 0, 0, 0, 1, 1)):
+def pl_plan_set_variants(h, fp64=(0, 0, 0, 0, 0, 0, 0), fp32=(0, 0, 0, 0, 1, 1, 0)):
     """Per precision, the choices in VARIANT_SLOTS order."""
     k = len(VARIANT_SLOTS)
     vals = tuple(int(x) for x in fp64) + tuple(int(x) for x in fp32)

@@ -27,7 +27,7 @@ struct Status {
 };
 
 // Schedule choices per precision, in the order of pl_plan_get_variants.
-enum VarSlot { V_XCG = 0, V_Y, V_Z, V_XOP, V_TAB_CG, V_TAB_OP, V_COUNT };
+enum VarSlot { V_XCG = 0, V_Y, V_Z, V_XOP, V_TAB_CG, V_TAB_OP, V_NT, V_COUNT };
 static_assert(V_COUNT == PL_NUM_VARIANTS, "schedule slots");
 
 }  // namespace
@@ -70,7 +70,7 @@ struct pl_plan {
   bool d32_valid = false;  // d32 mirrors d
   // schedule choices per precision [FP64/FP32] (see VarSlot); the table
   // choices apply only when the radial table is valid
-  int var[2][V_COUNT] = {{0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 1, 1}};
+  int var[2][V_COUNT] = {{0, 0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 1, 1, 0}};
   std::string err;
 };
 
@@ -201,6 +201,7 @@ ColArgs<T> col_args(pl_plan* p, int axis, const cx<T>* in, cx<T>* out) {
   a.radial = p->radial;
   a.partials = p->partials;
   a.out_scale = T(1);
+  a.nt = p->var[sizeof(T) == 4 ? 1 : 0][V_NT];
   const long h = p->g.h;
   if (axis == 0) {  // x: columns = (ky, kz) pairs
     a.ncols = (int)(p->n[1] * h);
@@ -242,6 +243,7 @@ RowArgs<T> row_args(pl_plan* p) {
   a.nbar = p->prob.nbar;
   a.beta = p->prob.beta;
   a.partials = p->partials;
+  a.nt = p->var[sizeof(T) == 4 ? 1 : 0][V_NT];
   return a;
 }
 
@@ -1094,9 +1096,9 @@ int tune_precision(pl_plan* p, const std::string& key, std::vector<std::string>&
     if (line.compare(0, key.size() + 1, key + " ") == 0) {
       int v[V_COUNT];
       float t_cg, t_hvp;
-      if (std::sscanf(line.c_str() + key.size(), "%d %d %d %d %d %d %f %f", &v[0], &v[1], &v[2], &v[3], &v[4],
-                      &v[5], &t_cg, &t_hvp) == V_COUNT + 2 &&
-          ((v[0] | v[1] | v[2] | v[3] | v[4] | v[5]) & ~1) == 0) {
+      if (std::sscanf(line.c_str() + key.size(), "%d %d %d %d %d %d %d %f %f", &v[0], &v[1], &v[2], &v[3], &v[4],
+                      &v[5], &v[6], &t_cg, &t_hvp) == V_COUNT + 2 &&
+          ((v[0] | v[1] | v[2] | v[3] | v[4] | v[5] | v[6]) & ~1) == 0) {
         for (int i = 0; i < V_COUNT; ++i) p->var[pi][i] = v[i];
         return PL_OK;
       }
@@ -1107,9 +1109,9 @@ int tune_precision(pl_plan* p, const std::string& key, std::vector<std::string>&
   const int reps = p->N >= (1L << 24) ? 5 : 20;
   // the solver's CG step: x passes carrying the Krylov updates, y, z, and
   // the table those x passes read
-  const int cg_slots[4] = {V_XCG, V_Y, V_Z, V_TAB_CG}, cg_max[4] = {mx, my, mr, mt};
+  const int cg_slots[5] = {V_XCG, V_Y, V_Z, V_TAB_CG, V_NT}, cg_max[5] = {mx, my, mr, mt, 1};
   float best_cg = 0.f, best_hvp = 0.f;
-  int rc = tune_slots(p, pi, cg_slots, cg_max, 4, [&](float* ms) { return time_cg_step<T>(p, reps, ms); }, &best_cg);
+  int rc = tune_slots(p, pi, cg_slots, cg_max, 5, [&](float* ms) { return time_cg_step<T>(p, reps, ms); }, &best_cg);
   if (rc) return rc;
   // the isolated operator's x passes and their table
   const int op_slots[2] = {V_XOP, V_TAB_OP}, op_max[2] = {mx, mt};
@@ -1117,8 +1119,8 @@ int tune_precision(pl_plan* p, const std::string& key, std::vector<std::string>&
   if (rc) return rc;
   const int* v = p->var[pi];
   char buf[256];
-  std::snprintf(buf, sizeof(buf), "%s %d %d %d %d %d %d %.4f %.4f", key.c_str(), v[0], v[1], v[2], v[3], v[4], v[5],
-                (double)best_cg, (double)best_hvp);
+  std::snprintf(buf, sizeof(buf), "%s %d %d %d %d %d %d %d %.4f %.4f", key.c_str(), v[0], v[1], v[2], v[3], v[4],
+                v[5], v[6], (double)best_cg, (double)best_hvp);
   cache_lines.push_back(buf);
   *added = true;
   return PL_OK;
@@ -1163,7 +1165,7 @@ extern "C" int pl_plan_autotune(pl_plan* p, const char* cache_path) {
     if (FILE* f = std::fopen(cache_path, "w")) {
       std::fprintf(f,
                    "# pl_plan_autotune cache: arch grid table precision x(Krylov passes) y z x(operator passes) "
-                   "table(Krylov) table(operator) ms/CG-step ms/HVP\n");
+                   "table(Krylov) table(operator) streaming-loads ms/CG-step ms/HVP\n");
       for (const std::string& l : lines) std::fprintf(f, "%s\n", l.c_str());
       std::fclose(f);
     }
