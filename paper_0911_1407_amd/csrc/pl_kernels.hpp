@@ -22,13 +22,15 @@ namespace pl {
 
 constexpr int RED_THREADS = 256;
 
-// Streaming loads: with nt set, operands read once per pass and not again
-// until the next Krylov step (r, p, x, the Hessian diagonal, the per-mode
-// 1/lambda table) are loaded non-temporally, so that they do not displace
+// Streaming loads: operands read once per pass and not again until the next
+// Krylov step can be loaded non-temporally, so that they do not displace
 // the pass-to-pass intermediate (each pass's input and output, default
-// policy) from the memory-side cache.  Whether that pays depends on the
-// working set against the cache, so it is a per-plan schedule choice.
+// policy) from the memory-side cache.  The nt field of the pass arguments
+// holds two bits: NT_VEC for the Krylov vectors r, p, x and the per-mode
+// 1/lambda table, NT_DIAG for the Hessian diagonal.  Which pays depends on
+// the working set against the cache, so it is a per-plan schedule choice.
 // Stores keep the default policy.
+enum { NT_VEC = 1, NT_DIAG = 2 };
 template <typename T>
 __device__ __forceinline__ T ld_stream(const T* p, int nt) {
   return nt ? __builtin_nontemporal_load(p) : *p;
@@ -167,7 +169,7 @@ struct ColArgs {
   cx<T>* cg_x;
   const double* scal;  // device scalars (SC_*)
   const double* skip;  // if non-null and *skip != 0 the launch does nothing
-  int nt;              // streaming operands loaded non-temporally (ld_stream)
+  int nt;              // NT_VEC | NT_DIAG: operands loaded non-temporally (ld_stream)
 };
 
 // Column tile width B: 256 threads per block where possible, at most 64 KB
@@ -235,9 +237,9 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
         long idx = base_off + (long)kx * a.row_stride;
         cx<T> pn = {T(0), T(0)};
         if (valid) {
-          cx<T> po = ld_stream(pio + idx, a.nt), rv = ld_stream(a.cg_r + idx, a.nt);
+          cx<T> po = ld_stream(pio + idx, a.nt & NT_VEC), rv = ld_stream(a.cg_r + idx, a.nt & NT_VEC);
           long mode = (long)kx * a.g.nyh + c;
-          const T il = inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt);
+          const T il = inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_VEC);
           const T mi = precond_inv<T>(il, dbar), bt = (T)beta;
           pn = {mi * rv.x + bt * po.x, mi * rv.y + bt * po.y};
           pio[idx] = pn;
@@ -276,7 +278,7 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
         long mode = (long)kx * a.g.nyh + c;
         cx<T> x = v[q * RL + m];
         if (mode == 0) x.x -= (T)a.k0_shift;
-        T il = valid ? inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt) : T(0);
+        T il = valid ? inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_VEC) : T(0);
         if (valid) acc[0] += herm_w(kz, a.g) * (double)il * ((double)x.x * x.x + (double)x.y * x.y);
         v[q * RL + m] = {x.x * il, x.y * il};
       }
@@ -297,8 +299,8 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
       for (int m = 0; m < RL; ++m) {
         int kx = out_pos<PL, PL::NS - 1>(t, q, m);
         long mode = (long)kx * a.g.nyh + c;
-        pre_p[q * RL + m] = valid ? ld_stream(a.base + mode, a.nt) : cx<T>{T(0), T(0)};
-        pre_il[q * RL + m] = valid ? inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt) : T(0);
+        pre_p[q * RL + m] = valid ? ld_stream(a.base + mode, a.nt & NT_VEC) : cx<T>{T(0), T(0)};
+        pre_il[q * RL + m] = valid ? inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_VEC) : T(0);
       }
     fft_thread<PL, false, MAP>(v, t, lds, a.tw, active);
     const double hw = herm_w(kz, a.g);
@@ -316,7 +318,7 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
           T il = pre_il[q * RL + m];
           cx<T> x = v[q * RL + m];
           const T qx = x.x + il * pv.x, qy = x.y + il * pv.y, al = (T)alpha;
-          cx<T> rv = ld_stream(a.cg_r + mode, a.nt), xv = ld_stream(a.cg_x + mode, a.nt);
+          cx<T> rv = ld_stream(a.cg_r + mode, a.nt & NT_VEC), xv = ld_stream(a.cg_x + mode, a.nt & NT_VEC);
           cx<T> rn = {rv.x - al * qx, rv.y - al * qy};
           a.cg_r[mode] = rn;
           a.cg_x[mode] = {xv.x + al * pv.x, xv.y + al * pv.y};
@@ -339,8 +341,8 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
       for (int m = 0; m < RL; ++m) {
         int kx = out_pos<PL, PL::NS - 1>(t, q, m);
         long mode = (long)kx * a.g.nyh + c;
-        pre_b[q * RL + m] = valid ? ld_stream(a.base + mode, a.nt) : cx<T>{T(0), T(0)};
-        pre_il[q * RL + m] = valid ? inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt) : T(0);
+        pre_b[q * RL + m] = valid ? ld_stream(a.base + mode, a.nt & NT_VEC) : cx<T>{T(0), T(0)};
+        pre_il[q * RL + m] = valid ? inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_VEC) : T(0);
       }
     fft_thread<PL, false, MAP>(v, t, lds, a.tw, active);
     double acc[3] = {0.0, 0.0, 0.0};
@@ -439,7 +441,7 @@ struct RowArgs {
   double* d_out;
   double* partials;
   const double* skip;  // if non-null and *skip != 0 the launch does nothing
-  int nt;              // streaming operands loaded non-temporally (ld_stream)
+  int nt;              // NT_VEC | NT_DIAG: operands loaded non-temporally (ld_stream)
 };
 
 template <int N, int V = 0>
@@ -519,11 +521,11 @@ __device__ __forceinline__ void row_body(const RowArgs<T>& a, int ublock, cx<T>*
       for (int m = 0; m < RL; ++m) {
         int e = out_pos<PL, PL::NS - 1>(t, q, m);
         if constexpr (sizeof(T) == 8) {
-          pre_dA[q * RL + m] = valid ? (T)ld_stream(a.d + rowA * N + e, a.nt) : T(0);
-          pre_dB[q * RL + m] = valid ? (T)ld_stream(a.d + rowB * N + e, a.nt) : T(0);
+          pre_dA[q * RL + m] = valid ? (T)ld_stream(a.d + rowA * N + e, a.nt & NT_DIAG) : T(0);
+          pre_dB[q * RL + m] = valid ? (T)ld_stream(a.d + rowB * N + e, a.nt & NT_DIAG) : T(0);
         } else {
-          pre_dA[q * RL + m] = valid ? ld_stream(a.d32 + rowA * N + e, a.nt) : T(0);
-          pre_dB[q * RL + m] = valid ? ld_stream(a.d32 + rowB * N + e, a.nt) : T(0);
+          pre_dA[q * RL + m] = valid ? ld_stream(a.d32 + rowA * N + e, a.nt & NT_DIAG) : T(0);
+          pre_dB[q * RL + m] = valid ? ld_stream(a.d32 + rowB * N + e, a.nt & NT_DIAG) : T(0);
         }
       }
   }
