@@ -38,6 +38,37 @@ TUNE_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_091
                           "tune_cache_gfx950.txt")
 
 
+# Memory-side traffic of one FP64 spectral HVP on the 256^3 selection
+# workload: FETCH_SIZE and WRITE_SIZE (rocprofv3 --pmc) of the five passes,
+# each scaled by what the counter reads for a 1 GiB device copy in the same
+# program.  It holds for the kernel sources it was measured on (sha256 of
+# paper_0911_1407_amd/csrc/*.hip and *.hpp, sorted by path, first 16 hex
+# digits) and the FP64 schedule it ran; otherwise the bench reports null.
+MEASURED_TRAFFIC = {
+    "sel256": {"src_sha": "7f70dbe12a1ebf14", "fp64_schedule": [0, 0, 0, 0, 0, 0, 1],
+               "bytes_per_hvp": 1703245591},
+}
+
+
+def kernel_sources_sha():
+    import glob
+    import hashlib
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_0911_1407_amd", "csrc")
+    paths = sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp")))
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, fp64_schedule):
+    m = MEASURED_TRAFFIC.get(workload)
+    if m is None or m["src_sha"] != kernel_sources_sha() or list(m["fp64_schedule"]) != list(fp64_schedule):
+        return None
+    return m["bytes_per_hvp"]
+
+
 def hvp_bytes(n, p, spectral=True):
     """Algorithmic HBM bytes of one Hessian-vector product.
 
@@ -272,7 +303,9 @@ def main():
                                f"FP64 Newton-Krylov MAP to rtol {rtol:g}",
                    "grid": list(n), "rtol": rtol, "tile_variants": variants},
         "roofline": {"bound": "hbm", "achieved": gbs64, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs64 / HBM_PEAK_GBS, "traffic": None,
+                     "frac": gbs64 / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(args.workload, variants["fp64"]) if args.n is None else None,
+                     "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                      "kernel": "spectral HVP (5 passes), FP64", "bytes_per_launch": b64,
                      "ms_per_launch": ms64},
         "hvp_fp32": {"achieved": gbs32, "frac": gbs32 / HBM_PEAK_GBS, "bytes_per_launch": b32,
