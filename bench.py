@@ -13,7 +13,8 @@ products performed in the timed steps divided by their wall time.
 
 Also reported (not part of `value`):
   roofline      -- the in-solver spectral HVP (5 passes) timed in isolation
-                   with HIP events on the plan's stream, against 8 TB/s
+                   with HIP events on the plan's stream (median of 200
+                   calls after 20 warm-up calls), against 8 TB/s
   mixed         -- the same solve with FP32 FFTs/HVPs and FP64 reductions
   adjoint       -- adjoint solve of L = sum (s* - s_true)^2 at the MAP
   batched       -- 64 independent reconstructions, n in {32, 48, 64, 96},
@@ -89,7 +90,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--hvp-reps", type=int, default=50)
+    ap.add_argument("--hvp-reps", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--only-hvp", action="store_true", help="profiling aid: only the isolated HVP loop")
@@ -137,17 +138,19 @@ def main():
     stream = torch.cuda.current_stream(dev)
 
     def time_hvp(vin, vout, reps):
-        for _ in range(5):
+        # 20 warm-up calls, then `reps` back-to-back calls, each bracketed by
+        # HIP events on the plan's stream; the median per-call time
+        for _ in range(20):
             plan.hessvec_hat(vin, out=vout)
         torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        ev[0].record(stream)
+        for i in range(reps):
             plan.hessvec_hat(vin, out=vout)
-        e1.record(stream)
+            ev[i + 1].record(stream)
         torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps  # ms per HVP
+        per_call = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(reps))
+        return float(np.median(per_call))  # ms per HVP
 
     ms64 = time_hvp(v_hat64, hv64, args.hvp_reps)
     ms32 = time_hvp(v_hat32, hv32, args.hvp_reps)

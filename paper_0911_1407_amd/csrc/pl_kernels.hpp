@@ -826,6 +826,25 @@ __global__ void __launch_bounds__(FIN_THREADS) finalize_kernel(const double* __r
   finalize_body<FIN_THREADS>(partials, nb, K, kind, dst, scale, scal, aux, partials2, nb2, scale2);
 }
 
+// r = b - q on the half spectrum, with per-block partial sums of the
+// Hermitian-weighted |r|^2 (N times the squared norm, by Parseval).
+__global__ void __launch_bounds__(RED_THREADS) resid_hat_kernel(const cx<double>* __restrict__ b,
+                                                                const cx<double>* __restrict__ q,
+                                                                cx<double>* __restrict__ r, Grid g, long nh,
+                                                                double* __restrict__ partials) {
+  ModeIter mi{g};
+  double acc[1] = {0.0};
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nh; i += (long)gridDim.x * blockDim.x) {
+    int kx, ky, kz;
+    mi.decompose(i, kx, ky, kz);
+    const cx<double> bv = b[i], qv = q[i];
+    const cx<double> v = {bv.x - qv.x, bv.y - qv.y};
+    r[i] = v;
+    acc[0] += herm_w(kz, g) * (v.x * v.x + v.y * v.y);
+  }
+  block_reduce_store<1>(acc, partials, blockIdx.x);
+}
+
 __global__ void set_scalar_kernel(double* scal, int idx, double value) {
   if (threadIdx.x == 0 && blockIdx.x == 0) scal[idx] = value;
 }
