@@ -176,6 +176,37 @@ int pl_solve_adjoint(pl_plan* plan, const double* s_star, const double* dL_ds, d
                      double* dL_dA, double* dL_dbeta, double* dL_dnbar, double* dL_dN, double* dL_dw,
                      const pl_solve_opts* opts, pl_solve_info* info);
 
+/* ---------------------------------------------------------------------------
+ * The paper's comparison estimators and quality measures (section 4.1).
+ * ------------------------------------------------------------------------- */
+
+/* LSQ-Wiener filter (section 4.1.1, the LSQ equation, unit bias): with the
+   mask W = diag(w), the Poisson noise covariance diag(w / nbar) and the
+   observed overdensity N / nbar - w, the filtered overdensity solves
+     (S^-1 + diag(nbar w)) delta = N - nbar w,
+   S being the problem's prior covariance (amp * pk, 1 / inv_p0 at k = 0).
+   delta_out (device, N): the LSQ overdensity.  opts: rtol on the spectral
+   residual, max_cg, precision (PL_MIXED: FP32 PCG sweeps refined against the
+   FP64 residual); max_newton, eta_max and ls_c1 are unused.  Uses the
+   problem of the last pl_set_problem; overwrites the cached Hessian
+   diagonal (a later pl_hessvec needs s).  PL_ERR_NOT_CONVERGED if max_cg
+   ends the solve above rtol (delta_out and info are still written).
+   Synchronises the stream. */
+int pl_lsq_solve(pl_plan* plan, double* delta_out, const pl_solve_opts* opts, pl_solve_info* info);
+
+/* Inverse-weighted overdensity (section 4.1.1, the IW definitions):
+   delta_out[i] = N_i / (w_i nbar) - 1 where w_i > 0, and 0 (the mean)
+   where w_i = 0.  delta_out: device, N.  Asynchronous on the stream. */
+int pl_inverse_weight(pl_plan* plan, double* delta_out);
+
+/* Correlation coefficient r = sum ref rec / (|ref| |rec|) and Euclidean
+   distance D = sqrt(sum (rec - ref)^2 / N) between two real fields on the
+   plan's grid (section 4.1.2).  rec, ref: device, N; r_out, d_euc_out:
+   host, nullable (r = 0 when either field is zero).  Sums in FP64 in a
+   fixed order.  Needs a workspace, not a problem.  Synchronises the
+   stream. */
+int pl_compare_fields(pl_plan* plan, const double* rec, const double* ref, double* r_out, double* d_euc_out);
+
 /* Message for the last failing call on plan (never NULL). */
 const char* pl_last_error(const pl_plan* plan);
 

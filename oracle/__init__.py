@@ -28,6 +28,10 @@ What it computes (every function cites the passage it follows):
                    loss of the MAP field with respect to the model parameters.
 * ``lambertw``  -- the principal branch of the Lambert W function by Halley's
                    iteration (Corless et al. 1996), for closed-form pins.
+* ``wiener``    -- the paper's comparison estimators (section 4.1.1: inverse
+                   weighting and the LSQ-Wiener filter) and quality measures
+                   (section 4.1.2: correlation coefficient, Euclidean
+                   distance).
 * ``closed_form`` -- closed-form MAP fields for special cases (white prior,
                    uniform data, zero completeness) and their derivatives.
 

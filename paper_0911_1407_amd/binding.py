@@ -33,7 +33,8 @@ EXPORTED = ("pl_default_opts", "pl_plan_create", "pl_plan_set_workspace", "pl_pl
             "pl_hessvec_hat", "pl_hessvec_hat_f32", "pl_newton_krylov_solve", "pl_solve_adjoint",
             "pl_last_error", "pl_batch_create", "pl_batch_set_workspace", "pl_batch_set_problem",
             "pl_batch_solve", "pl_batch_destroy", "pl_batch_last_error", "pl_plan_autotune",
-            "pl_plan_get_variants", "pl_plan_set_variants", "pl_plan_prior_is_radial")
+            "pl_plan_get_variants", "pl_plan_set_variants", "pl_plan_prior_is_radial", "pl_lsq_solve",
+            "pl_inverse_weight", "pl_compare_fields")
 
 BATCH_LENGTHS = (32, 48, 64, 96, 128)
 
@@ -107,6 +108,9 @@ def load(path=LIB_PATH):
     lib.pl_plan_autotune.argtypes = [vp, ctypes.c_char_p]
     lib.pl_plan_get_variants.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     lib.pl_plan_prior_is_radial.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.pl_lsq_solve.argtypes = [vp, vp, ctypes.POINTER(pl_solve_opts), ctypes.POINTER(pl_solve_info)]
+    lib.pl_inverse_weight.argtypes = [vp, vp]
+    lib.pl_compare_fields.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.pl_plan_set_variants.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     lib.pl_batch_last_error.argtypes = [vp]
     lib.pl_batch_last_error.restype = ctypes.c_char_p
@@ -215,6 +219,24 @@ def pl_last_error(h):
 
 def pl_plan_autotune(h, cache_path=None):
     return _check(h, load().pl_plan_autotune(h, cache_path.encode() if cache_path else None))
+
+
+def pl_lsq_solve(h, delta_out, opts=None):
+    info = pl_solve_info()
+    rc = load().pl_lsq_solve(h, _ptr(delta_out), ctypes.byref(opts) if opts else None, ctypes.byref(info))
+    _check(h, rc, allow=(PL_ERR_NOT_CONVERGED,))
+    return info
+
+
+def pl_inverse_weight(h, delta_out):
+    return _check(h, load().pl_inverse_weight(h, _ptr(delta_out)))
+
+
+def pl_compare_fields(h, rec, ref):
+    r = ctypes.c_double(0.0)
+    d = ctypes.c_double(0.0)
+    _check(h, load().pl_compare_fields(h, _ptr(rec), _ptr(ref), ctypes.byref(r), ctypes.byref(d)))
+    return r.value, d.value
 
 
 def pl_plan_prior_is_radial(h):
@@ -388,6 +410,22 @@ class Plan:
         dw = self.torch.empty_like(s_star) if want_fields else None
         scal, info = pl_solve_adjoint(self.h, s_star, dL_ds, lam, dN, dw, make_opts(**kw))
         return dict(scal, N=dN, w=dw, lam=lam), info.as_dict()
+
+    def lsq(self, **kw):
+        """LSQ-Wiener overdensity of the current problem: (delta, info)."""
+        delta = self.torch.empty(self.n, dtype=self.torch.float64, device=self.device)
+        info = pl_lsq_solve(self.h, delta, make_opts(**kw))
+        return delta, info.as_dict()
+
+    def inverse_weight(self):
+        """Inverse-weighted overdensity N / (w nbar) - 1 (0 where w = 0)."""
+        delta = self.torch.empty(self.n, dtype=self.torch.float64, device=self.device)
+        pl_inverse_weight(self.h, delta)
+        return delta
+
+    def compare(self, rec, ref):
+        """(correlation coefficient, Euclidean distance) of rec against ref."""
+        return pl_compare_fields(self.h, self._dev(rec), self._dev(ref))
 
     def autotune(self, cache_path=None):
         """Pick the fastest tile variants for this grid (needs set_problem)."""

@@ -845,6 +845,47 @@ __global__ void __launch_bounds__(RED_THREADS) resid_hat_kernel(const cx<double>
   block_reduce_store<1>(acc, partials, blockIdx.x);
 }
 
+// LSQ-Wiener set-up: the constant Hessian diagonal d = nbar w and the
+// right-hand side N - nbar w (real space).
+__global__ void __launch_bounds__(RED_THREADS) lsq_setup_kernel(const double* __restrict__ w,
+                                                                const double* __restrict__ counts, double nbar,
+                                                                double* __restrict__ d, double* __restrict__ rhs,
+                                                                long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double nw = nbar * w[i];
+    d[i] = nw;
+    rhs[i] = counts[i] - nw;
+  }
+}
+
+// Inverse-weighted overdensity N / (w nbar) - 1 (the paper's IW estimator,
+// section 4.1.1); cells without data (w = 0) are set to the mean, 0.
+__global__ void __launch_bounds__(RED_THREADS) inverse_weight_kernel(const double* __restrict__ w,
+                                                                     const double* __restrict__ counts, double nbar,
+                                                                     double* __restrict__ out, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double wv = w[i];
+    out[i] = wv > 0.0 ? counts[i] / (wv * nbar) - 1.0 : 0.0;
+  }
+}
+
+// Sums for the correlation coefficient and the Euclidean distance between a
+// reconstruction and a reference field (section 4.1.2): per block
+// (sum ref rec, sum ref^2, sum rec^2, sum (rec - ref)^2).
+__global__ void __launch_bounds__(RED_THREADS) compare_fields_kernel(const double* __restrict__ rec,
+                                                                     const double* __restrict__ ref, long n,
+                                                                     double* __restrict__ partials) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double x = ref[i], y = rec[i], dd = y - x;
+    acc[0] += x * y;
+    acc[1] += x * x;
+    acc[2] += y * y;
+    acc[3] += dd * dd;
+  }
+  block_reduce_store<4>(acc, partials, blockIdx.x);
+}
+
 __global__ void set_scalar_kernel(double* scal, int idx, double value) {
   if (threadIdx.x == 0 && blockIdx.x == 0) scal[idx] = value;
 }

@@ -20,8 +20,8 @@ using namespace pl;
 namespace {
 
 constexpr int NB_RED = 1024;  // blocks of the grid-stride reduction kernels
-// relative tolerance of each FP32 sweep of the mixed-precision adjoint
-constexpr double kAdjointInnerRtol = 1e-3;
+// relative tolerance of each FP32 sweep of a mixed-precision linear solve
+constexpr double kRefineInnerRtol = 1e-3;
 
 struct Status {
   int code = PL_OK;
@@ -610,45 +610,30 @@ int newton_solve(pl_plan* p, double* s_io, const pl_solve_opts& o, pl_solve_info
   return status;
 }
 
+// Solve H x_hat = g_hat (FP64 right-hand side in the plan's g_hat) with the
+// plan's current Hessian diagonal d; the solution is left in x64 (FP64).
+// T = double: one FP64 PCG.  T = float: iterative refinement -- each sweep
+// solves H dl = r with FP32 PCG to a loose relative tolerance; x
+// accumulates in FP64 and r = b - H x is recomputed with an FP64 HVP, so
+// the FP32 rounding of the Krylov recurrences limits neither the attainable
+// accuracy nor (through lost orthogonality) the iteration count.
+// *rres: final residual norm, *bnorm: norm of the right-hand side.
 template <typename T>
-int adjoint_solve(pl_plan* p, const double* s_star, const double* dL_ds, double* lambda_out, double* dA,
-                  double* dbeta, double* dnbar, double* dN, double* dw, const pl_solve_opts& o,
-                  pl_solve_info* info) {
-  pl_solve_info inf{};
-  const double invN = 1.0 / (double)p->N;
-  // linearise at s*: s_hat = F s*, gradient pipeline gives d, e
-  int rc = fwd_r2c<double>(p, s_star, p->s_hat);
-  if (rc) return rc;
-  rc = grad_hat(p, p->s_ws);
-  if (rc) return rc;
-  rc = read_scalars(p);
-  if (rc) return rc;
-  rc = set_precond_constant(p);
-  if (rc) return rc;
-  if constexpr (sizeof(T) == 4) {
-    rc = ensure_d32(p);
-    if (rc) return rc;
-  }
-  // rhs spectrum in g_hat
-  rc = fwd_r2c<double>(p, dL_ds, p->g_hat);
-  if (rc) return rc;
+int solve_spd(pl_plan* p, const pl_solve_opts& o, int* its_out, int* hv_out, double* rres_out, double* bnorm_out) {
   int its = 0, hv = 0;
   double rres = 0.0, bnorm = 0.0;
+  int rc = PL_OK;
+  const double invN = 1.0 / (double)p->N;
   if constexpr (sizeof(T) == 8) {
     rc = pcg<double>(p, p->g_hat, 1.0, 0.0, o.rtol, o.max_cg, o.check_every, &its, &hv, &rres, &bnorm);
     if (rc) return rc;
   } else {
-    // Mixed precision: iterative refinement.  Each sweep solves H dl = r
-    // with FP32 PCG to a loose relative tolerance; lambda accumulates in
-    // FP64 and r = b - H lambda is recomputed with an FP64 HVP, so the FP32
-    // rounding of the Krylov recurrences limits neither the attainable
-    // accuracy nor (through lost orthogonality) the iteration count.
     HIPCHK(p, hipMemsetAsync(p->x64, 0, sizeof(cx<double>) * p->Nh, p->stream));
     const cx<double>* rhs = p->g_hat;
     double rn = 0.0, rn_prev = 0.0;
     for (int sweep = 0; its < o.max_cg; ++sweep) {
       const double target = sweep == 0 ? o.rtol : o.rtol * bnorm / rn;  // relative to this sweep's rhs
-      const double eta = std::max(kAdjointInnerRtol, target);
+      const double eta = std::max(kRefineInnerRtol, target);
       int it = 0, h = 0;
       double rr_abs = 0.0, rhs_n = 0.0;
       rc = pcg<float>(p, rhs, 1.0, 0.0, eta, o.max_cg - its, o.check_every, &it, &h, &rr_abs, &rhs_n);
@@ -678,6 +663,39 @@ int adjoint_solve(pl_plan* p, const double* s_star, const double* dL_ds, double*
     }
     rres = rn;
   }
+  *its_out = its;
+  *hv_out = hv;
+  *rres_out = rres;
+  *bnorm_out = bnorm;
+  return PL_OK;
+}
+
+template <typename T>
+int adjoint_solve(pl_plan* p, const double* s_star, const double* dL_ds, double* lambda_out, double* dA,
+                  double* dbeta, double* dnbar, double* dN, double* dw, const pl_solve_opts& o,
+                  pl_solve_info* info) {
+  pl_solve_info inf{};
+  const double invN = 1.0 / (double)p->N;
+  // linearise at s*: s_hat = F s*, gradient pipeline gives d, e
+  int rc = fwd_r2c<double>(p, s_star, p->s_hat);
+  if (rc) return rc;
+  rc = grad_hat(p, p->s_ws);
+  if (rc) return rc;
+  rc = read_scalars(p);
+  if (rc) return rc;
+  rc = set_precond_constant(p);
+  if (rc) return rc;
+  if constexpr (sizeof(T) == 4) {
+    rc = ensure_d32(p);
+    if (rc) return rc;
+  }
+  // rhs spectrum in g_hat
+  rc = fwd_r2c<double>(p, dL_ds, p->g_hat);
+  if (rc) return rc;
+  int its = 0, hv = 0;
+  double rres = 0.0, bnorm = 0.0;
+  rc = solve_spd<T>(p, o, &its, &hv, &rres, &bnorm);
+  if (rc) return rc;
   inf.cg_its = its;
   inf.hvps = hv;
   inf.grad0 = bnorm;
@@ -701,6 +719,53 @@ int adjoint_solve(pl_plan* p, const double* s_star, const double* dL_ds, double*
   if (dA) *dA = p->h_scal[SC_ADJ + 3] / p->prob.amp;
   inf.status = inf.rel_grad > o.rtol ? PL_ERR_NOT_CONVERGED : PL_OK;
   if (inf.status) p->err = "adjoint solve stopped above the tolerance";
+  if (info) *info = inf;
+  return inf.status;
+}
+
+// LSQ-Wiener filter, the paper's linear comparison estimator (section
+// 4.1.1, the LSQ equation): with the mask operator
+// W = diag(w), the Poisson noise covariance diag(w / nbar), the observed
+// overdensity delta_o = N / nbar - w and unit bias, the filter
+// (S^-1 + W^T N^-1 W)^-1 W^T N^-1 delta_o is the solution of
+//   (S^-1 + diag(nbar w)) delta = N - nbar w,
+// the Hessian system of the MAP pipeline with the constant diagonal
+// d = nbar w.  S is the plan's prior covariance (A pk, inv_p0 at k = 0).
+template <typename T>
+int lsq_solve(pl_plan* p, double* delta_out, const pl_solve_opts& o, pl_solve_info* info) {
+  pl_solve_info inf{};
+  hipLaunchKernelGGL(lsq_setup_kernel, dim3(grid_blocks(p->N)), dim3(RED_THREADS), 0, p->stream, p->prob.w,
+                     p->prob.counts, p->prob.nbar, p->d, p->rtmp, p->N);
+  HIPCHK(p, hipGetLastError());
+  p->d_valid = true;
+  p->d32_valid = false;
+  // sum of d (the preconditioner's percentile is taken relative to its mean)
+  hipLaunchKernelGGL(sum_kernel, dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, p->d, p->N, p->partials);
+  HIPCHK(p, hipGetLastError());
+  HIPCHK(p, finalize(p, NB_RED, 1, FIN_STORE, SC_DSUM, 1.0));
+  int rc = set_precond_constant(p);
+  if (rc) return rc;
+  if constexpr (sizeof(T) == 4) {
+    rc = ensure_d32(p);
+    if (rc) return rc;
+  }
+  rc = fwd_r2c<double>(p, p->rtmp, p->g_hat);
+  if (rc) return rc;
+  int its = 0, hv = 0;
+  double rres = 0.0, bnorm = 0.0;
+  rc = solve_spd<T>(p, o, &its, &hv, &rres, &bnorm);
+  if (rc) return rc;
+  rc = inv_c2r<double>(p, p->x64, p->t64, delta_out);
+  if (rc) return rc;
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  p->d_valid = false;  // nbar w is not a linearisation of the posterior
+  p->d32_valid = false;
+  inf.cg_its = its;
+  inf.hvps = hv;
+  inf.grad0 = bnorm;
+  inf.rel_grad = bnorm > 0.0 ? rres / bnorm : 0.0;
+  inf.status = inf.rel_grad > o.rtol ? PL_ERR_NOT_CONVERGED : PL_OK;
+  if (inf.status) p->err = "LSQ solve stopped above the tolerance";
   if (info) *info = inf;
   return inf.status;
 }
@@ -987,6 +1052,46 @@ int pl_solve_adjoint(pl_plan* p, const double* s_star, const double* dL_ds, doub
     return adjoint_solve<float>(p, s_star, dL_ds, lambda_out, dL_dA, dL_dbeta, dL_dnbar, dL_dN, dL_dw, o, info);
   }
   return adjoint_solve<double>(p, s_star, dL_ds, lambda_out, dL_dA, dL_dbeta, dL_dnbar, dL_dN, dL_dw, o, info);
+}
+
+int pl_lsq_solve(pl_plan* p, double* delta_out, const pl_solve_opts* opts, pl_solve_info* info) {
+  int rc = check_ready(p);
+  if (rc) return rc;
+  if (!delta_out) return fail(p, PL_ERR_INVALID_ARG, "null pointer");
+  pl_solve_opts o = resolve_opts(p, opts);
+  if (!(o.rtol >= 0.0) || o.max_cg <= 0) return fail(p, PL_ERR_INVALID_ARG, "invalid solve options");
+  if (o.precision == PL_MIXED) {
+    if (p->precision != PL_MIXED) return fail(p, PL_ERR_INVALID_ARG, "mixed LSQ solve needs a PL_MIXED plan");
+    return lsq_solve<float>(p, delta_out, o, info);
+  }
+  return lsq_solve<double>(p, delta_out, o, info);
+}
+
+int pl_inverse_weight(pl_plan* p, double* delta_out) {
+  int rc = check_ready(p);
+  if (rc) return rc;
+  if (!delta_out) return fail(p, PL_ERR_INVALID_ARG, "null pointer");
+  hipLaunchKernelGGL(inverse_weight_kernel, dim3(grid_blocks(p->N)), dim3(RED_THREADS), 0, p->stream, p->prob.w,
+                     p->prob.counts, p->prob.nbar, delta_out, p->N);
+  HIPCHK(p, hipGetLastError());
+  return PL_OK;
+}
+
+int pl_compare_fields(pl_plan* p, const double* rec, const double* ref, double* r_out, double* d_euc_out) {
+  if (!p) return PL_ERR_INVALID_ARG;
+  if (!p->ws) return fail(p, PL_ERR_INVALID_ARG, "workspace not set");
+  if (!rec || !ref) return fail(p, PL_ERR_INVALID_ARG, "null pointer");
+  hipLaunchKernelGGL(compare_fields_kernel, dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, rec, ref, p->N,
+                     p->partials);
+  HIPCHK(p, hipGetLastError());
+  HIPCHK(p, finalize(p, NB_RED, 4, FIN_STORE, SC_DF, 1.0));
+  int rc = read_scalars(p);
+  if (rc) return rc;
+  const double srr = p->h_scal[SC_DF], sxx = p->h_scal[SC_DF + 1], syy = p->h_scal[SC_DF + 2],
+               sdd = p->h_scal[SC_DF + 3];
+  if (r_out) *r_out = (sxx > 0.0 && syy > 0.0) ? srr / (std::sqrt(sxx) * std::sqrt(syy)) : 0.0;
+  if (d_euc_out) *d_euc_out = std::sqrt(sdd / (double)p->N);
+  return PL_OK;
 }
 
 }  // extern "C"
