@@ -17,6 +17,10 @@ Also reported (not part of `value`):
                    calls after 20 warm-up calls), against 8 TB/s
   mixed         -- the same solve with FP32 FFTs/HVPs and FP64 reductions
   adjoint       -- adjoint solve of L = sum (s* - s_true)^2 at the MAP
+  estimators    -- the paper's comparison estimators (LSQ-Wiener filter,
+                   inverse weighting) with the correlation coefficient and
+                   Euclidean distance of each reconstruction, MAP included,
+                   against the true overdensity
   batched       -- 64 independent reconstructions, n in {32, 48, 64, 96},
                    solved together (mixed precision) vs one after another
                    (plain FP64)
@@ -222,6 +226,31 @@ def main():
     print(f"# adjoint fp64 {1e3 * t_adj:.1f} ms {ainfo}; mixed {1e3 * t_adj32:.1f} ms",
           file=sys.stderr, flush=True)
 
+    # ---------------- comparison estimators (section 4.1) ----------------
+    # LSQ-Wiener filter (FP64 and refined mixed), inverse weighting, and the
+    # correlation coefficient / Euclidean distance of each reconstruction
+    # against the true overdensity exp(s_true) - 1
+    plan.lsq(rtol=rtol, max_cg=20000, precision=0)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    d_lsq, linfo = plan.lsq(rtol=rtol, max_cg=20000, precision=0)
+    torch.cuda.synchronize()
+    t_lsq = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    d_lsq32, linfo32 = plan.lsq(rtol=rtol, max_cg=20000, precision=1)
+    torch.cuda.synchronize()
+    t_lsq32 = time.perf_counter() - t0
+    d_true = torch.expm1(s_true)
+    quality = {}
+    for name, rec in (("lognormal_map", torch.expm1(s_fp64)), ("lsq_wiener", d_lsq),
+                      ("inverse_weighting", plan.inverse_weight())):
+        r, dist = plan.compare(rec, d_true)
+        quality[name] = {"r": r, "d_euc": dist}
+    estimators = {"lsq_ms_fp64": 1e3 * t_lsq, "lsq_ms_mixed": 1e3 * t_lsq32, "lsq_cg_its_fp64": linfo["cg_its"],
+                  "lsq_cg_its_mixed": linfo32["cg_its"], "quality_vs_true_overdensity": quality}
+    print(f"# lsq fp64 {1e3 * t_lsq:.1f} ms ({linfo['cg_its']} its), mixed {1e3 * t_lsq32:.1f} ms "
+          f"({linfo32['cg_its']} its); quality {quality}", file=sys.stderr, flush=True)
+
     # ---------------- batched workload ----------------
     batch = None
     if not args.no_batch and args.workload == "sel256" and args.n is None:
@@ -324,6 +353,7 @@ def main():
         "adjoint": {"ms_fp64": 1e3 * t_adj, "ms_mixed": 1e3 * t_adj32, "cg_its_fp64": ainfo["cg_its"],
                     "cg_its_mixed": ainfo32["cg_its"], "dL_dA": grads["A"], "dL_dbeta": grads["beta"],
                     "dL_dnbar": grads["nbar"]},
+        "estimators": estimators,
         "batched": batch,
         "cpu_baseline": cpu,
     }
