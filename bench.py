@@ -17,6 +17,8 @@ Also reported (not part of `value`):
                    calls after 20 warm-up calls), against 8 TB/s
   mixed         -- the same solve with FP32 FFTs/HVPs and FP64 reductions
   adjoint       -- adjoint solve of L = sum (s* - s_true)^2 at the MAP
+  nlcg          -- the paper-literal Krylov step (eq. New5 step length,
+                   nonlinear-CG search vectors), FP64, same tolerance
   estimators    -- the paper's comparison estimators (LSQ-Wiener filter,
                    inverse weighting) with the correlation coefficient and
                    Euclidean distance of each reconstruction, MAP included,
@@ -226,6 +228,20 @@ def main():
     print(f"# adjoint fp64 {1e3 * t_adj:.1f} ms {ainfo}; mixed {1e3 * t_adj32:.1f} ms",
           file=sys.stderr, flush=True)
 
+    # ---------------- paper-literal Krylov step (nonlinear-CG search vectors) ----------------
+    s_nl, ninfo = plan.solve_nlcg(rtol=rtol, max_cg=20000)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s_nl, ninfo = plan.solve_nlcg(rtol=rtol, max_cg=20000)
+    torch.cuda.synchronize()
+    t_nlcg = time.perf_counter() - t0
+    nlcg_rel = float(torch.linalg.norm(s_nl - s_fp64) / torch.linalg.norm(s_fp64))
+    nlcg = {"ms": 1e3 * t_nlcg, "steps": ninfo["cg_its"], "hvps": ninfo["hvps"], "status": ninfo["status"],
+            "rel_grad": ninfo["rel_grad"], "rel_l2_vs_newton_krylov": nlcg_rel,
+            "time_vs_newton_krylov": 1e3 * t_nlcg / ms_per_step}
+    print(f"# nlcg fp64 {1e3 * t_nlcg:.1f} ms, {ninfo['cg_its']} steps, rel vs Newton-Krylov {nlcg_rel:.2e}",
+          file=sys.stderr, flush=True)
+
     # ---------------- comparison estimators (section 4.1) ----------------
     # LSQ-Wiener filter (FP64 and refined mixed), inverse weighting, and the
     # correlation coefficient / Euclidean distance of each reconstruction
@@ -353,6 +369,7 @@ def main():
         "adjoint": {"ms_fp64": 1e3 * t_adj, "ms_mixed": 1e3 * t_adj32, "cg_its_fp64": ainfo["cg_its"],
                     "cg_its_mixed": ainfo32["cg_its"], "dL_dA": grads["A"], "dL_dbeta": grads["beta"],
                     "dL_dnbar": grads["nbar"]},
+        "nlcg": nlcg,
         "estimators": estimators,
         "batched": batch,
         "cpu_baseline": cpu,

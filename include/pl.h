@@ -176,6 +176,20 @@ int pl_solve_adjoint(pl_plan* plan, const double* s_star, const double* dL_ds, d
                      double* dL_dA, double* dL_dbeta, double* dL_dnbar, double* dL_dN, double* dL_dw,
                      const pl_solve_opts* opts, pl_solve_info* info);
 
+/* The Krylov step of section 3.1 with a nonlinear-CG search vector, the
+   paper-literal form of the solver: s <- s + tau xi with the step length of
+   eq. (New5), tau = -xi^T grad Q / xi^T H xi (one HVP per step).  The paper
+   leaves the search vector to an earlier reference; here xi is the
+   preconditioned Polak-Ribiere+ conjugate direction (preconditioner
+   1/lambda_k + c in Fourier space), restarted along -M^-1 g when it is not
+   a descent direction, and each step is safeguarded by the Armijo search of
+   pl_newton_krylov_solve started at tau.  Same MAP, same stopping rule and
+   s_inout contract as pl_newton_krylov_solve; FP64 only (opts.precision =
+   PL_MIXED is rejected).  opts.max_cg caps the number of steps; max_newton
+   and eta_max are unused.  info: newton_its = cg_its = steps, hvps = HVPs.
+   Synchronises the stream. */
+int pl_nlcg_solve(pl_plan* plan, double* s_inout, const pl_solve_opts* opts, pl_solve_info* info);
+
 /* ---------------------------------------------------------------------------
  * The paper's comparison estimators and quality measures (section 4.1).
  * ------------------------------------------------------------------------- */

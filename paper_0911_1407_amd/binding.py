@@ -33,7 +33,7 @@ EXPORTED = ("pl_default_opts", "pl_plan_create", "pl_plan_set_workspace", "pl_pl
             "pl_hessvec_hat", "pl_hessvec_hat_f32", "pl_newton_krylov_solve", "pl_solve_adjoint",
             "pl_last_error", "pl_batch_create", "pl_batch_set_workspace", "pl_batch_set_problem",
             "pl_batch_solve", "pl_batch_destroy", "pl_batch_last_error", "pl_plan_autotune",
-            "pl_plan_get_variants", "pl_plan_set_variants", "pl_plan_prior_is_radial", "pl_lsq_solve",
+            "pl_plan_get_variants", "pl_plan_set_variants", "pl_plan_prior_is_radial", "pl_lsq_solve", "pl_nlcg_solve",
             "pl_inverse_weight", "pl_compare_fields")
 
 BATCH_LENGTHS = (32, 48, 64, 96, 128)
@@ -109,6 +109,7 @@ def load(path=LIB_PATH):
     lib.pl_plan_get_variants.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     lib.pl_plan_prior_is_radial.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     lib.pl_lsq_solve.argtypes = [vp, vp, ctypes.POINTER(pl_solve_opts), ctypes.POINTER(pl_solve_info)]
+    lib.pl_nlcg_solve.argtypes = [vp, vp, ctypes.POINTER(pl_solve_opts), ctypes.POINTER(pl_solve_info)]
     lib.pl_inverse_weight.argtypes = [vp, vp]
     lib.pl_compare_fields.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.pl_plan_set_variants.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
@@ -219,6 +220,13 @@ def pl_last_error(h):
 
 def pl_plan_autotune(h, cache_path=None):
     return _check(h, load().pl_plan_autotune(h, cache_path.encode() if cache_path else None))
+
+
+def pl_nlcg_solve(h, s_inout, opts=None):
+    info = pl_solve_info()
+    rc = load().pl_nlcg_solve(h, _ptr(s_inout), ctypes.byref(opts) if opts else None, ctypes.byref(info))
+    _check(h, rc, allow=(PL_ERR_NOT_CONVERGED, PL_ERR_LINESEARCH))
+    return info
 
 
 def pl_lsq_solve(h, delta_out, opts=None):
@@ -343,6 +351,7 @@ class Plan:
         self._ws_view = self.ws[off:]
         pl_plan_set_workspace(self.h, self._ws_view)
         self._keep = ()
+        self.params = None  # set by set_problem
 
     @property
     def ncells(self):
@@ -397,7 +406,9 @@ class Plan:
 
     def solve(self, s0=None, **kw):
         if s0 is None:
-            s = self.torch.full(self.n, float(self.params["mu"]), dtype=self.torch.float64, device=self.device)
+            # s0 = mu (0 before a problem is set; the library then reports it)
+            mu = float(self.params["mu"]) if self.params else 0.0
+            s = self.torch.full(self.n, mu, dtype=self.torch.float64, device=self.device)
         else:
             s = self._dev(s0).clone()
         info = pl_newton_krylov_solve(self.h, s, make_opts(**kw))
@@ -410,6 +421,18 @@ class Plan:
         dw = self.torch.empty_like(s_star) if want_fields else None
         scal, info = pl_solve_adjoint(self.h, s_star, dL_ds, lam, dN, dw, make_opts(**kw))
         return dict(scal, N=dN, w=dw, lam=lam), info.as_dict()
+
+    def solve_nlcg(self, s0=None, **kw):
+        """MAP by the Krylov step with nonlinear-CG search vectors (FP64)."""
+        if s0 is None:
+            # s0 = mu (0 before a problem is set; the library then reports it)
+            mu = float(self.params["mu"]) if self.params else 0.0
+            s = self.torch.full(self.n, mu, dtype=self.torch.float64, device=self.device)
+        else:
+            s = self._dev(s0).clone()
+        kw.setdefault("precision", 0)
+        info = pl_nlcg_solve(self.h, s, make_opts(**kw))
+        return s, info.as_dict()
 
     def lsq(self, **kw):
         """LSQ-Wiener overdensity of the current problem: (delta, info)."""

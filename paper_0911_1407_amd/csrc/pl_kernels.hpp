@@ -886,6 +886,54 @@ __global__ void __launch_bounds__(RED_THREADS) compare_fields_kernel(const doubl
   block_reduce_store<4>(acc, partials, blockIdx.x);
 }
 
+// Nonlinear CG (the Krylov step with a nonlinear-CG search vector): per
+// block, sum_k c_k m_k |g_k|^2 and sum_k c_k m_k Re(conj(g_k) g_old_k) with
+// m_k = 1 / (1/lambda_k + dbar) (the preconditioner) and c_k the Hermitian
+// weights -- N times the real-space dots g^T M^-1 g and g^T M^-1 g_old.
+__global__ void __launch_bounds__(RED_THREADS) nlcg_dots_kernel(const cx<double>* __restrict__ g,
+                                                                const cx<double>* __restrict__ g_old,
+                                                                const double* __restrict__ tab, int radial, Grid gr,
+                                                                long nh, const double* __restrict__ scal,
+                                                                double* __restrict__ partials) {
+  ModeIter mi{gr};
+  const double dbar = scal[SC_DBAR];
+  double acc[2] = {0.0, 0.0};
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nh; i += (long)gridDim.x * blockDim.x) {
+    int kx, ky, kz;
+    mi.decompose(i, kx, ky, kz);
+    const double m = precond_inv<double>(inv_lam_at(tab, radial, gr, kx, ky, kz, i), dbar) * herm_w(kz, gr);
+    const cx<double> gv = g[i], go = g_old[i];
+    acc[0] += m * (gv.x * gv.x + gv.y * gv.y);
+    acc[1] += m * (gv.x * go.x + gv.y * go.y);
+  }
+  block_reduce_store<2>(acc, partials, blockIdx.x);
+}
+
+// xi = -M^-1 g + beta xi (beta = 0: steepest descent), g_old = g; per block
+// sum_k c_k Re(conj(xi_k) g_k) (N times the slope xi^T g).
+__global__ void __launch_bounds__(RED_THREADS) nlcg_update_kernel(const cx<double>* __restrict__ g,
+                                                                  cx<double>* __restrict__ g_old,
+                                                                  cx<double>* __restrict__ xi, double beta,
+                                                                  const double* __restrict__ tab, int radial, Grid gr,
+                                                                  long nh, const double* __restrict__ scal,
+                                                                  double* __restrict__ partials) {
+  ModeIter mi{gr};
+  const double dbar = scal[SC_DBAR];
+  double acc[1] = {0.0};
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nh; i += (long)gridDim.x * blockDim.x) {
+    int kx, ky, kz;
+    mi.decompose(i, kx, ky, kz);
+    const double m = precond_inv<double>(inv_lam_at(tab, radial, gr, kx, ky, kz, i), dbar);
+    const cx<double> gv = g[i], xv = xi[i];
+    const cx<double> xn = {beta == 0.0 ? -m * gv.x : -m * gv.x + beta * xv.x,
+                           beta == 0.0 ? -m * gv.y : -m * gv.y + beta * xv.y};
+    xi[i] = xn;
+    g_old[i] = gv;
+    acc[0] += herm_w(kz, gr) * (xn.x * gv.x + xn.y * gv.y);
+  }
+  block_reduce_store<1>(acc, partials, blockIdx.x);
+}
+
 __global__ void set_scalar_kernel(double* scal, int idx, double value) {
   if (threadIdx.x == 0 && blockIdx.x == 0) scal[idx] = value;
 }

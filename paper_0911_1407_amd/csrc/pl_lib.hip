@@ -482,23 +482,16 @@ pl_solve_opts resolve_opts(pl_plan* p, const pl_solve_opts* o) {
 // One Newton step at the current spectral iterate: inner PCG on
 // H p = -g in T precision, then the Armijo line search along p.  Returns
 // PL_OK with *alpha > 0 on success, *alpha < 0 if no step was found.
+// Armijo backtracking along the spectral direction x from s_hat (section
+// 3.1 gives the step; the globalisation is this build's reading): the
+// decrease f(s + a p) - f(s) = a b + a^2 c / 2 + sum_i [e_i expm1(a beta p_i)
+// - a beta N_i p_i] (b = p^T S^-1 (s - mu), c = p^T S^-1 p, p = F^-1 x) is
+// tested against c1 a p^T g for a = a0, a0/2, a0/4, ... (4 per pass, at
+// most 32).  *alpha = the accepted step or -1; *descent = (p^T g < 0).
 template <typename T>
-int newton_step(pl_plan* p, double eta_gn, const pl_solve_opts& o, pl_solve_info& inf, double* alpha,
-                bool* descent) {
+int line_search(pl_plan* p, cx<T>* x, double a_start, const pl_solve_opts& o, double* alpha, bool* descent) {
   const double invN = 1.0 / (double)p->N;
-  int rc;
-  if constexpr (sizeof(T) == 4) {
-    rc = ensure_d32(p);
-    if (rc) return rc;
-  }
-  int its = 0, hv = 0;
-  rc = pcg<T>(p, p->g_hat, -1.0, eta_gn, 0.0, o.max_cg, o.check_every, &its, &hv, nullptr, nullptr);
-  if (rc) return rc;
-  inf.cg_its += its;
-  inf.hvps += hv;
-  // line search along the Newton direction x (spectral) / preal (real)
-  cx<T>* x = View<T>::x(p);
-  rc = inv_c2r<T>(p, x, View<T>::t(p), View<T>::preal(p));
+  int rc = inv_c2r<T>(p, x, View<T>::t(p), View<T>::preal(p));
   if (rc) return rc;
   hipLaunchKernelGGL((ls_dots_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, x, p->s_hat, p->g_hat,
                      p->radial ? p->tab_rad : p->tab_mode, p->radial, p->g, p->Nh, (double)p->N * p->prob.mu,
@@ -511,7 +504,7 @@ int newton_step(pl_plan* p, double eta_gn, const pl_solve_opts& o, pl_solve_info
   *alpha = -1.0;
   *descent = slope < 0.0;
   if (slope < 0.0) {
-    double a0 = 1.0;
+    double a0 = a_start;
     for (int batch = 0; batch < 8 && *alpha < 0.0; ++batch) {
       hipLaunchKernelGGL((ls_eval_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, View<T>::preal(p),
                          p->e, p->prob.counts, p->prob.beta, a0, p->N, p->partials);
@@ -530,6 +523,26 @@ int newton_step(pl_plan* p, double eta_gn, const pl_solve_opts& o, pl_solve_info
       a0 *= 1.0 / 16.0;
     }
   }
+  return PL_OK;
+}
+
+template <typename T>
+int newton_step(pl_plan* p, double eta_gn, const pl_solve_opts& o, pl_solve_info& inf, double* alpha,
+                bool* descent) {
+  int rc;
+  if constexpr (sizeof(T) == 4) {
+    rc = ensure_d32(p);
+    if (rc) return rc;
+  }
+  int its = 0, hv = 0;
+  rc = pcg<T>(p, p->g_hat, -1.0, eta_gn, 0.0, o.max_cg, o.check_every, &its, &hv, nullptr, nullptr);
+  if (rc) return rc;
+  inf.cg_its += its;
+  inf.hvps += hv;
+  // line search along the Newton direction x (spectral) / preal (real)
+  cx<T>* x = View<T>::x(p);
+  rc = line_search<T>(p, x, 1.0, o, alpha, descent);
+  if (rc) return rc;
   if (*alpha > 0.0) {
     hipLaunchKernelGGL((axpy_hat_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, p->s_hat, x, *alpha,
                        p->Nh);
@@ -721,6 +734,127 @@ int adjoint_solve(pl_plan* p, const double* s_star, const double* dL_ds, double*
   if (inf.status) p->err = "adjoint solve stopped above the tolerance";
   if (info) *info = inf;
   return inf.status;
+}
+
+// The Krylov step of section 3.1 with a nonlinear-CG search vector:
+// x <- x + tau xi with tau = -xi^T grad Q / xi^T H xi (eq. New5, one HVP per
+// step).  The paper leaves the scheme for xi to an earlier reference; here
+// xi is the preconditioned Polak-Ribiere+ conjugate direction
+//   xi = -M^-1 g + beta xi_old,  beta = max(0, g^T M^-1 (g - g_old) / g_old^T M^-1 g_old),
+// M = 1/lambda_k + dbar in Fourier space, restarted (beta = 0) when xi is not
+// a descent direction, and each step is safeguarded by the Armijo search
+// started at tau.  FP64; opts.max_cg caps the number of steps.
+constexpr int kNlcgPrecondEvery = 16;  // steps between refreshes of dbar
+
+int nlcg_solve(pl_plan* p, double* s_io, const pl_solve_opts& o, pl_solve_info* info) {
+  pl_solve_info inf{};
+  const double invN = 1.0 / (double)p->N;
+  int rc = fwd_r2c<double>(p, s_io, p->s_hat);
+  if (rc) return rc;
+  rc = grad_hat(p, s_io);
+  if (rc) return rc;
+  rc = read_scalars(p);
+  if (rc) return rc;
+  const double g0 = std::sqrt(std::max(0.0, p->h_scal[SC_GG]));
+  double gn = g0;
+  inf.grad0 = g0;
+  inf.obj = 0.5 * p->h_scal[SC_PRIOR] + p->h_scal[SC_LIK];
+  if (!std::isfinite(g0) || !std::isfinite(inf.obj)) {
+    if (info) *info = inf;
+    return fail(p, PL_ERR_DOMAIN, "gradient at the starting point is not finite");
+  }
+  cx<double>* xi = p->x64;
+  cx<double>* g_old = p->r64;
+  cx<double>* q = p->p64;
+  const double* tab = p->radial ? p->tab_rad : p->tab_mode;
+  double gz_old = 0.0;
+  bool restart = true;
+  int status = PL_OK;
+  for (int it = 0; g0 > 0.0; ++it) {
+    if (gn <= o.rtol * g0) break;
+    if (it >= o.max_cg) {
+      status = PL_ERR_NOT_CONVERGED;
+      p->err = "nonlinear-CG step cap reached";
+      break;
+    }
+    if (it % kNlcgPrecondEvery == 0) {
+      rc = set_precond_constant(p);
+      if (rc) return rc;
+    }
+    // search vector
+    hipLaunchKernelGGL(nlcg_dots_kernel, dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, p->g_hat, g_old, tab,
+                       p->radial, p->g, p->Nh, p->scal, p->partials);
+    HIPCHK(p, hipGetLastError());
+    HIPCHK(p, finalize(p, NB_RED, 2, FIN_STORE, SC_DF, invN));
+    rc = read_scalars(p);
+    if (rc) return rc;
+    const double gz = p->h_scal[SC_DF], gzo = p->h_scal[SC_DF + 1];
+    double beta = (restart || !(gz_old > 0.0)) ? 0.0 : std::max(0.0, (gz - gzo) / gz_old);
+    double slope = 0.0;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      hipLaunchKernelGGL(nlcg_update_kernel, dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, p->g_hat, g_old, xi,
+                         beta, tab, p->radial, p->g, p->Nh, p->scal, p->partials);
+      HIPCHK(p, hipGetLastError());
+      HIPCHK(p, finalize(p, NB_RED, 1, FIN_STORE, SC_DF + 2, invN));
+      rc = read_scalars(p);
+      if (rc) return rc;
+      slope = p->h_scal[SC_DF + 2];
+      if (slope < 0.0 || beta == 0.0) break;
+      beta = 0.0;  // not a descent direction: restart along -M^-1 g
+    }
+    gz_old = gz;
+    restart = false;
+    if (!(slope < 0.0)) {
+      status = PL_ERR_LINESEARCH;
+      p->err = "preconditioned gradient is not a descent direction";
+      break;
+    }
+    // step length of eq. (New5) on the local quadratic model
+    int nb = 0;
+    rc = hvp_hat<double>(p, xi, q, &nb);
+    if (rc) return rc;
+    HIPCHK(p, finalize(p, nb, 3, FIN_STORE, SC_ADJ, invN));
+    rc = read_scalars(p);
+    if (rc) return rc;
+    inf.hvps += 1;
+    const double xhx = p->h_scal[SC_ADJ];
+    if (!(xhx > 0.0)) {
+      status = PL_ERR_LINESEARCH;
+      p->err = "non-positive curvature along the search vector";
+      break;
+    }
+    const double tau = -slope / xhx;
+    double alpha = -1.0;
+    bool descent = false;
+    rc = line_search<double>(p, xi, tau, o, &alpha, &descent);
+    if (rc) return rc;
+    if (alpha < 0.0) {
+      status = PL_ERR_LINESEARCH;
+      p->err = "no step along the search vector satisfies the Armijo condition";
+      break;
+    }
+    if (alpha < tau) restart = true;  // a shortened step: rebuild conjugacy from -M^-1 g
+    hipLaunchKernelGGL((axpy_hat_kernel<double>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, p->s_hat, xi,
+                       alpha, p->Nh);
+    HIPCHK(p, hipGetLastError());
+    rc = grad_hat(p, s_io);
+    if (rc) return rc;
+    rc = read_scalars(p);
+    if (rc) return rc;
+    gn = std::sqrt(std::max(0.0, p->h_scal[SC_GG]));
+    inf.obj = 0.5 * p->h_scal[SC_PRIOR] + p->h_scal[SC_LIK];
+    inf.newton_its = it + 1;
+    inf.cg_its = it + 1;
+    if (!std::isfinite(gn)) {
+      status = PL_ERR_DOMAIN;
+      p->err = "gradient became non-finite";
+      break;
+    }
+  }
+  inf.rel_grad = g0 > 0.0 ? gn / g0 : 0.0;
+  inf.status = status;
+  if (info) *info = inf;
+  return status;
 }
 
 // LSQ-Wiener filter, the paper's linear comparison estimator (section
@@ -1052,6 +1186,20 @@ int pl_solve_adjoint(pl_plan* p, const double* s_star, const double* dL_ds, doub
     return adjoint_solve<float>(p, s_star, dL_ds, lambda_out, dL_dA, dL_dbeta, dL_dnbar, dL_dN, dL_dw, o, info);
   }
   return adjoint_solve<double>(p, s_star, dL_ds, lambda_out, dL_dA, dL_dbeta, dL_dnbar, dL_dN, dL_dw, o, info);
+}
+
+int pl_nlcg_solve(pl_plan* p, double* s_inout, const pl_solve_opts* opts, pl_solve_info* info) {
+  int rc = check_ready(p);
+  if (rc) return rc;
+  if (!s_inout) return fail(p, PL_ERR_INVALID_ARG, "null pointer");
+  pl_solve_opts o = resolve_opts(p, opts);
+  if (!(o.rtol >= 0.0) || o.max_cg <= 0 || !(o.ls_c1 > 0.0 && o.ls_c1 < 1.0))
+    return fail(p, PL_ERR_INVALID_ARG, "invalid solve options");
+  if (opts && opts->precision == PL_MIXED)
+    return fail(p, PL_ERR_INVALID_ARG, "the nonlinear-CG solve runs in FP64 only");
+  rc = check_finite(p, s_inout, p->N, "s_inout");
+  if (rc) return rc;
+  return nlcg_solve(p, s_inout, o, info);
 }
 
 int pl_lsq_solve(pl_plan* p, double* delta_out, const pl_solve_opts* opts, pl_solve_info* info) {
