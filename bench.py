@@ -262,7 +262,17 @@ def main():
                       ("inverse_weighting", plan.inverse_weight())):
         r, dist = plan.compare(rec, d_true)
         quality[name] = {"r": r, "d_euc": dist}
-    estimators = {"lsq_ms_fp64": 1e3 * t_lsq, "lsq_ms_mixed": 1e3 * t_lsq32, "lsq_cg_its_fp64": linfo["cg_its"],
+    # lognormal prior from a matter spectrum (section 2.3), the workload's
+    # spectrum and amplitude read as the matter spectrum
+    pk_dev = torch.from_numpy(inst["pk"]).to(dev)
+    plan.lognormal_prior(pk_dev, inst["amp"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, pinfo = plan.lognormal_prior(pk_dev, inst["amp"])
+    torch.cuda.synchronize()
+    t_prior = time.perf_counter() - t0
+    estimators = {"lognormal_prior_ms": 1e3 * t_prior, "lognormal_prior": pinfo,
+                  "lsq_ms_fp64": 1e3 * t_lsq, "lsq_ms_mixed": 1e3 * t_lsq32, "lsq_cg_its_fp64": linfo["cg_its"],
                   "lsq_cg_its_mixed": linfo32["cg_its"], "quality_vs_true_overdensity": quality}
     print(f"# lsq fp64 {1e3 * t_lsq:.1f} ms ({linfo['cg_its']} its), mixed {1e3 * t_lsq32:.1f} ms "
           f"({linfo32['cg_its']} its); quality {quality}", file=sys.stderr, flush=True)

@@ -190,6 +190,25 @@ int pl_solve_adjoint(pl_plan* plan, const double* s_star, const double* dL_ds, d
    Synchronises the stream. */
 int pl_nlcg_solve(pl_plan* plan, double* s_inout, const pl_solve_opts* opts, pl_solve_info* info);
 
+/* Lognormal prior from a matter spectrum (section 2.3): the correlation
+   function S(r) of the overdensity (the inverse transform of the
+   eigenvalues amp * pk_k * N / V, so S(0) is the cell variance), its log
+   transform S_L(r) = ln(1 + S(r)), and the spectrum of S_L,
+   P_L(k) = (F S_L)_k * V / N, written to pk_log_out to be used with amp = 1
+   in pl_set_problem.  mu_out (host, nullable) receives the mean field
+   mu = -sigma0^2 / 2 with sigma0^2 = S_L(0) (section 2.3, the mean-field
+   equation), sigma0_sq_out (host, nullable) sigma0^2.  The log transform
+   need not keep every eigenvalue positive: values at or below
+   1e-10 * S_L(0) (S_L(0) is their mean) are raised to it, and
+   n_clipped_out (host, nullable) receives how many k != 0 modes were.  The
+   k = 0 entry follows the same rule; pl_set_problem takes the k = 0 prior
+   from inv_p0 instead.  pk, pk_log_out: device, the half spectrum
+   [nx][ny][nz/2+1].  PL_ERR_DOMAIN if amp <= 0 or S(r) <= -1 somewhere.
+   Needs a workspace, not a problem; overwrites the plan's solver
+   workspace.  Synchronises the stream. */
+int pl_lognormal_prior(pl_plan* plan, const double* pk, double amp, double* pk_log_out, double* mu_out,
+                       double* sigma0_sq_out, int64_t* n_clipped_out);
+
 /* ---------------------------------------------------------------------------
  * The paper's comparison estimators and quality measures (section 4.1).
  * ------------------------------------------------------------------------- */

@@ -28,6 +28,9 @@ What it computes (every function cites the passage it follows):
                    loss of the MAP field with respect to the model parameters.
 * ``lambertw``  -- the principal branch of the Lambert W function by Halley's
                    iteration (Corless et al. 1996), for closed-form pins.
+* ``prior``     -- the lognormal prior covariance and mean built from a
+                   matter spectrum (section 2.3, S_L(r) = ln(1 + S(r)),
+                   mu = -S_L(0)/2).
 * ``wiener``    -- the paper's comparison estimators (section 4.1.1: inverse
                    weighting and the LSQ-Wiener filter) and quality measures
                    (section 4.1.2: correlation coefficient, Euclidean

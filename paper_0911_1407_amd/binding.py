@@ -33,7 +33,7 @@ EXPORTED = ("pl_default_opts", "pl_plan_create", "pl_plan_set_workspace", "pl_pl
             "pl_hessvec_hat", "pl_hessvec_hat_f32", "pl_newton_krylov_solve", "pl_solve_adjoint",
             "pl_last_error", "pl_batch_create", "pl_batch_set_workspace", "pl_batch_set_problem",
             "pl_batch_solve", "pl_batch_destroy", "pl_batch_last_error", "pl_plan_autotune",
-            "pl_plan_get_variants", "pl_plan_set_variants", "pl_plan_prior_is_radial", "pl_lsq_solve", "pl_nlcg_solve",
+            "pl_plan_get_variants", "pl_plan_set_variants", "pl_plan_prior_is_radial", "pl_lsq_solve", "pl_nlcg_solve", "pl_lognormal_prior",
             "pl_inverse_weight", "pl_compare_fields")
 
 BATCH_LENGTHS = (32, 48, 64, 96, 128)
@@ -110,6 +110,8 @@ def load(path=LIB_PATH):
     lib.pl_plan_prior_is_radial.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     lib.pl_lsq_solve.argtypes = [vp, vp, ctypes.POINTER(pl_solve_opts), ctypes.POINTER(pl_solve_info)]
     lib.pl_nlcg_solve.argtypes = [vp, vp, ctypes.POINTER(pl_solve_opts), ctypes.POINTER(pl_solve_info)]
+    lib.pl_lognormal_prior.argtypes = [vp, vp, ctypes.c_double, vp, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.pl_inverse_weight.argtypes = [vp, vp]
     lib.pl_compare_fields.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.pl_plan_set_variants.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
@@ -220,6 +222,15 @@ def pl_last_error(h):
 
 def pl_plan_autotune(h, cache_path=None):
     return _check(h, load().pl_plan_autotune(h, cache_path.encode() if cache_path else None))
+
+
+def pl_lognormal_prior(h, pk, amp, pk_log_out):
+    mu = ctypes.c_double(0.0)
+    s0 = ctypes.c_double(0.0)
+    nc = ctypes.c_int64(0)
+    _check(h, load().pl_lognormal_prior(h, _ptr(pk), float(amp), _ptr(pk_log_out), ctypes.byref(mu),
+                                        ctypes.byref(s0), ctypes.byref(nc)))
+    return {"mu": mu.value, "sigma0_sq": s0.value, "n_clipped": int(nc.value)}
 
 
 def pl_nlcg_solve(h, s_inout, opts=None):
@@ -433,6 +444,13 @@ class Plan:
         kw.setdefault("precision", 0)
         info = pl_nlcg_solve(self.h, s, make_opts(**kw))
         return s, info.as_dict()
+
+    def lognormal_prior(self, pk, amp):
+        """Log-field spectrum P_L (device, half spectrum, for amp = 1) and
+        {mu, sigma0_sq, n_clipped} from the matter spectrum amp * pk."""
+        out = self.torch.empty(self.half_shape, dtype=self.torch.float64, device=self.device)
+        info = pl_lognormal_prior(self.h, self._dev(pk), amp, out)
+        return out, info
 
     def lsq(self, **kw):
         """LSQ-Wiener overdensity of the current problem: (delta, info)."""

@@ -934,6 +934,43 @@ __global__ void __launch_bounds__(RED_THREADS) nlcg_update_kernel(const cx<doubl
   block_reduce_store<1>(acc, partials, blockIdx.x);
 }
 
+// Lognormal prior from a matter spectrum (section 2.3): the eigenvalues of
+// S, lambda_k = coef pk_k (coef = amp N / V), as a real half spectrum.
+__global__ void __launch_bounds__(RED_THREADS) spectrum_to_half_kernel(const double* __restrict__ pk, double coef,
+                                                                       cx<double>* __restrict__ out, long nh) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nh; i += (long)gridDim.x * blockDim.x)
+    out[i] = {coef * pk[i], 0.0};
+}
+
+// S_L(r) = ln(1 + S(r)) in place; flags[0] |= 1 where S(r) <= -1 (no
+// logarithm).
+__global__ void __launch_bounds__(RED_THREADS) log1p_field_kernel(double* __restrict__ x, long n,
+                                                                  int* __restrict__ flags) {
+  int bad = 0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double v = x[i];
+    if (!(v > -1.0)) bad = 1;
+    x[i] = log1p(v);
+  }
+  if (bad) atomicOr(flags, 1);
+}
+
+// P_L = lambda^L_k / coef (the real part of F S_L), raised to floor where
+// it is not above it; flags[1] counts the raised k != 0 modes.
+__global__ void __launch_bounds__(RED_THREADS) half_to_spectrum_kernel(const cx<double>* __restrict__ in,
+                                                                       double inv_coef, double floor_val,
+                                                                       double* __restrict__ pk_out, long nh,
+                                                                       int* __restrict__ flags) {
+  int clipped = 0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nh; i += (long)gridDim.x * blockDim.x) {
+    const double lam = in[i].x;
+    const bool low = !(lam > floor_val);
+    if (low && i != 0) ++clipped;
+    pk_out[i] = (low ? floor_val : lam) * inv_coef;
+  }
+  if (clipped) atomicAdd(flags + 1, clipped);
+}
+
 __global__ void set_scalar_kernel(double* scal, int idx, double value) {
   if (threadIdx.x == 0 && blockIdx.x == 0) scal[idx] = value;
 }

@@ -22,6 +22,9 @@ namespace {
 constexpr int NB_RED = 1024;  // blocks of the grid-stride reduction kernels
 // relative tolerance of each FP32 sweep of a mixed-precision linear solve
 constexpr double kRefineInnerRtol = 1e-3;
+// eigenvalues of the lognormal prior covariance below this fraction of
+// S_L(0) (their mean) are raised to it (pl_lognormal_prior)
+constexpr double kPriorFloorRel = 1e-10;
 
 struct Status {
   int code = PL_OK;
@@ -1200,6 +1203,49 @@ int pl_nlcg_solve(pl_plan* p, double* s_inout, const pl_solve_opts* opts, pl_sol
   rc = check_finite(p, s_inout, p->N, "s_inout");
   if (rc) return rc;
   return nlcg_solve(p, s_inout, o, info);
+}
+
+int pl_lognormal_prior(pl_plan* p, const double* pk, double amp, double* pk_log_out, double* mu_out,
+                       double* sigma0_sq_out, int64_t* n_clipped_out) {
+  if (!p) return PL_ERR_INVALID_ARG;
+  if (!p->ws) return fail(p, PL_ERR_INVALID_ARG, "workspace not set");
+  if (!pk || !pk_log_out) return fail(p, PL_ERR_INVALID_ARG, "null pointer");
+  if (!(amp > 0.0) || !std::isfinite(amp)) return fail(p, PL_ERR_DOMAIN, "amp must be finite and > 0");
+  const double coef = amp * (double)p->N / (p->box[0] * p->box[1] * p->box[2]);
+  cx<double>* t = p->t64;
+  double* field = p->s_ws;
+  HIPCHK(p, hipMemsetAsync(p->flags, 0, sizeof(int) * 4, p->stream));
+  // S(r): inverse transform of the eigenvalues of S (the 1/N of the inverse
+  // makes S(0) the cell variance (1/V) sum_k amp pk_k)
+  hipLaunchKernelGGL(spectrum_to_half_kernel, dim3(grid_blocks(p->Nh)), dim3(RED_THREADS), 0, p->stream, pk, coef, t,
+                     p->Nh);
+  HIPCHK(p, hipGetLastError());
+  int rc = inv_c2r<double>(p, t, t, field);
+  if (rc) return rc;
+  hipLaunchKernelGGL(log1p_field_kernel, dim3(grid_blocks(p->N)), dim3(RED_THREADS), 0, p->stream, field, p->N,
+                     p->flags);
+  HIPCHK(p, hipGetLastError());
+  double s_l0 = 0.0;
+  int h[4] = {0, 0, 0, 0};
+  HIPCHK(p, hipMemcpyAsync(&s_l0, field, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(p, hipMemcpyAsync(h, p->flags, sizeof(int) * 4, hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  if (h[0]) return fail(p, PL_ERR_DOMAIN, "the correlation function reaches -1: ln(1 + S) is undefined");
+  rc = fwd_r2c<double>(p, field, t);
+  if (rc) return rc;
+  // the mean of lambda^L over the full spectrum is S_L(0) = sigma0^2
+  const double floor_val = kPriorFloorRel * std::fabs(s_l0);
+  // P_L = lambda^L V / N: the log-field spectrum itself (use it with amp = 1)
+  const double v_over_n = p->box[0] * p->box[1] * p->box[2] / (double)p->N;
+  hipLaunchKernelGGL(half_to_spectrum_kernel, dim3(grid_blocks(p->Nh)), dim3(RED_THREADS), 0, p->stream, t,
+                     v_over_n, floor_val, pk_log_out, p->Nh, p->flags);
+  HIPCHK(p, hipGetLastError());
+  HIPCHK(p, hipMemcpyAsync(h, p->flags, sizeof(int) * 4, hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  if (sigma0_sq_out) *sigma0_sq_out = s_l0;
+  if (mu_out) *mu_out = -0.5 * s_l0;
+  if (n_clipped_out) *n_clipped_out = h[1];
+  return PL_OK;
 }
 
 int pl_lsq_solve(pl_plan* p, double* delta_out, const pl_solve_opts* opts, pl_solve_info* info) {
