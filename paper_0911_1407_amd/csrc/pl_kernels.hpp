@@ -486,26 +486,28 @@ __device__ __forceinline__ void row_body(const RowArgs<T>& a, int ublock, cx<T>*
         v[q * R0 + r] = valid ? cx<T>{a.in_r[rowA * N + e], a.in_r[rowB * N + e]} : cx<T>{T(0), T(0)};
       }
   } else {
-    // load the two half rows (2H contiguous complex values) into LDS
-    const cx<T>* src = a.in_c + rowA * H;
-    if (active)
-      for (int i = t; i < 2 * H; i += P) lds[MAP::off(i)] = src[i];
-    __syncthreads();
+    // the two half rows A (at rowA * H) and B (next H values) give
+    // Z[e] = A[e] + i B[e], with A[e] = conj A[N - e] above N/2: each lane
+    // loads its elements straight from memory (the lanes of a row pair read
+    // consecutive, or mirrored consecutive, values)
+    const cx<T>* srcA = a.in_c + rowA * H;
+    const cx<T>* srcB = srcA + H;
 #pragma unroll
     for (int q = 0; q < W / R0; ++q)
 #pragma unroll
       for (int r = 0; r < R0; ++r) {
-        int e = active ? in_pos<PL, 0>(t, q, r) : 0;
-        cx<T> A, Bv;
-        if (e <= N / 2) {
-          A = lds[MAP::off(e)];
-          Bv = lds[MAP::off(H + e)];
-          if (e == 0 || e == N / 2) { A.y = T(0); Bv.y = T(0); }
-        } else {
-          A = conj(lds[MAP::off(N - e)]);
-          Bv = conj(lds[MAP::off(H + N - e)]);
+        const int e = active ? in_pos<PL, 0>(t, q, r) : 0;
+        const bool lo = e <= N / 2;
+        const int ie = lo ? e : N - e;
+        cx<T> A = srcA[ie], Bv = srcB[ie];
+        if (!lo) {
+          A.y = -A.y;
+          Bv.y = -Bv.y;
+        } else if (e == 0 || e == N / 2) {
+          A.y = T(0);
+          Bv.y = T(0);
         }
-        v[q * R0 + r] = {A.x - Bv.y, A.y + Bv.x};
+        v[q * R0 + r] = valid ? cx<T>{A.x - Bv.y, A.y + Bv.x} : cx<T>{T(0), T(0)};
       }
   }
 
@@ -634,21 +636,36 @@ __device__ __forceinline__ void row_body(const RowArgs<T>& a, int ublock, cx<T>*
 
   // ---- split Z' into the two half rows: A'[k] = (Z[k] + conj Z[N-k])/2,
   //      B'[k] = (Z[k] - conj Z[N-k])/(2i) ----
-  __syncthreads();
-  if (active) {
-#pragma unroll
-    for (int q = 0; q < W / RL; ++q)
-#pragma unroll
-      for (int m = 0; m < RL; ++m) lds[MAP::off(out_pos<PL, PL::NS - 1>(t, q, m))] = v[q * RL + m];
-  }
-  __syncthreads();
-  if (valid) {
+  // The last stage leaves element k = t + P j (j = q + (W/RL) m) in slot
+  // (q, m) of lane t.  Its mirror N - k = (P - t) + P (W - 1 - j) sits in
+  // lane (P - t) mod P of the same row pair, slot W - 1 - j (lane 0: its
+  // own slot (W - j) mod W); it is fetched with a cross-lane shuffle, so the
+  // split needs neither LDS nor a barrier.  All lanes take part in the
+  // shuffles (uniform control flow); only valid ones store.
+  {
+    constexpr int QL = W / RL;
     cx<T>* dst = a.out_c + rowA * H;
-    for (int k = t; k < H; k += P) {
-      cx<T> zk = lds[MAP::off(k)];
-      cx<T> zc = lds[MAP::off(k == 0 ? 0 : N - k)];
-      dst[k] = {T(0.5) * (zk.x + zc.x), T(0.5) * (zk.y - zc.y)};
-      dst[H + k] = {T(0.5) * (zk.y + zc.y), T(0.5) * (zc.x - zk.x)};
+    const int lane = (int)(threadIdx.x & 63);
+    const int src_lane = (lane & ~(P - 1)) | ((P - t) & (P - 1));
+#pragma unroll
+    for (int j = 0; j <= W / 2; ++j) {
+      const int jo = W - 1 - j;                   // partner slot (t > 0)
+      const int jz = (W - j) % W;                 // own slot (t = 0)
+      const cx<T> send = v[(jo % QL) * RL + jo / QL];
+      cx<T> zc;
+      if constexpr (P > 1) {
+        zc.x = __shfl(send.x, src_lane, 64);
+        zc.y = __shfl(send.y, src_lane, 64);
+        if (t == 0) zc = v[(jz % QL) * RL + jz / QL];
+      } else {
+        zc = v[(jz % QL) * RL + jz / QL];
+      }
+      const cx<T> zk = v[(j % QL) * RL + j / QL];
+      const int k = t + P * j;
+      if (valid && k < H) {
+        dst[k] = {T(0.5) * (zk.x + zc.x), T(0.5) * (zk.y - zc.y)};
+        dst[H + k] = {T(0.5) * (zk.y + zc.y), T(0.5) * (zc.x - zk.x)};
+      }
     }
   }
   if constexpr (OP == ROW_GRAD || OP == ROW_HVP) block_reduce_store<2>(acc, a.partials, block_linear);
