@@ -19,8 +19,9 @@ Also reported (not part of `value`):
   adjoint       -- adjoint solve of L = sum (s* - s_true)^2 at the MAP
   nlcg          -- the paper-literal Krylov step (eq. New5 step length,
                    nonlinear-CG search vectors), FP64, same tolerance
-  estimators    -- the paper's comparison estimators (LSQ-Wiener filter,
-                   inverse weighting) with the correlation coefficient and
+  estimators    -- the paper's comparison estimators (Gaussian-prior MAP,
+                   LSQ-Wiener filter, inverse weighting, lognormal prior
+                   construction) with the correlation coefficient and
                    Euclidean distance of each reconstruction, MAP included,
                    against the true overdensity
   batched       -- 64 independent reconstructions, n in {32, 48, 64, 96},
@@ -256,9 +257,16 @@ def main():
     d_lsq32, linfo32 = plan.lsq(rtol=rtol, max_cg=20000, precision=1)
     torch.cuda.synchronize()
     t_lsq32 = time.perf_counter() - t0
+    # Gaussian-prior MAP (eq. MAPG), FP64
+    plan.solve_gaussian(rtol=rtol, max_newton=200, max_cg=20000)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    d_gauss, ginfo = plan.solve_gaussian(rtol=rtol, max_newton=200, max_cg=20000)
+    torch.cuda.synchronize()
+    t_gauss = time.perf_counter() - t0
     d_true = torch.expm1(s_true)
     quality = {}
-    for name, rec in (("lognormal_map", torch.expm1(s_fp64)), ("lsq_wiener", d_lsq),
+    for name, rec in (("lognormal_map", torch.expm1(s_fp64)), ("gaussian_map", d_gauss), ("lsq_wiener", d_lsq),
                       ("inverse_weighting", plan.inverse_weight())):
         r, dist = plan.compare(rec, d_true)
         quality[name] = {"r": r, "d_euc": dist}
@@ -272,6 +280,8 @@ def main():
     torch.cuda.synchronize()
     t_prior = time.perf_counter() - t0
     estimators = {"lognormal_prior_ms": 1e3 * t_prior, "lognormal_prior": pinfo,
+                  "gaussian_map_ms_fp64": 1e3 * t_gauss, "gaussian_map_newton_its": ginfo["newton_its"],
+                  "gaussian_map_cg_its": ginfo["cg_its"], "gaussian_map_status": ginfo["status"],
                   "lsq_ms_fp64": 1e3 * t_lsq, "lsq_ms_mixed": 1e3 * t_lsq32, "lsq_cg_its_fp64": linfo["cg_its"],
                   "lsq_cg_its_mixed": linfo32["cg_its"], "quality_vs_true_overdensity": quality}
     print(f"# lsq fp64 {1e3 * t_lsq:.1f} ms ({linfo['cg_its']} its), mixed {1e3 * t_lsq32:.1f} ms "

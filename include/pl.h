@@ -176,6 +176,22 @@ int pl_solve_adjoint(pl_plan* plan, const double* s_star, const double* dL_ds, d
                      double* dL_dA, double* dL_dbeta, double* dL_dnbar, double* dL_dN, double* dL_dw,
                      const pl_solve_opts* opts, pl_solve_info* info);
 
+/* MAP of the Gaussian-prior model (section 2.2, unit bias: eq. MAPG,
+   delta = S (N / (1 + delta) - nbar w)), the paper's comparison MAP filter.
+   Solved as the minimum of the negative log-posterior
+     f(delta) = 1/2 delta^T S^-1 delta + sum_i [nbar w_i delta_i - N_i ln(1 + delta_i)],
+   whose root is eq. MAPG and whose Hessian S^-1 + diag(N / (1 + delta)^2)
+   is symmetric (eq. MAPG multiplied through by S gives the non-symmetric
+   form of section 3.1.1; same root), by the inexact Newton-Krylov iteration
+   of pl_newton_krylov_solve with the same options and info.  Uses the
+   problem's w, counts, nbar, prior covariance amp * pk and inv_p0; mu and
+   beta are not used (zero-mean prior, unit bias).  delta_inout: device, N,
+   the start on input (zeros is the prior mean) and the MAP overdensity on
+   output; every cell with counts must have 1 + delta > 0 at the start
+   (PL_ERR_DOMAIN), and the line search keeps it so.  A solution needs
+   inv_p0 > 0 or some counts > 0.  Synchronises the stream. */
+int pl_gaussian_map_solve(pl_plan* plan, double* delta_inout, const pl_solve_opts* opts, pl_solve_info* info);
+
 /* The Krylov step of section 3.1 with a nonlinear-CG search vector, the
    paper-literal form of the solver: s <- s + tau xi with the step length of
    eq. (New5), tau = -xi^T grad Q / xi^T H xi (one HVP per step).  The paper

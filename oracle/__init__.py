@@ -28,6 +28,8 @@ What it computes (every function cites the passage it follows):
                    loss of the MAP field with respect to the model parameters.
 * ``lambertw``  -- the principal branch of the Lambert W function by Halley's
                    iteration (Corless et al. 1996), for closed-form pins.
+* ``gaussian``  -- the MAP of the Gaussian-prior model (section 2.2, unit
+                   bias, eq. MAPG), the paper's comparison MAP filter.
 * ``prior``     -- the lognormal prior covariance and mean built from a
                    matter spectrum (section 2.3, S_L(r) = ln(1 + S(r)),
                    mu = -S_L(0)/2).

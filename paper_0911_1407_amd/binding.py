@@ -34,6 +34,7 @@ EXPORTED = ("pl_default_opts", "pl_plan_create", "pl_plan_set_workspace", "pl_pl
             "pl_last_error", "pl_batch_create", "pl_batch_set_workspace", "pl_batch_set_problem",
             "pl_batch_solve", "pl_batch_destroy", "pl_batch_last_error", "pl_plan_autotune",
             "pl_plan_get_variants", "pl_plan_set_variants", "pl_plan_prior_is_radial", "pl_lsq_solve", "pl_nlcg_solve", "pl_lognormal_prior",
+            "pl_gaussian_map_solve",
             "pl_inverse_weight", "pl_compare_fields")
 
 BATCH_LENGTHS = (32, 48, 64, 96, 128)
@@ -110,6 +111,7 @@ def load(path=LIB_PATH):
     lib.pl_plan_prior_is_radial.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     lib.pl_lsq_solve.argtypes = [vp, vp, ctypes.POINTER(pl_solve_opts), ctypes.POINTER(pl_solve_info)]
     lib.pl_nlcg_solve.argtypes = [vp, vp, ctypes.POINTER(pl_solve_opts), ctypes.POINTER(pl_solve_info)]
+    lib.pl_gaussian_map_solve.argtypes = [vp, vp, ctypes.POINTER(pl_solve_opts), ctypes.POINTER(pl_solve_info)]
     lib.pl_lognormal_prior.argtypes = [vp, vp, ctypes.c_double, vp, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.pl_inverse_weight.argtypes = [vp, vp]
@@ -231,6 +233,14 @@ def pl_lognormal_prior(h, pk, amp, pk_log_out):
     _check(h, load().pl_lognormal_prior(h, _ptr(pk), float(amp), _ptr(pk_log_out), ctypes.byref(mu),
                                         ctypes.byref(s0), ctypes.byref(nc)))
     return {"mu": mu.value, "sigma0_sq": s0.value, "n_clipped": int(nc.value)}
+
+
+def pl_gaussian_map_solve(h, delta_inout, opts=None):
+    info = pl_solve_info()
+    rc = load().pl_gaussian_map_solve(h, _ptr(delta_inout), ctypes.byref(opts) if opts else None,
+                                      ctypes.byref(info))
+    _check(h, rc, allow=(PL_ERR_NOT_CONVERGED, PL_ERR_LINESEARCH))
+    return info
 
 
 def pl_nlcg_solve(h, s_inout, opts=None):
@@ -432,6 +442,15 @@ class Plan:
         dw = self.torch.empty_like(s_star) if want_fields else None
         scal, info = pl_solve_adjoint(self.h, s_star, dL_ds, lam, dN, dw, make_opts(**kw))
         return dict(scal, N=dN, w=dw, lam=lam), info.as_dict()
+
+    def solve_gaussian(self, delta0=None, **kw):
+        """MAP overdensity of the Gaussian-prior model (eq. MAPG): (delta, info)."""
+        if delta0 is None:
+            d = self.torch.zeros(self.n, dtype=self.torch.float64, device=self.device)
+        else:
+            d = self._dev(delta0).clone()
+        info = pl_gaussian_map_solve(self.h, d, make_opts(**kw))
+        return d, info.as_dict()
 
     def solve_nlcg(self, s0=None, **kw):
         """MAP by the Krylov step with nonlinear-CG search vectors (FP64)."""

@@ -31,6 +31,11 @@ constexpr int RED_THREADS = 256;
 // the working set against the cache, so it is a per-plan schedule choice.
 // Stores keep the default policy.
 enum { NT_VEC = 1, NT_DIAG = 2 };
+
+// Posterior model of a solve: the lognormal prior on s = ln(1 + delta) with
+// the power-law bias (section 2.3, 2.4), or the Gaussian prior on delta with
+// unit bias (section 2.2.2, eq. MAPG).
+enum { MODEL_LOGNORMAL = 0, MODEL_GAUSSIAN = 1 };
 template <typename T>
 __device__ __forceinline__ T ld_stream(const T* p, int nt) {
   return nt ? __builtin_nontemporal_load(p) : *p;
@@ -442,6 +447,7 @@ struct RowArgs {
   double* partials;
   const double* skip;  // if non-null and *skip != 0 the launch does nothing
   int nt;              // NT_VEC | NT_DIAG: operands loaded non-temporally (ld_stream)
+  int model;           // ROW_GRAD likelihood: MODEL_LOGNORMAL or MODEL_GAUSSIAN
 };
 
 template <int N, int V = 0>
@@ -615,15 +621,28 @@ __device__ __forceinline__ void row_body(const RowArgs<T>& a, int ublock, cx<T>*
               for (int h = 0; h < 2; ++h) {
                 long i = (h ? rowB : rowA) * N + e;
                 double s = (double)(h ? z.y : z.x) * (double)a.scale;
-                double ex = a.nbar * a.w[i] * exp(a.beta * s);
                 double cnt = a.counts[i];
                 a.s_out[i] = s;
-                a.e_out[i] = ex;
-                double dd = a.beta * a.beta * ex;
-                a.d_out[i] = dd;
-                acc[0] += ex - a.beta * cnt * s;
-                acc[1] += dd;
-                l[h] = a.beta * (ex - cnt);
+                if (a.model == MODEL_GAUSSIAN) {
+                  // Gaussian prior on delta = s, unity bias (section 2.2.2):
+                  // -ln L = sum nbar w (1 + delta) - N ln(1 + delta) + const
+                  const double nw = a.nbar * a.w[i], op = 1.0 + s;
+                  const double inv = cnt > 0.0 ? 1.0 / op : 0.0;
+                  const double dd = cnt * inv * inv;
+                  a.e_out[i] = op;
+                  a.d_out[i] = dd;
+                  acc[0] += nw * s - (cnt > 0.0 ? cnt * log1p(s) : 0.0);
+                  acc[1] += dd;
+                  l[h] = nw - cnt * inv;
+                } else {
+                  double ex = a.nbar * a.w[i] * exp(a.beta * s);
+                  a.e_out[i] = ex;
+                  double dd = a.beta * a.beta * ex;
+                  a.d_out[i] = dd;
+                  acc[0] += ex - a.beta * cnt * s;
+                  acc[1] += dd;
+                  l[h] = a.beta * (ex - cnt);
+                }
               }
             }
             v[q * RL + m] = {(T)l[0], (T)l[1]};
@@ -988,6 +1007,17 @@ __global__ void __launch_bounds__(RED_THREADS) half_to_spectrum_kernel(const cx<
   if (clipped) atomicAdd(flags + 1, clipped);
 }
 
+// flags[0] = 1 where a cell with counts has 1 + delta <= 0 (the Gaussian
+// model's likelihood is undefined there); flags[0] must start at 0.
+__global__ void __launch_bounds__(RED_THREADS) gauss_domain_kernel(const double* __restrict__ delta,
+                                                                   const double* __restrict__ counts, long n,
+                                                                   int* __restrict__ flags) {
+  int bad = 0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    if (counts[i] > 0.0 && !(1.0 + delta[i] > 0.0)) bad = 1;
+  if (bad) atomicOr(flags, 1);
+}
+
 __global__ void set_scalar_kernel(double* scal, int idx, double value) {
   if (threadIdx.x == 0 && blockIdx.x == 0) scal[idx] = value;
 }
@@ -1063,6 +1093,31 @@ __global__ void __launch_bounds__(RED_THREADS) ls_eval_kernel(const T* __restric
                                                               const double* __restrict__ counts, double beta,
                                                               double a0, long n, double* __restrict__ partials) {
   ls_eval_body<T>(p, e, counts, beta, a0, n, partials, blockIdx.x, gridDim.x);
+}
+
+// Line search of the Gaussian-prior model: for a = a0, a0/2, a0/4, a0/8 the
+// likelihood part of f(delta + a p) - f(delta),
+//   sum_i [nbar w_i a p_i - N_i log1p(a p_i / (1 + delta_i))]  (op = 1 + delta),
+// which is +inf or NaN (rejected) where a step leaves 1 + delta > 0 in a
+// cell with counts.
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS) ls_eval_gauss_kernel(const T* __restrict__ p,
+                                                                    const double* __restrict__ op,
+                                                                    const double* __restrict__ w,
+                                                                    const double* __restrict__ counts, double nbar,
+                                                                    double a0, long n, double* __restrict__ partials) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double pi = (double)p[i], nw = nbar * w[i], ci = counts[i];
+    const double ratio = ci > 0.0 ? pi / op[i] : 0.0;
+    double a = a0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc[j] += nw * a * pi - (ci > 0.0 ? ci * log1p(a * ratio) : 0.0);
+      a *= 0.5;
+    }
+  }
+  block_reduce_store<4>(acc, partials, blockIdx.x);
 }
 
 #ifdef PL_OPS_KERNELS

@@ -76,6 +76,9 @@ struct pl_plan {
   // schedule choices per precision [FP64/FP32] (see VarSlot); the table
   // choices apply only when the radial table is valid
   int var[2][V_COUNT] = {{0, 0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 1, 1, 0}};
+  // posterior model of the running solve (MODEL_*); the lognormal one
+  // except inside pl_gaussian_map_solve
+  int model = MODEL_LOGNORMAL;
   std::string err;
 };
 
@@ -194,6 +197,10 @@ struct View<float> {
 // Passes
 // ---------------------------------------------------------------------------
 
+// Prior mean of the running solve's field: mu (lognormal model) or 0
+// (Gaussian prior on delta).
+double prior_mean(const pl_plan* p) { return p->model == MODEL_GAUSSIAN ? 0.0 : p->prob.mu; }
+
 template <typename T>
 ColArgs<T> col_args(pl_plan* p, int axis, const cx<T>* in, cx<T>* out) {
   ColArgs<T> a{};
@@ -249,6 +256,7 @@ RowArgs<T> row_args(pl_plan* p) {
   a.beta = p->prob.beta;
   a.partials = p->partials;
   a.nt = p->var[sizeof(T) == 4 ? 1 : 0][V_NT];
+  a.model = p->model;
   return a;
 }
 
@@ -339,7 +347,7 @@ int grad_hat(pl_plan* p, double* s_out) {
   HIPCHK(p, run_col<double>(p, 1, false, COL_PLAIN, col_args<double>(p, 1, t, t), nullptr));
   ColArgs<double> ca = col_args<double>(p, 0, t, p->g_hat);
   ca.base = p->s_hat;
-  ca.k0_shift = (double)p->N * p->prob.mu;
+  ca.k0_shift = (double)p->N * prior_mean(p);
   HIPCHK(p, run_col<double>(p, 0, false, COL_ADDPRIOR, ca, &nb));
   HIPCHK(p, finalize(p, nb, 3, FIN_STORE, SC_GG - 1, 1.0 / (double)p->N));
   p->d_valid = true;
@@ -497,7 +505,7 @@ int line_search(pl_plan* p, cx<T>* x, double a_start, const pl_solve_opts& o, do
   int rc = inv_c2r<T>(p, x, View<T>::t(p), View<T>::preal(p));
   if (rc) return rc;
   hipLaunchKernelGGL((ls_dots_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, x, p->s_hat, p->g_hat,
-                     p->radial ? p->tab_rad : p->tab_mode, p->radial, p->g, p->Nh, (double)p->N * p->prob.mu,
+                     p->radial ? p->tab_rad : p->tab_mode, p->radial, p->g, p->Nh, (double)p->N * prior_mean(p),
                      p->partials);
   HIPCHK(p, hipGetLastError());
   HIPCHK(p, finalize(p, NB_RED, 3, FIN_STORE, SC_LS_B, invN));
@@ -509,8 +517,12 @@ int line_search(pl_plan* p, cx<T>* x, double a_start, const pl_solve_opts& o, do
   if (slope < 0.0) {
     double a0 = a_start;
     for (int batch = 0; batch < 8 && *alpha < 0.0; ++batch) {
-      hipLaunchKernelGGL((ls_eval_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, View<T>::preal(p),
-                         p->e, p->prob.counts, p->prob.beta, a0, p->N, p->partials);
+      if (p->model == MODEL_GAUSSIAN)
+        hipLaunchKernelGGL((ls_eval_gauss_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream,
+                           View<T>::preal(p), p->e, p->prob.w, p->prob.counts, p->prob.nbar, a0, p->N, p->partials);
+      else
+        hipLaunchKernelGGL((ls_eval_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, View<T>::preal(p),
+                           p->e, p->prob.counts, p->prob.beta, a0, p->N, p->partials);
       HIPCHK(p, hipGetLastError());
       HIPCHK(p, finalize(p, NB_RED, 4, FIN_STORE, SC_DF, 1.0));
       rc = read_scalars(p);
@@ -1189,6 +1201,34 @@ int pl_solve_adjoint(pl_plan* p, const double* s_star, const double* dL_ds, doub
     return adjoint_solve<float>(p, s_star, dL_ds, lambda_out, dL_dA, dL_dbeta, dL_dnbar, dL_dN, dL_dw, o, info);
   }
   return adjoint_solve<double>(p, s_star, dL_ds, lambda_out, dL_dA, dL_dbeta, dL_dnbar, dL_dN, dL_dw, o, info);
+}
+
+int pl_gaussian_map_solve(pl_plan* p, double* delta_inout, const pl_solve_opts* opts, pl_solve_info* info) {
+  int rc = check_ready(p);
+  if (rc) return rc;
+  if (!delta_inout) return fail(p, PL_ERR_INVALID_ARG, "null pointer");
+  pl_solve_opts o = resolve_opts(p, opts);
+  if (!(o.rtol >= 0.0) || o.max_newton < 0 || o.max_cg <= 0 || !(o.eta_max > 0.0) || !(o.ls_c1 > 0.0 && o.ls_c1 < 1.0))
+    return fail(p, PL_ERR_INVALID_ARG, "invalid solve options");
+  rc = check_finite(p, delta_inout, p->N, "delta_inout");
+  if (rc) return rc;
+  if (o.precision == PL_MIXED && p->precision != PL_MIXED)
+    return fail(p, PL_ERR_INVALID_ARG, "mixed solve needs a PL_MIXED plan");
+  // the start must lie where every cell with counts has 1 + delta > 0
+  HIPCHK(p, hipMemsetAsync(p->flags, 0, sizeof(int), p->stream));
+  hipLaunchKernelGGL(gauss_domain_kernel, dim3(grid_blocks(p->N)), dim3(RED_THREADS), 0, p->stream, delta_inout,
+                     p->prob.counts, p->N, p->flags);
+  HIPCHK(p, hipGetLastError());
+  int h = 0;
+  HIPCHK(p, hipMemcpyAsync(&h, p->flags, sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  if (h) return fail(p, PL_ERR_DOMAIN, "1 + delta <= 0 in a cell with counts at the start");
+  p->model = MODEL_GAUSSIAN;
+  rc = o.precision == PL_MIXED ? newton_solve<float>(p, delta_inout, o, info)
+                               : newton_solve<double>(p, delta_inout, o, info);
+  p->model = MODEL_LOGNORMAL;
+  p->d_valid = false;  // the cached diagonal belongs to the Gaussian model
+  return rc;
 }
 
 int pl_nlcg_solve(pl_plan* p, double* s_inout, const pl_solve_opts* opts, pl_solve_info* info) {
