@@ -266,11 +266,12 @@ const char* pl_last_error(const pl_plan* plan);
    table (when pl_plan_prior_is_radial) or from the per-mode table: the
    shell table saves a streaming read, the per-mode table avoids a
    scattered lookup.  Operands that a pass reads once (Krylov vectors, the
-   Hessian diagonal, the per-mode table) can be loaded non-temporally so
-   that the pass-to-pass intermediate stays in the memory-side cache, which
-   pays when that intermediate fits there.  Times the solver's fused CG step
-   (five passes) per combination of the Krylov-carrying x variant, the y and
-   z variants, the Krylov passes' table and the load policy, then the
+   Hessian diagonal, the per-mode table) can be loaded, and the Krylov
+   vectors stored, non-temporally so that the pass-to-pass intermediate
+   stays in the memory-side cache, which pays when that intermediate fits
+   there.  Times the solver's fused CG step (five passes) per combination of
+   the Krylov-carrying x variant, the y and z variants, the Krylov passes'
+   table and the streaming policy, then the
    isolated operator (pl_hessvec_hat) per
    combination of its own x variant and table, on the plan's workspace (after
    pl_set_problem; it overwrites the cached Hessian diagonal and the solver's
@@ -283,15 +284,17 @@ int pl_plan_autotune(pl_plan* plan, const char* cache_path);
 /* Number of schedule choices per precision.  In order: x variant of the
    Krylov-carrying passes, y variant, z variant, x variant of the operator's
    passes, table of the Krylov passes (1 shell, 0 per mode), table of the
-   operator's passes, streaming loads (bit 0: Krylov vectors and per-mode
-   table non-temporal, bit 1: Hessian diagonal non-temporal; 0..3).
+   operator's passes, streaming policy (bit 0: Krylov vectors and per-mode
+   table loaded non-temporally, bit 1: Hessian diagonal loaded
+   non-temporally, bit 2: the Krylov passes' stores of r, p, x
+   non-temporal; 0..7).
    Variants: 0 default, 1 wide (a length without a wide variant runs the
    default); a shell-table choice runs the per-mode table when the spectrum
    is not radial. */
 #define PL_NUM_VARIANTS 7
 /* Current choices: out = the PL_NUM_VARIANTS choices for FP64, then FP32. */
 int pl_plan_get_variants(const pl_plan* plan, int32_t out[2 * PL_NUM_VARIANTS]);
-/* Force the choices (same order); each entry 0 or 1, streaming loads 0..3. */
+/* Force the choices (same order); each entry 0 or 1, streaming policy 0..7. */
 int pl_plan_set_variants(pl_plan* plan, const int32_t v[2 * PL_NUM_VARIANTS]);
 
 /* ---------------------------------------------------------------------------

@@ -29,8 +29,10 @@ constexpr int RED_THREADS = 256;
 // holds two bits: NT_VEC for the Krylov vectors r, p, x and the per-mode
 // 1/lambda table, NT_DIAG for the Hessian diagonal.  Which pays depends on
 // the working set against the cache, so it is a per-plan schedule choice.
-// Stores keep the default policy.
-enum { NT_VEC = 1, NT_DIAG = 2 };
+// With NT_STORE the Krylov passes also store r, p and x non-temporally
+// (those vectors are read again only by the next step's streaming loads);
+// the intermediate's stores keep the default policy.
+enum { NT_VEC = 1, NT_DIAG = 2, NT_STORE = 4 };
 
 // Posterior model of a solve: the lognormal prior on s = ln(1 + delta) with
 // the power-law bias (section 2.3, 2.4), or the Gaussian prior on delta with
@@ -39,6 +41,18 @@ enum { MODEL_LOGNORMAL = 0, MODEL_GAUSSIAN = 1 };
 template <typename T>
 __device__ __forceinline__ T ld_stream(const T* p, int nt) {
   return nt ? __builtin_nontemporal_load(p) : *p;
+}
+template <typename T>
+__device__ __forceinline__ void st_stream(cx<T>* p, cx<T> v, int nt) {
+  if (nt) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    v2 x;
+    x.x = v.x;
+    x.y = v.y;
+    __builtin_nontemporal_store(x, reinterpret_cast<v2*>(p));
+  } else {
+    *p = v;
+  }
 }
 template <typename T>
 __device__ __forceinline__ cx<T> ld_stream(const cx<T>* p, int nt) {
@@ -247,7 +261,7 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
           const T il = inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_VEC);
           const T mi = precond_inv<T>(il, dbar), bt = (T)beta;
           pn = {mi * rv.x + bt * po.x, mi * rv.y + bt * po.y};
-          pio[idx] = pn;
+          st_stream(pio + idx, pn, a.nt & NT_STORE);
           acc[0] += hw * (double)(il * (pn.x * pn.x + pn.y * pn.y));
         }
         v[q * R0 + r] = pn;
@@ -325,8 +339,8 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
           const T qx = x.x + il * pv.x, qy = x.y + il * pv.y, al = (T)alpha;
           cx<T> rv = ld_stream(a.cg_r + mode, a.nt & NT_VEC), xv = ld_stream(a.cg_x + mode, a.nt & NT_VEC);
           cx<T> rn = {rv.x - al * qx, rv.y - al * qy};
-          a.cg_r[mode] = rn;
-          a.cg_x[mode] = {xv.x + al * pv.x, xv.y + al * pv.y};
+          st_stream(a.cg_r + mode, rn, a.nt & NT_STORE);
+          st_stream(a.cg_x + mode, cx<T>{xv.x + al * pv.x, xv.y + al * pv.y}, a.nt & NT_STORE);
           const T rr = rn.x * rn.x + rn.y * rn.y;
           acc[0] += hw * (double)rr;
           acc[1] += hw * (double)(precond_inv<T>(il, dbar) * rr);
