@@ -284,17 +284,18 @@ int pl_plan_autotune(pl_plan* plan, const char* cache_path);
 /* Number of schedule choices per precision.  In order: x variant of the
    Krylov-carrying passes, y variant, z variant, x variant of the operator's
    passes, table of the Krylov passes (1 shell, 0 per mode), table of the
-   operator's passes, streaming policy (bit 0: Krylov vectors and per-mode
-   table loaded non-temporally, bit 1: Hessian diagonal loaded
-   non-temporally, bit 2: the Krylov passes' stores of r, p, x
-   non-temporal; 0..7).
+   operator's passes, streaming policy (bit 0: loads of the Krylov vectors
+   p, x and of the per-mode table non-temporal, bit 1: Hessian diagonal
+   loads non-temporal, bit 2: the Krylov passes' stores of p, x
+   non-temporal, bit 3: loads and stores of the residual r non-temporal;
+   0..15).
    Variants: 0 default, 1 wide (a length without a wide variant runs the
    default); a shell-table choice runs the per-mode table when the spectrum
    is not radial. */
 #define PL_NUM_VARIANTS 7
 /* Current choices: out = the PL_NUM_VARIANTS choices for FP64, then FP32. */
 int pl_plan_get_variants(const pl_plan* plan, int32_t out[2 * PL_NUM_VARIANTS]);
-/* Force the choices (same order); each entry 0 or 1, streaming policy 0..7. */
+/* Force the choices (same order); each entry 0 or 1, streaming policy 0..15. */
 int pl_plan_set_variants(pl_plan* plan, const int32_t v[2 * PL_NUM_VARIANTS]);
 
 /* ---------------------------------------------------------------------------

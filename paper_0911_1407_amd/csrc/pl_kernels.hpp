@@ -26,13 +26,14 @@ constexpr int RED_THREADS = 256;
 // Krylov step can be loaded non-temporally, so that they do not displace
 // the pass-to-pass intermediate (each pass's input and output, default
 // policy) from the memory-side cache.  The nt field of the pass arguments
-// holds two bits: NT_VEC for the Krylov vectors r, p, x and the per-mode
-// 1/lambda table, NT_DIAG for the Hessian diagonal.  Which pays depends on
-// the working set against the cache, so it is a per-plan schedule choice.
-// With NT_STORE the Krylov passes also store r, p and x non-temporally
-// (those vectors are read again only by the next step's streaming loads);
-// the intermediate's stores keep the default policy.
-enum { NT_VEC = 1, NT_DIAG = 2, NT_STORE = 4 };
+// holds four bits: NT_VEC for the loads of the Krylov vectors p, x and of
+// the per-mode 1/lambda table, NT_DIAG for the Hessian diagonal, NT_STORE
+// for the Krylov passes' stores of p and x, NT_R for the residual r (its
+// loads and stores: when the vectors are small enough, r, read twice and
+// written once per step, is worth keeping cached beside the intermediate).
+// Which pays depends on the working set against the cache, so it is a
+// per-plan schedule choice.  The intermediate keeps the default policy.
+enum { NT_VEC = 1, NT_DIAG = 2, NT_STORE = 4, NT_R = 8, NT_ALL = 15 };
 
 // Posterior model of a solve: the lognormal prior on s = ln(1 + delta) with
 // the power-law bias (section 2.3, 2.4), or the Gaussian prior on delta with
@@ -188,7 +189,7 @@ struct ColArgs {
   cx<T>* cg_x;
   const double* scal;  // device scalars (SC_*)
   const double* skip;  // if non-null and *skip != 0 the launch does nothing
-  int nt;              // NT_VEC | NT_DIAG: operands loaded non-temporally (ld_stream)
+  int nt;              // NT_* bits: operands loaded / stored non-temporally
 };
 
 // Column tile width B: 256 threads per block where possible, at most 64 KB
@@ -256,7 +257,7 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
         long idx = base_off + (long)kx * a.row_stride;
         cx<T> pn = {T(0), T(0)};
         if (valid) {
-          cx<T> po = ld_stream(pio + idx, a.nt & NT_VEC), rv = ld_stream(a.cg_r + idx, a.nt & NT_VEC);
+          cx<T> po = ld_stream(pio + idx, a.nt & NT_VEC), rv = ld_stream(a.cg_r + idx, a.nt & NT_R);
           long mode = (long)kx * a.g.nyh + c;
           const T il = inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_VEC);
           const T mi = precond_inv<T>(il, dbar), bt = (T)beta;
@@ -337,9 +338,9 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
           T il = pre_il[q * RL + m];
           cx<T> x = v[q * RL + m];
           const T qx = x.x + il * pv.x, qy = x.y + il * pv.y, al = (T)alpha;
-          cx<T> rv = ld_stream(a.cg_r + mode, a.nt & NT_VEC), xv = ld_stream(a.cg_x + mode, a.nt & NT_VEC);
+          cx<T> rv = ld_stream(a.cg_r + mode, a.nt & NT_R), xv = ld_stream(a.cg_x + mode, a.nt & NT_VEC);
           cx<T> rn = {rv.x - al * qx, rv.y - al * qy};
-          st_stream(a.cg_r + mode, rn, a.nt & NT_STORE);
+          st_stream(a.cg_r + mode, rn, a.nt & NT_R);
           st_stream(a.cg_x + mode, cx<T>{xv.x + al * pv.x, xv.y + al * pv.y}, a.nt & NT_STORE);
           const T rr = rn.x * rn.x + rn.y * rn.y;
           acc[0] += hw * (double)rr;
@@ -460,7 +461,7 @@ struct RowArgs {
   double* d_out;
   double* partials;
   const double* skip;  // if non-null and *skip != 0 the launch does nothing
-  int nt;              // NT_VEC | NT_DIAG: operands loaded non-temporally (ld_stream)
+  int nt;              // NT_* bits: operands loaded / stored non-temporally
   int model;           // ROW_GRAD likelihood: MODEL_LOGNORMAL or MODEL_GAUSSIAN
 };
 

@@ -1472,7 +1472,7 @@ int tune_precision(pl_plan* p, const std::string& key, std::vector<std::string>&
       float t_cg, t_hvp;
       if (std::sscanf(line.c_str() + key.size(), "%d %d %d %d %d %d %d %f %f", &v[0], &v[1], &v[2], &v[3], &v[4],
                       &v[5], &v[6], &t_cg, &t_hvp) == V_COUNT + 2 &&
-          ((v[0] | v[1] | v[2] | v[3] | v[4] | v[5]) & ~1) == 0 && (v[V_NT] & ~(NT_VEC | NT_DIAG | NT_STORE)) == 0) {
+          ((v[0] | v[1] | v[2] | v[3] | v[4] | v[5]) & ~1) == 0 && (v[V_NT] & ~NT_ALL) == 0) {
         for (int i = 0; i < V_COUNT; ++i) p->var[pi][i] = v[i];
         return PL_OK;
       }
@@ -1483,7 +1483,7 @@ int tune_precision(pl_plan* p, const std::string& key, std::vector<std::string>&
   const int reps = p->N >= (1L << 24) ? 5 : 20;
   // the solver's CG step: x passes carrying the Krylov updates, y, z, and
   // the table those x passes read
-  const int cg_slots[5] = {V_XCG, V_Y, V_Z, V_TAB_CG, V_NT}, cg_max[5] = {mx, my, mr, mt, NT_VEC | NT_DIAG | NT_STORE};
+  const int cg_slots[5] = {V_XCG, V_Y, V_Z, V_TAB_CG, V_NT}, cg_max[5] = {mx, my, mr, mt, NT_ALL};
   float best_cg = 0.f, best_hvp = 0.f;
   int rc = tune_slots(p, pi, cg_slots, cg_max, 5, [&](float* ms) { return time_cg_step<T>(p, reps, ms); }, &best_cg);
   if (rc) return rc;
@@ -1550,7 +1550,7 @@ extern "C" int pl_plan_autotune(pl_plan* p, const char* cache_path) {
 extern "C" int pl_plan_set_variants(pl_plan* p, const int32_t v[2 * PL_NUM_VARIANTS]) {
   if (!p || !v) return PL_ERR_INVALID_ARG;
   for (int i = 0; i < 2 * V_COUNT; ++i) {
-    const int hi = (i % V_COUNT == V_NT) ? (NT_VEC | NT_DIAG | NT_STORE) : 1;
+    const int hi = (i % V_COUNT == V_NT) ? NT_ALL : 1;
     if (v[i] < 0 || v[i] > hi) return fail(p, PL_ERR_INVALID_ARG, "schedule choice out of range");
   }
   for (int pi = 0; pi < 2; ++pi)
