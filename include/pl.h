@@ -270,8 +270,9 @@ const char* pl_last_error(const pl_plan* plan);
    vectors stored, non-temporally so that the pass-to-pass intermediate
    stays in the memory-side cache, which pays when that intermediate fits
    there.  Times the solver's fused CG step (five passes) per combination of
-   the Krylov-carrying x variant, the y and z variants, the Krylov passes'
-   table and the streaming policy, then the
+   the Krylov-carrying x variant, the y and z variants and the Krylov
+   passes' table, then per streaming policy with those fixed, then the
+   tile and table choices again under that policy, then the
    isolated operator (pl_hessvec_hat) per
    combination of its own x variant and table, on the plan's workspace (after
    pl_set_problem; it overwrites the cached Hessian diagonal and the solver's
@@ -284,18 +285,17 @@ int pl_plan_autotune(pl_plan* plan, const char* cache_path);
 /* Number of schedule choices per precision.  In order: x variant of the
    Krylov-carrying passes, y variant, z variant, x variant of the operator's
    passes, table of the Krylov passes (1 shell, 0 per mode), table of the
-   operator's passes, streaming policy (bit 0: loads of the Krylov vectors
-   p, x and of the per-mode table non-temporal, bit 1: Hessian diagonal
-   loads non-temporal, bit 2: the Krylov passes' stores of p, x
-   non-temporal, bit 3: loads and stores of the residual r non-temporal;
-   0..15).
+   operator's passes, streaming policy (one bit per array, covering its
+   loads and stores: bit 0 residual r, bit 1 direction p and the operator's
+   input, bit 2 iterate x, bit 3 per-mode table, bit 4 Hessian diagonal;
+   0..31).
    Variants: 0 default, 1 wide (a length without a wide variant runs the
    default); a shell-table choice runs the per-mode table when the spectrum
    is not radial. */
 #define PL_NUM_VARIANTS 7
 /* Current choices: out = the PL_NUM_VARIANTS choices for FP64, then FP32. */
 int pl_plan_get_variants(const pl_plan* plan, int32_t out[2 * PL_NUM_VARIANTS]);
-/* Force the choices (same order); each entry 0 or 1, streaming policy 0..15. */
+/* Force the choices (same order); each entry 0 or 1, streaming policy 0..31. */
 int pl_plan_set_variants(pl_plan* plan, const int32_t v[2 * PL_NUM_VARIANTS]);
 
 /* ---------------------------------------------------------------------------

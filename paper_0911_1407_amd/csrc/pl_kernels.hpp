@@ -26,14 +26,15 @@ constexpr int RED_THREADS = 256;
 // Krylov step can be loaded non-temporally, so that they do not displace
 // the pass-to-pass intermediate (each pass's input and output, default
 // policy) from the memory-side cache.  The nt field of the pass arguments
-// holds four bits: NT_VEC for the loads of the Krylov vectors p, x and of
-// the per-mode 1/lambda table, NT_DIAG for the Hessian diagonal, NT_STORE
-// for the Krylov passes' stores of p and x, NT_R for the residual r (its
-// loads and stores: when the vectors are small enough, r, read twice and
-// written once per step, is worth keeping cached beside the intermediate).
-// Which pays depends on the working set against the cache, so it is a
-// per-plan schedule choice.  The intermediate keeps the default policy.
-enum { NT_VEC = 1, NT_DIAG = 2, NT_STORE = 4, NT_R = 8, NT_ALL = 15 };
+// holds one bit per array, covering its loads and stores in the Krylov and
+// operator passes: NT_R (residual r), NT_P (direction p, and the operator's
+// input), NT_X (iterate x), NT_TAB (per-mode 1/lambda table), NT_DIAG
+// (Hessian diagonal).  Which arrays are worth keeping cached beside the
+// intermediate depends on their size against the cache (all streamed at
+// 256^3 in FP64; r, read twice and written once per step, kept in FP32), so
+// the bits are a per-plan schedule choice.  The intermediate keeps the
+// default policy.
+enum { NT_R = 1, NT_P = 2, NT_X = 4, NT_TAB = 8, NT_DIAG = 16, NT_ALL = 31 };
 
 // Posterior model of a solve: the lognormal prior on s = ln(1 + delta) with
 // the power-law bias (section 2.3, 2.4), or the Gaussian prior on delta with
@@ -257,12 +258,12 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
         long idx = base_off + (long)kx * a.row_stride;
         cx<T> pn = {T(0), T(0)};
         if (valid) {
-          cx<T> po = ld_stream(pio + idx, a.nt & NT_VEC), rv = ld_stream(a.cg_r + idx, a.nt & NT_R);
+          cx<T> po = ld_stream(pio + idx, a.nt & NT_P), rv = ld_stream(a.cg_r + idx, a.nt & NT_R);
           long mode = (long)kx * a.g.nyh + c;
-          const T il = inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_VEC);
+          const T il = inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_TAB);
           const T mi = precond_inv<T>(il, dbar), bt = (T)beta;
           pn = {mi * rv.x + bt * po.x, mi * rv.y + bt * po.y};
-          st_stream(pio + idx, pn, a.nt & NT_STORE);
+          st_stream(pio + idx, pn, a.nt & NT_P);
           acc[0] += hw * (double)(il * (pn.x * pn.x + pn.y * pn.y));
         }
         v[q * R0 + r] = pn;
@@ -298,7 +299,7 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
         long mode = (long)kx * a.g.nyh + c;
         cx<T> x = v[q * RL + m];
         if (mode == 0) x.x -= (T)a.k0_shift;
-        T il = valid ? inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_VEC) : T(0);
+        T il = valid ? inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_TAB) : T(0);
         if (valid) acc[0] += herm_w(kz, a.g) * (double)il * ((double)x.x * x.x + (double)x.y * x.y);
         v[q * RL + m] = {x.x * il, x.y * il};
       }
@@ -319,8 +320,8 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
       for (int m = 0; m < RL; ++m) {
         int kx = out_pos<PL, PL::NS - 1>(t, q, m);
         long mode = (long)kx * a.g.nyh + c;
-        pre_p[q * RL + m] = valid ? ld_stream(a.base + mode, a.nt & NT_VEC) : cx<T>{T(0), T(0)};
-        pre_il[q * RL + m] = valid ? inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_VEC) : T(0);
+        pre_p[q * RL + m] = valid ? ld_stream(a.base + mode, a.nt & NT_P) : cx<T>{T(0), T(0)};
+        pre_il[q * RL + m] = valid ? inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_TAB) : T(0);
       }
     fft_thread<PL, false, MAP>(v, t, lds, a.tw, active);
     const double hw = herm_w(kz, a.g);
@@ -338,10 +339,10 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
           T il = pre_il[q * RL + m];
           cx<T> x = v[q * RL + m];
           const T qx = x.x + il * pv.x, qy = x.y + il * pv.y, al = (T)alpha;
-          cx<T> rv = ld_stream(a.cg_r + mode, a.nt & NT_R), xv = ld_stream(a.cg_x + mode, a.nt & NT_VEC);
+          cx<T> rv = ld_stream(a.cg_r + mode, a.nt & NT_R), xv = ld_stream(a.cg_x + mode, a.nt & NT_X);
           cx<T> rn = {rv.x - al * qx, rv.y - al * qy};
           st_stream(a.cg_r + mode, rn, a.nt & NT_R);
-          st_stream(a.cg_x + mode, cx<T>{xv.x + al * pv.x, xv.y + al * pv.y}, a.nt & NT_STORE);
+          st_stream(a.cg_x + mode, cx<T>{xv.x + al * pv.x, xv.y + al * pv.y}, a.nt & NT_X);
           const T rr = rn.x * rn.x + rn.y * rn.y;
           acc[0] += hw * (double)rr;
           acc[1] += hw * (double)(precond_inv<T>(il, dbar) * rr);
@@ -361,8 +362,8 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
       for (int m = 0; m < RL; ++m) {
         int kx = out_pos<PL, PL::NS - 1>(t, q, m);
         long mode = (long)kx * a.g.nyh + c;
-        pre_b[q * RL + m] = valid ? ld_stream(a.base + mode, a.nt & NT_VEC) : cx<T>{T(0), T(0)};
-        pre_il[q * RL + m] = valid ? inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_VEC) : T(0);
+        pre_b[q * RL + m] = valid ? ld_stream(a.base + mode, a.nt & NT_P) : cx<T>{T(0), T(0)};
+        pre_il[q * RL + m] = valid ? inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_TAB) : T(0);
       }
     fft_thread<PL, false, MAP>(v, t, lds, a.tw, active);
     double acc[3] = {0.0, 0.0, 0.0};

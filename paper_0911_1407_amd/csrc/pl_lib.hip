@@ -1481,11 +1481,20 @@ int tune_precision(pl_plan* p, const std::string& key, std::vector<std::string>&
   const int mx = has_wide_variant(p->n[0]) ? 1 : 0, my = has_wide_variant(p->n[1]) ? 1 : 0,
             mr = has_wide_variant(p->n[2]) ? 1 : 0, mt = p->radial ? 1 : 0;
   const int reps = p->N >= (1L << 24) ? 5 : 20;
-  // the solver's CG step: x passes carrying the Krylov updates, y, z, and
-  // the table those x passes read
-  const int cg_slots[5] = {V_XCG, V_Y, V_Z, V_TAB_CG, V_NT}, cg_max[5] = {mx, my, mr, mt, NT_ALL};
+  // the solver's CG step: first the tile variants of the x passes carrying
+  // the Krylov updates, y and z and the table those x passes read (default
+  // load/store policy), then the streaming policy with those fixed, then the
+  // tiles once more under that policy
+  const int cg_slots[4] = {V_XCG, V_Y, V_Z, V_TAB_CG}, cg_max[4] = {mx, my, mr, mt};
   float best_cg = 0.f, best_hvp = 0.f;
-  int rc = tune_slots(p, pi, cg_slots, cg_max, 5, [&](float* ms) { return time_cg_step<T>(p, reps, ms); }, &best_cg);
+  p->var[pi][V_NT] = 0;
+  int rc = tune_slots(p, pi, cg_slots, cg_max, 4, [&](float* ms) { return time_cg_step<T>(p, reps, ms); }, &best_cg);
+  if (rc) return rc;
+  const int nt_slot[1] = {V_NT}, nt_max[1] = {NT_ALL};
+  rc = tune_slots(p, pi, nt_slot, nt_max, 1, [&](float* ms) { return time_cg_step<T>(p, reps, ms); }, &best_cg);
+  if (rc) return rc;
+  // the tiles again, under the chosen policy
+  rc = tune_slots(p, pi, cg_slots, cg_max, 4, [&](float* ms) { return time_cg_step<T>(p, reps, ms); }, &best_cg);
   if (rc) return rc;
   // the isolated operator's x passes and their table
   const int op_slots[2] = {V_XOP, V_TAB_OP}, op_max[2] = {mx, mt};
