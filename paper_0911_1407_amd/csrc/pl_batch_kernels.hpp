@@ -139,7 +139,7 @@ __global__ void __launch_bounds__(RED_THREADS) dquant_hist_batch_kernel(const Ba
 }
 
 template <typename T>
-__global__ void dquant_select_batch_kernel(const BatchElem<T>* __restrict__ E) {
+__global__ void __launch_bounds__(DQ_SELECT_THREADS) dquant_select_batch_kernel(const BatchElem<T>* __restrict__ E) {
   const BatchElem<T> a = E[blockIdx.x];
   if (!a.active) return;
   dquant_select_body(a.hist, a.n, a.scal_rw);

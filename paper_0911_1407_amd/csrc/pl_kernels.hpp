@@ -1149,42 +1149,95 @@ __global__ void __launch_bounds__(RED_THREADS) ls_eval_gauss_kernel(const T* __r
 constexpr int DQ_BINS = 2048;
 constexpr float DQ_LO = -24.0f, DQ_HI = 24.0f;
 
-__device__ __forceinline__ void dquant_hist_body(const double* __restrict__ d, long n, const double* __restrict__ scal,
-                                                 int* __restrict__ hist, int bx, int nbx) {
-  __shared__ int h[DQ_BINS];
-  for (int i = threadIdx.x; i < DQ_BINS; i += blockDim.x) h[i] = 0;
-  __syncthreads();
-  const double mean = scal[SC_DSUM] / (double)n;
-  const float scale = (float)DQ_BINS / (DQ_HI - DQ_LO);
-  for (long i = bx * (long)blockDim.x + threadIdx.x; i < n; i += (long)nbx * blockDim.x) {
-    const double r = mean > 0.0 ? d[i] / mean : 0.0;
-    int b = 0;
-    if (r > 0.0) {
-      float x = (log2f((float)r) - DQ_LO) * scale;
-      b = x < 0.0f ? 0 : (x >= (float)(DQ_BINS - 1) ? DQ_BINS - 1 : (int)x);
-    }
-    atomicAdd(&h[b], 1);
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < DQ_BINS; i += blockDim.x)
-    if (h[i]) atomicAdd(&hist[i], h[i]);
+// One sub-histogram per wave (fewer same-address LDS atomics), four loads in
+// flight per thread before their bins are counted, d scaled by 1/mean.
+__device__ __forceinline__ int dquant_bin(double dv, double inv_mean) {
+  const double r = dv * inv_mean;
+  if (!(r > 0.0)) return 0;
+  const float x = (log2f((float)r) - DQ_LO) * ((float)DQ_BINS / (DQ_HI - DQ_LO));
+  return x < 0.0f ? 0 : (x >= (float)(DQ_BINS - 1) ? DQ_BINS - 1 : (int)x);
 }
 
-__device__ __forceinline__ void dquant_select_body(int* __restrict__ hist, long n, double* __restrict__ scal) {
-  if (threadIdx.x != 0) return;
+__device__ __forceinline__ void dquant_hist_body(const double* __restrict__ d, long n, const double* __restrict__ scal,
+                                                 int* __restrict__ hist, int bx, int nbx) {
+  constexpr int NW = RED_THREADS / 64;
+  __shared__ int h[NW * DQ_BINS];
+  for (int i = threadIdx.x; i < NW * DQ_BINS; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  int* hw = h + (threadIdx.x >> 6) * DQ_BINS;
   const double mean = scal[SC_DSUM] / (double)n;
-  const long target = (long)(0.25 * (double)n);
-  long acc = 0;
-  int b = 0;
-  for (; b < DQ_BINS; ++b) {
-    acc += hist[b];
-    if (acc > target) break;
+  const double inv_mean = mean > 0.0 ? 1.0 / mean : 0.0;
+  const long stride = (long)nbx * blockDim.x;
+  long i = bx * (long)blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const double v0 = d[i], v1 = d[i + stride], v2 = d[i + 2 * stride], v3 = d[i + 3 * stride];
+    atomicAdd(&hw[dquant_bin(v0, inv_mean)], 1);
+    atomicAdd(&hw[dquant_bin(v1, inv_mean)], 1);
+    atomicAdd(&hw[dquant_bin(v2, inv_mean)], 1);
+    atomicAdd(&hw[dquant_bin(v3, inv_mean)], 1);
   }
-  double c = 0.0;
-  if (b > 0 && b < DQ_BINS) c = mean * exp2((double)DQ_LO + ((double)b + 0.5) * (double)(DQ_HI - DQ_LO) / DQ_BINS);
-  if (c < 1e-3 * mean) c = 1e-3 * mean;
-  scal[SC_DBAR] = c;
-  for (int i = 0; i < DQ_BINS; ++i) hist[i] = 0;  // ready for the next use
+  for (; i < n; i += stride) atomicAdd(&hw[dquant_bin(d[i], inv_mean)], 1);
+  __syncthreads();
+  for (int b = threadIdx.x; b < DQ_BINS; b += blockDim.x) {
+    int c = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) c += h[w * DQ_BINS + b];
+    if (c) atomicAdd(&hist[b], c);
+  }
+}
+
+// Block of DQ_SELECT_THREADS: each thread owns DQ_BINS / DQ_SELECT_THREADS
+// consecutive bins; a block prefix sum finds the first bin whose cumulative
+// count exceeds n/4, and the histogram is cleared for its next use.
+constexpr int DQ_SELECT_THREADS = 256;
+__device__ __forceinline__ void dquant_select_body(int* __restrict__ hist, long n, double* __restrict__ scal) {
+  constexpr int PER = DQ_BINS / DQ_SELECT_THREADS;
+  static_assert(DQ_BINS % DQ_SELECT_THREADS == 0 && DQ_SELECT_THREADS % 64 == 0, "select block shape");
+  __shared__ long wave_tot[DQ_SELECT_THREADS / 64];
+  __shared__ int found;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  int v[PER];
+  long own = 0;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    v[j] = hist[t * PER + j];
+    own += v[j];
+  }
+  long incl = own;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const long y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) wave_tot[wv] = incl;
+  if (t == 0) found = DQ_BINS;
+  __syncthreads();
+  long acc = incl - own;
+  for (int w = 0; w < wv; ++w) acc += wave_tot[w];
+  const long target = (long)(0.25 * (double)n);
+  if (acc <= target && acc + own > target) {  // exactly one thread: cumulative counts are monotone
+    int b = t * PER;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      acc += v[j];
+      if (acc > target) {
+        b = t * PER + j;
+        break;
+      }
+    }
+    found = b;
+  }
+#pragma unroll
+  for (int j = 0; j < PER; ++j) hist[t * PER + j] = 0;  // ready for the next use
+  __syncthreads();
+  if (t == 0) {
+    const int b = found;
+    const double mean = scal[SC_DSUM] / (double)n;
+    double c = 0.0;
+    if (b > 0 && b < DQ_BINS) c = mean * exp2((double)DQ_LO + ((double)b + 0.5) * (double)(DQ_HI - DQ_LO) / DQ_BINS);
+    if (c < 1e-3 * mean) c = 1e-3 * mean;
+    scal[SC_DBAR] = c;
+  }
 }
 
 // d = beta^2 nbar w e^{beta s}, e = nbar w e^{beta s} (real-space input s)
@@ -1210,7 +1263,7 @@ __global__ void __launch_bounds__(RED_THREADS) dquant_hist_kernel(const double* 
   dquant_hist_body(d, n, scal, hist, blockIdx.x, gridDim.x);
 }
 
-__global__ void dquant_select_kernel(int* __restrict__ hist, long n, double* __restrict__ scal) {
+__global__ void __launch_bounds__(DQ_SELECT_THREADS) dquant_select_kernel(int* __restrict__ hist, long n, double* __restrict__ scal) {
   dquant_select_body(hist, n, scal);
 }
 

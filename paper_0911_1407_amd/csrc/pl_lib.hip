@@ -357,9 +357,9 @@ int grad_hat(pl_plan* p, double* s_out) {
 
 // Preconditioner constant from the current d (device only; see dquant_*).
 int set_precond_constant(pl_plan* p) {
-  hipLaunchKernelGGL(dquant_hist_kernel, dim3(256), dim3(RED_THREADS), 0, p->stream, p->d, p->N, p->scal, p->hist);
+  hipLaunchKernelGGL(dquant_hist_kernel, dim3(1024), dim3(RED_THREADS), 0, p->stream, p->d, p->N, p->scal, p->hist);
   HIPCHK(p, hipGetLastError());
-  hipLaunchKernelGGL(dquant_select_kernel, dim3(1), dim3(64), 0, p->stream, p->hist, p->N, p->scal);
+  hipLaunchKernelGGL(dquant_select_kernel, dim3(1), dim3(DQ_SELECT_THREADS), 0, p->stream, p->hist, p->N, p->scal);
   HIPCHK(p, hipGetLastError());
   return PL_OK;
 }
@@ -1995,7 +1995,7 @@ int batch_newton(pl_batch* b, double* const* s_io, const pl_solve_opts& o, pl_so
     hipLaunchKernelGGL((dquant_hist_batch_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream,
                        elems<T>(b, false));
     BHIP(b, hipGetLastError());
-    hipLaunchKernelGGL((dquant_select_batch_kernel<T>), dim3(K), dim3(64), 0, b->stream, elems<T>(b, false));
+    hipLaunchKernelGGL((dquant_select_batch_kernel<T>), dim3(K), dim3(DQ_SELECT_THREADS), 0, b->stream, elems<T>(b, false));
     BHIP(b, hipGetLastError());
     if constexpr (sizeof(T) == 4) {
       hipLaunchKernelGGL((d32_batch_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream, elems<T>(b, false));
