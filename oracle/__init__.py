@@ -30,6 +30,8 @@ What it computes (every function cites the passage it follows):
                    iteration (Corless et al. 1996), for closed-form pins.
 * ``gaussian``  -- the MAP of the Gaussian-prior model (section 2.2, unit
                    bias, eq. MAPG), the paper's comparison MAP filter.
+* ``linbias``   -- the MAP with the linear (non-local) bias of sections
+                   2.2.1 and 2.4.1, for the lognormal and the Gaussian prior.
 * ``prior``     -- the lognormal prior covariance and mean built from a
                    matter spectrum (section 2.3, S_L(r) = ln(1 + S(r)),
                    mu = -S_L(0)/2).

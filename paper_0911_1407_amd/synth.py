@@ -73,6 +73,14 @@ def power_shape_half(n, box, slope=-1.5, smooth=2.0):
     return pk
 
 
+def bias_multiplier_half(n, box, b0=1.0, smooth=3.0):
+    """Linear-bias multiplier b_hat(k) = b0 exp(-(smooth k)^2 / 2) on the half
+    spectrum: a galaxy field that is a smoothed copy of the matter field
+    (smooth in Mpc/h).  Deterministic and even in k."""
+    k = _kmag_half(n, box)
+    return b0 * np.exp(-0.5 * (smooth * k) ** 2)
+
+
 def amplitude_for_sigma(pk_shape, n, box, sigma):
     vol = box[0] * box[1] * box[2]
     total = float(np.sum(hermitian_multiplicity(n) * pk_shape)) / vol
