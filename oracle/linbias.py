@@ -118,13 +118,17 @@ def gradient(prob, bk, x, kind):
     return model.prior_apply(prob, x - prior_mean(prob, kind)) + dphi(kind, x) * bias_apply(bk, u)
 
 
-def hessvec(prob, bk, x, v, kind):
+def lik_hessvec(prob, bk, x, v, kind):
+    """Likelihood part of H v: phi'' (B u) v + phi' B [(N / y^2) B (phi' v)]."""
     y = galaxy_field(prob, bk, x, kind)
     u = prob.nbar * prob.w - np.where(prob.counts > 0, prob.counts / y, 0.0)
     W = np.where(prob.counts > 0, prob.counts / y ** 2, 0.0)
     a = dphi(kind, x)
-    return (model.prior_apply(prob, v) + d2phi(kind, x) * bias_apply(bk, u) * v
-            + a * bias_apply(bk, W * bias_apply(bk, a * v)))
+    return d2phi(kind, x) * bias_apply(bk, u) * v + a * bias_apply(bk, W * bias_apply(bk, a * v))
+
+
+def hessvec(prob, bk, x, v, kind):
+    return model.prior_apply(prob, v) + lik_hessvec(prob, bk, x, v, kind)
 
 
 # ---------------------------------------------------------------------------
@@ -213,7 +217,8 @@ def truncated_pcg(prob, bk, x, kind, g_hat, tol_abs, max_cg):
     for k in range(max_cg):
         if np.sqrt(_dot(cw, N, r, r)) <= tol_abs:
             break
-        q = dft.rfftn(hessvec(prob, bk, x, dft.irfftn(p, n), kind))
+        # H p with the prior term as an exact pointwise product (section 2.3)
+        q = inv_lam * p + dft.rfftn(lik_hessvec(prob, bk, x, dft.irfftn(p, n), kind))
         pq = _dot(cw, N, p, q)
         if pq <= 0.0:
             if k == 0:
@@ -230,18 +235,26 @@ def truncated_pcg(prob, bk, x, kind, g_hat, tol_abs, max_cg):
     return sol, its
 
 
-def _armijo(prob, bk, x, p, g, kind, c1=1e-4, max_halvings=60):
+def _spectral_grad(prob, bk, x_hat, kind, inv_lam, m_hat):
+    """Real field x = F^-1 x_hat and the gradient spectrum
+    g_hat = (x_hat - m_hat) / lambda + F[phi'(x) B u]: with the iterate held
+    as its spectrum the prior term is an exact pointwise product (section 2.3:
+    S^-1 is diagonal in Fourier space), so the gradient has no FFT-roundoff
+    floor from the large 1/lambda of high-k modes."""
+    x = dft.irfftn(x_hat, prob.n)
+    y = galaxy_field(prob, bk, x, kind)
+    u = prob.nbar * prob.w - np.where(prob.counts > 0, prob.counts / y, 0.0)
+    return x, inv_lam * (x_hat - m_hat) + dft.rfftn(dphi(kind, x) * bias_apply(bk, u))
+
+
+def _armijo(prob, bk, x, p, b, c, slope, kind, c1=1e-4, max_halvings=60):
     """Armijo backtracking from a = 1 (halving) on the decrease in difference
     form: a b + a^2 c / 2 + sum_i [nbar w_i dy_i - N_i log1p(dy_i / y_i)] with
     b = p^T S^-1 (x - m), c = p^T S^-1 p and dy = B (phi(x + a p) - phi(x))
     (phi(x + a p) - phi(x) = exp(x) expm1(a p) for the lognormal prior); a step
     that leaves y <= 0 in a cell with counts is rejected."""
-    slope = float(np.sum(g * p))
     if slope >= 0:
         return None
-    Sp = model.prior_apply(prob, p)
-    b = float(np.sum((x - prior_mean(prob, kind)) * Sp))
-    c = float(np.sum(p * Sp))
     y = galaxy_field(prob, bk, x, kind)
     pos = prob.counts > 0
     a = 1.0
@@ -258,35 +271,43 @@ def _armijo(prob, bk, x, p, g, kind, c1=1e-4, max_halvings=60):
 
 
 def newton_spectral(prob, bk, kind, rtol=1e-12, max_newton=200, max_cg=20000, eta_max=0.5):
-    """Inexact Newton with the truncated PCG, from x0 = m (uniform).  Returns
-    (x, info) with info = dict(newton_its, cg_its, status, rel_grad)."""
-    n = prob.n
-    x = np.full(n, prior_mean(prob, kind))
-    g = gradient(prob, bk, x, kind)
-    g0 = np.linalg.norm(g)
+    """Inexact Newton with the truncated PCG, from x0 = m (uniform), the
+    iterate held as its half spectrum.  Returns (x, info) with info =
+    dict(newton_its, cg_its, status, rel_grad); norms are those of the
+    spectral gradient (Parseval)."""
+    n, N = prob.n, prob.ncells
+    cw = hermitian_weights(n)
+    inv_lam = inv_lambda_half(prob)
+    m_hat = np.zeros(inv_lam.shape, dtype=np.complex128)
+    m_hat[0, 0, 0] = N * prior_mean(prob, kind)
+    x_hat = dft.rfftn(np.full(n, prior_mean(prob, kind)))
+    x, g_hat = _spectral_grad(prob, bk, x_hat, kind, inv_lam, m_hat)
+    gn = g0 = np.sqrt(_dot(cw, N, g_hat, g_hat))
     info = {"newton_its": 0, "cg_its": 0, "status": "ok", "rel_grad": 0.0}
     if g0 == 0.0:
         return x, info
     for it in range(max_newton):
-        gn = np.linalg.norm(g)
         if gn <= rtol * g0:
             break
         eta = min(eta_max, max(np.sqrt(gn / g0), 0.5 * rtol * g0 / gn))
-        g_hat = dft.rfftn(g)
         p_hat, its = truncated_pcg(prob, bk, x, kind, g_hat, eta * gn, max_cg)
         info["cg_its"] += its
-        p = dft.irfftn(p_hat, n)
-        a = _armijo(prob, bk, x, p, g, kind)
+        Sp = inv_lam * p_hat
+        b = _dot(cw, N, Sp, x_hat - m_hat)
+        c = _dot(cw, N, Sp, p_hat)
+        slope = _dot(cw, N, g_hat, p_hat)
+        a = _armijo(prob, bk, x, dft.irfftn(p_hat, n), b, c, slope, kind)
         if a is None:
             info["status"] = "linesearch"
             break
-        x = x + a * p
-        g = gradient(prob, bk, x, kind)
+        x_hat = x_hat + a * p_hat
+        x, g_hat = _spectral_grad(prob, bk, x_hat, kind, inv_lam, m_hat)
+        gn = np.sqrt(_dot(cw, N, g_hat, g_hat))
         info["newton_its"] = it + 1
     else:
-        if np.linalg.norm(g) > rtol * g0:
+        if gn > rtol * g0:
             info["status"] = "not_converged"
-    info["rel_grad"] = float(np.linalg.norm(g) / g0)
+    info["rel_grad"] = float(gn / g0)
     return x, info
 
 
