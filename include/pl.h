@@ -192,6 +192,51 @@ int pl_solve_adjoint(pl_plan* plan, const double* s_star, const double* dL_ds, d
    inv_p0 > 0 or some counts > 0.  Synchronises the stream. */
 int pl_gaussian_map_solve(pl_plan* plan, double* delta_inout, const pl_solve_opts* opts, pl_solve_info* info);
 
+/* Linear (non-local) bias, sections 2.2.1 and 2.4.1: the galaxy overdensity
+   is delta_g = B delta_M, B the convolution whose Fourier multiplier is the
+   real table bk (device, [nx][ny][nz/2+1] doubles like pk; the paper's
+   b_hat(k) = sqrt(P_g(k) / P_M(k)); it must satisfy bk(-k) = bk(k), which
+   makes B symmetric), and expected counts are nbar w (1 + B delta_M).
+   model selects the prior and the unknown x:
+     PL_MODEL_LOGNORMAL  x = s = ln(1 + delta_M), prior mean mu, covariance
+                         S_L = amp * pk (section 2.3);
+     PL_MODEL_GAUSSIAN   x = delta_M, zero mean, covariance amp * pk
+                         (section 2.2).
+   With y = 1 + B delta_M(x) the negative log-posterior (constants dropped) is
+     f(x) = 1/2 (x - m)^T S^-1 (x - m) + sum_i [nbar w_i y_i - N_i ln y_i],
+   its gradient S^-1 (x - m) + delta_M'(x) B (nbar w - N / y) (the left minus
+   the right side of the linear-bias MAP equations), its Hessian
+     S^-1 + diag(delta_M''(x) B u) + diag(delta_M') B diag(N / y^2) B diag(delta_M')
+   with u = nbar w - N / y.  The domain is y > 0 in every cell with counts
+   (NaN or inf outside it; PL_ERR_DOMAIN where a solve starts outside).  The
+   problem's beta must be 1 (this bias replaces the power law;
+   PL_ERR_INVALID_ARG otherwise).  FP64 only; any plan precision.  bk == 1
+   everywhere reproduces the unit-bias models up to the constant
+   sum_i nbar w_i in f. */
+#define PL_MODEL_LOGNORMAL 0
+#define PL_MODEL_GAUSSIAN 1
+/* grad_out (device, N) = g(x) at the real field x (device, N); *obj_out
+   (host, nullable) = f(x); synchronises only when obj_out is given. */
+int pl_linear_bias_grad(pl_plan* plan, int model, const double* bk, const double* x, double* grad_out,
+                        double* obj_out);
+/* hv_out (device, N) = H(x) v.  x (device, N) may be NULL to reuse the
+   linearisation of the previous pl_linear_bias_grad / pl_linear_bias_hessvec
+   call with the same model and bk, if no other call has used the plan since
+   (PL_ERR_NO_PROBLEM otherwise).  Asynchronous. */
+int pl_linear_bias_hessvec(pl_plan* plan, int model, const double* bk, const double* x, const double* v,
+                           double* hv_out);
+/* MAP by inexact Newton with a truncated PCG (stopped at the forcing
+   tolerance or at the first direction of non-positive curvature; the
+   preconditioned steepest-descent direction if that is the first one),
+   preconditioner 1/lambda_k + c bk_k^2 (c the 25th percentile of the
+   per-cell curvature), Armijo backtracking from a = 1 (at most 40 halvings)
+   that keeps the iterate in the domain.  x_inout: device, N, the start on
+   input (mu or 0, the prior mean, is the usual one) and the MAP on output.
+   Options and info as pl_newton_krylov_solve; opts->precision must not be
+   PL_MIXED.  Synchronises the stream. */
+int pl_linear_bias_solve(pl_plan* plan, int model, const double* bk, double* x_inout, const pl_solve_opts* opts,
+                         pl_solve_info* info);
+
 /* The Krylov step of section 3.1 with a nonlinear-CG search vector, the
    paper-literal form of the solver: s <- s + tau xi with the step length of
    eq. (New5), tau = -xi^T grad Q / xi^T H xi (one HVP per step).  The paper

@@ -35,7 +35,13 @@ EXPORTED = ("pl_default_opts", "pl_plan_create", "pl_plan_set_workspace", "pl_pl
             "pl_batch_solve", "pl_batch_destroy", "pl_batch_last_error", "pl_plan_autotune",
             "pl_plan_get_variants", "pl_plan_set_variants", "pl_plan_prior_is_radial", "pl_lsq_solve", "pl_nlcg_solve", "pl_lognormal_prior",
             "pl_gaussian_map_solve",
-            "pl_inverse_weight", "pl_compare_fields")
+            "pl_inverse_weight", "pl_compare_fields", "pl_linear_bias_grad", "pl_linear_bias_hessvec",
+            "pl_linear_bias_solve")
+
+# priors of the linear-bias calls (PL_MODEL_* in pl.h)
+MODEL_LOGNORMAL = 0
+MODEL_GAUSSIAN = 1
+MODELS = {"lognormal": MODEL_LOGNORMAL, "gaussian": MODEL_GAUSSIAN}
 
 BATCH_LENGTHS = (32, 48, 64, 96, 128)
 
@@ -117,6 +123,10 @@ def load(path=LIB_PATH):
     lib.pl_inverse_weight.argtypes = [vp, vp]
     lib.pl_compare_fields.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.pl_plan_set_variants.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.pl_linear_bias_grad.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(dbl)]
+    lib.pl_linear_bias_hessvec.argtypes = [vp, i32, vp, vp, vp, vp]
+    lib.pl_linear_bias_solve.argtypes = [vp, i32, vp, vp, ctypes.POINTER(pl_solve_opts),
+                                         ctypes.POINTER(pl_solve_info)]
     lib.pl_batch_last_error.argtypes = [vp]
     lib.pl_batch_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -239,6 +249,25 @@ def pl_gaussian_map_solve(h, delta_inout, opts=None):
     info = pl_solve_info()
     rc = load().pl_gaussian_map_solve(h, _ptr(delta_inout), ctypes.byref(opts) if opts else None,
                                       ctypes.byref(info))
+    _check(h, rc, allow=(PL_ERR_NOT_CONVERGED, PL_ERR_LINESEARCH))
+    return info
+
+
+def pl_linear_bias_grad(h, model, bk, x, grad_out, want_obj=True):
+    obj = ctypes.c_double()
+    _check(h, load().pl_linear_bias_grad(h, int(model), _ptr(bk), _ptr(x), _ptr(grad_out),
+                                         ctypes.byref(obj) if want_obj else None))
+    return obj.value if want_obj else None
+
+
+def pl_linear_bias_hessvec(h, model, bk, x, v, hv_out):
+    return _check(h, load().pl_linear_bias_hessvec(h, int(model), _ptr(bk), _ptr(x), _ptr(v), _ptr(hv_out)))
+
+
+def pl_linear_bias_solve(h, model, bk, x_inout, opts=None):
+    info = pl_solve_info()
+    rc = load().pl_linear_bias_solve(h, int(model), _ptr(bk), _ptr(x_inout), ctypes.byref(opts) if opts else None,
+                                     ctypes.byref(info))
     _check(h, rc, allow=(PL_ERR_NOT_CONVERGED, PL_ERR_LINESEARCH))
     return info
 
@@ -451,6 +480,37 @@ class Plan:
             d = self._dev(delta0).clone()
         info = pl_gaussian_map_solve(self.h, d, make_opts(**kw))
         return d, info.as_dict()
+
+    def _model(self, model):
+        return MODELS[model] if isinstance(model, str) else int(model)
+
+    def linear_bias_grad(self, model, bk, x, out=None):
+        """Gradient and objective of the linear-bias posterior at x (sections
+        2.2.1 / 2.4.1); model "lognormal" (x = s) or "gaussian" (x = delta)."""
+        x, bk = self._dev(x), self._dev(bk)
+        out = self.torch.empty_like(x) if out is None else out
+        obj = pl_linear_bias_grad(self.h, self._model(model), bk, x, out)
+        return out, obj
+
+    def linear_bias_hessvec(self, model, bk, v, x=None, out=None):
+        v, bk = self._dev(v), self._dev(bk)
+        out = self.torch.empty_like(v) if out is None else out
+        pl_linear_bias_hessvec(self.h, self._model(model), bk, None if x is None else self._dev(x), v, out)
+        return out
+
+    def solve_linear_bias(self, model, bk, x0=None, **kw):
+        """MAP with the linear bias b_hat (bk, half spectrum): (x, info); the
+        start defaults to the prior mean (mu, or 0 for the Gaussian prior)."""
+        m = self._model(model)
+        bk = self._dev(bk)
+        if x0 is None:
+            mu = float(self.params["mu"]) if (self.params and m == MODEL_LOGNORMAL) else 0.0
+            x = self.torch.full(self.n, mu, dtype=self.torch.float64, device=self.device)
+        else:
+            x = self._dev(x0).clone()
+        kw.setdefault("precision", 0)
+        info = pl_linear_bias_solve(self.h, m, bk, x, make_opts(**kw))
+        return x, info.as_dict()
 
     def solve_nlcg(self, s0=None, **kw):
         """MAP by the Krylov step with nonlinear-CG search vectors (FP64)."""

@@ -14,6 +14,7 @@
 #define PL_OPS_KERNELS 1
 #include "pl_batch_kernels.hpp"
 #include "pl_passes.hpp"
+#include "pl_linbias_kernels.hpp"
 
 using namespace pl;
 
@@ -79,6 +80,11 @@ struct pl_plan {
   // posterior model of the running solve (MODEL_*); the lognormal one
   // except inside pl_gaussian_map_solve
   int model = MODEL_LOGNORMAL;
+  // the linear-bias linearisation (e, d, rtmp) is current for this model and
+  // b_hat table; any other entry point clears it
+  bool lb_ready = false;
+  int lb_model = -1;
+  const double* lb_bk = nullptr;
   std::string err;
 };
 
@@ -356,8 +362,9 @@ int grad_hat(pl_plan* p, double* s_out) {
 }
 
 // Preconditioner constant from the current d (device only; see dquant_*).
-int set_precond_constant(pl_plan* p) {
-  hipLaunchKernelGGL(dquant_hist_kernel, dim3(1024), dim3(RED_THREADS), 0, p->stream, p->d, p->N, p->scal, p->hist);
+int set_precond_constant(pl_plan* p, const double* d = nullptr) {
+  hipLaunchKernelGGL(dquant_hist_kernel, dim3(1024), dim3(RED_THREADS), 0, p->stream, d ? d : p->d, p->N, p->scal,
+                     p->hist);
   HIPCHK(p, hipGetLastError());
   hipLaunchKernelGGL(dquant_select_kernel, dim3(1), dim3(DQ_SELECT_THREADS), 0, p->stream, p->hist, p->N, p->scal);
   HIPCHK(p, hipGetLastError());
@@ -465,6 +472,7 @@ int pcg(pl_plan* p, const cx<double>* rhs, double sign, double tol_abs, double t
 
 int check_ready(pl_plan* p) {
   if (!p) return PL_ERR_INVALID_ARG;
+  p->lb_ready = false;
   if (!p->ws) return fail(p, PL_ERR_INVALID_ARG, "workspace not set");
   if (!p->has_problem) return fail(p, PL_ERR_NO_PROBLEM, "pl_set_problem has not been called");
   return PL_OK;
@@ -977,6 +985,7 @@ int pl_plan_set_workspace(pl_plan* p, void* dev_ptr) {
   if (!p) return PL_ERR_INVALID_ARG;
   if (!dev_ptr || ((uintptr_t)dev_ptr & 255)) return fail(p, PL_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
   p->ws = (char*)dev_ptr;
+  p->lb_ready = false;
   carve(p, p->ws);
   for (int a = 0; a < 3; ++a) {
     auto t64 = make_twiddles<double>(p->n[a]);
@@ -1015,6 +1024,7 @@ const char* pl_last_error(const pl_plan* p) {
 
 int pl_set_problem(pl_plan* p, const pl_problem* pr) {
   if (!p || !pr) return PL_ERR_INVALID_ARG;
+  p->lb_ready = false;
   if (!p->ws) return fail(p, PL_ERR_INVALID_ARG, "workspace not set");
   if (!pr->w || !pr->counts || !pr->pk) return fail(p, PL_ERR_INVALID_ARG, "null problem array");
   if (!(pr->amp > 0.0) || !std::isfinite(pr->amp)) return fail(p, PL_ERR_DOMAIN, "amp must be > 0");
@@ -1248,6 +1258,7 @@ int pl_nlcg_solve(pl_plan* p, double* s_inout, const pl_solve_opts* opts, pl_sol
 int pl_lognormal_prior(pl_plan* p, const double* pk, double amp, double* pk_log_out, double* mu_out,
                        double* sigma0_sq_out, int64_t* n_clipped_out) {
   if (!p) return PL_ERR_INVALID_ARG;
+  p->lb_ready = false;
   if (!p->ws) return fail(p, PL_ERR_INVALID_ARG, "workspace not set");
   if (!pk || !pk_log_out) return fail(p, PL_ERR_INVALID_ARG, "null pointer");
   if (!(amp > 0.0) || !std::isfinite(amp)) return fail(p, PL_ERR_DOMAIN, "amp must be finite and > 0");
@@ -2265,6 +2276,403 @@ int pl_batch_destroy(pl_batch* b) {
 const char* pl_batch_last_error(const pl_batch* b) {
   if (!b) return "null batch";
   return b->err.c_str();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Linear (non-local) bias, sections 2.2.1 and 2.4.1: delta_g = B delta_M with
+// B the convolution of Fourier multiplier b_hat.  The unknown x is s =
+// ln(1 + delta_M) (lognormal prior, MODEL_LOGNORMAL) or delta_M itself
+// (Gaussian prior, MODEL_GAUSSIAN); phi(x) = delta_M, y = 1 + B phi(x).
+//   f = 1/2 (x - m)^T S^-1 (x - m) + sum_i [nbar w_i y_i - N_i ln y_i]
+//   g = S^-1 (x - m) + phi' B u,                u = nbar w - N / y
+//   H = S^-1 + diag(phi'' B u) + diag(phi') B diag(N / y^2) B diag(phi')
+// (B = B^T for a real, even b_hat).  Real-field workspace during a solve:
+// e = phi' (lognormal), d = phi'' B u (lognormal), rtmp = y, s_ws the
+// pointwise chain, preal the real copy of a spectral operand.
+// ---------------------------------------------------------------------------
+namespace {
+
+// The x pass with the caller's table (run_col substitutes the prior's)
+hipError_t run_col_own_table(pl_plan* p, bool inverse, int op, const ColArgs<double>& a, int* nb) {
+  int dummy;
+  return launch_col<double>(p->n[0], inverse, op, a, 1, p->stream, nb ? nb : &dummy, p->var[0][V_XOP]);
+}
+
+// out = B in for real fields: z r2c, y forward, the x pass's forward
+// transform, multiply by b_hat and inverse transform, y inverse, z c2r.
+int lb_conv(pl_plan* p, const double* bk, const double* in, double* out) {
+  cx<double>* t = p->t64;
+  RowArgs<double> ra = row_args<double>(p);
+  ra.in_r = in;
+  ra.out_c = t;
+  HIPCHK(p, run_row<double>(p, ROW_R2C, ra, nullptr));
+  HIPCHK(p, run_col<double>(p, 1, false, COL_PLAIN, col_args<double>(p, 1, t, t), nullptr));
+  ColArgs<double> ca = col_args<double>(p, 0, t, t);
+  ca.inv_lam = bk;
+  ca.radial = 0;
+  ca.k0_shift = 0.0;
+  HIPCHK(p, run_col_own_table(p, false, COL_PRIOR, ca, nullptr));
+  HIPCHK(p, run_col<double>(p, 1, true, COL_PLAIN, col_args<double>(p, 1, t, t), nullptr));
+  RowArgs<double> rb = row_args<double>(p);
+  rb.in_c = t;
+  rb.out_r = out;
+  HIPCHK(p, run_row<double>(p, ROW_C2R, rb, nullptr));
+  return PL_OK;
+}
+
+// Linearisation at the real field x: e = phi'(x) (lognormal), rtmp = y,
+// SC_LIK = the likelihood sum, s_ws = l = phi' B u, d = phi'' B u (lognormal).
+int lb_linearize(pl_plan* p, int model, const double* bk, const double* x) {
+  const int nb = grid_blocks(p->N);
+  hipLaunchKernelGGL(lb_phi_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, x, nullptr, 0.0, model, p->s_ws,
+                     model == MODEL_LOGNORMAL ? p->e : nullptr, p->N);
+  HIPCHK(p, hipGetLastError());
+  int rc = lb_conv(p, bk, p->s_ws, p->s_ws);
+  if (rc) return rc;
+  hipLaunchKernelGGL(lb_lik_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->s_ws, p->prob.w, p->prob.counts,
+                     p->prob.nbar, p->rtmp, p->N, p->partials);
+  HIPCHK(p, hipGetLastError());
+  HIPCHK(p, finalize(p, nb, 1, FIN_STORE, SC_LIK, 1.0));
+  rc = lb_conv(p, bk, p->s_ws, p->s_ws);
+  if (rc) return rc;
+  hipLaunchKernelGGL(lb_grad_pointwise_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->s_ws, p->e, model, p->d,
+                     p->N);
+  HIPCHK(p, hipGetLastError());
+  p->d_valid = false;  // d no longer holds the power-law model's diagonal
+  p->d32_valid = false;
+  p->lb_ready = true;
+  p->lb_model = model;
+  p->lb_bk = bk;
+  return PL_OK;
+}
+
+// g_out = (x_hat - m_hat) / lambda + F l (l in s_ws); SC_GG = ||g||^2 and
+// SC_PRIOR = (x - m)^T S^-1 (x - m), as the power-law gradient leaves them.
+int lb_assemble_grad(pl_plan* p, const cx<double>* x_hat, cx<double>* g_out) {
+  cx<double>* t = p->t64;
+  RowArgs<double> ra = row_args<double>(p);
+  ra.in_r = p->s_ws;
+  ra.out_c = t;
+  HIPCHK(p, run_row<double>(p, ROW_R2C, ra, nullptr));
+  HIPCHK(p, run_col<double>(p, 1, false, COL_PLAIN, col_args<double>(p, 1, t, t), nullptr));
+  ColArgs<double> ca = col_args<double>(p, 0, t, g_out);
+  ca.base = x_hat;
+  ca.k0_shift = (double)p->N * prior_mean(p);
+  int nb = 0;
+  HIPCHK(p, run_col<double>(p, 0, false, COL_ADDPRIOR, ca, &nb));
+  HIPCHK(p, finalize(p, nb, 3, FIN_STORE, SC_GG - 1, 1.0 / (double)p->N));
+  return PL_OK;
+}
+
+// out = H pin on half spectra at the current linearisation; out may be t64.
+int lb_hvp_hat(pl_plan* p, int model, const double* bk, const cx<double>* pin, cx<double>* out) {
+  const int nb = grid_blocks(p->N);
+  int rc = inv_c2r<double>(p, pin, p->t64, p->preal);  // q = F^-1 pin
+  if (rc) return rc;
+  const double* src = p->preal;
+  if (model == MODEL_LOGNORMAL) {
+    hipLaunchKernelGGL(lb_mul_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->e, p->preal, p->s_ws, p->N);
+    HIPCHK(p, hipGetLastError());
+    src = p->s_ws;
+  }
+  rc = lb_conv(p, bk, src, p->s_ws);
+  if (rc) return rc;
+  hipLaunchKernelGGL(lb_weight_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->s_ws, p->rtmp, p->prob.counts,
+                     p->N);
+  HIPCHK(p, hipGetLastError());
+  rc = lb_conv(p, bk, p->s_ws, p->s_ws);
+  if (rc) return rc;
+  if (model == MODEL_LOGNORMAL) {
+    hipLaunchKernelGGL(lb_combine_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->s_ws, p->preal, p->d, p->e,
+                       p->N);
+    HIPCHK(p, hipGetLastError());
+  }
+  cx<double>* t = p->t64;
+  RowArgs<double> ra = row_args<double>(p);
+  ra.in_r = p->s_ws;
+  ra.out_c = t;
+  HIPCHK(p, run_row<double>(p, ROW_R2C, ra, nullptr));
+  HIPCHK(p, run_col<double>(p, 1, false, COL_PLAIN, col_args<double>(p, 1, t, t), nullptr));
+  ColArgs<double> ca = col_args<double>(p, 0, t, out);
+  ca.base = pin;
+  ca.k0_shift = 0.0;
+  HIPCHK(p, run_col<double>(p, 0, false, COL_ADDPRIOR, ca, nullptr));
+  return PL_OK;
+}
+
+// Preconditioner constant c of M_k = 1/lambda_k + c b_hat_k^2: the 25th
+// percentile of the per-cell curvature (lb_curv_kernel), as for the
+// power-law model.
+int lb_precond(pl_plan* p, int model) {
+  const int nb = grid_blocks(p->N);
+  hipLaunchKernelGGL(lb_curv_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->e, p->rtmp, p->prob.counts, p->d,
+                     model, p->preal, p->N);
+  HIPCHK(p, hipGetLastError());
+  hipLaunchKernelGGL(sum_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->preal, p->N, p->partials);
+  HIPCHK(p, hipGetLastError());
+  HIPCHK(p, finalize(p, nb, 1, FIN_STORE, SC_DSUM, 1.0));
+  return set_precond_constant(p, p->preal);
+}
+
+// Truncated PCG on H x = -g (g_hat) into x64: stops at ||r|| <= tol_abs or at
+// the first direction of non-positive curvature; if that is the first
+// direction, x = M^-1 (-g) (preconditioned steepest descent).  Host-driven,
+// two scalar read-backs per iteration.
+int lb_pcg(pl_plan* p, int model, const double* bk, double tol_abs, int max_cg, int* its_out, int* hv_out) {
+  cx<double>*x = p->x64, *r = p->r64, *pp = p->p64, *q = p->t64;
+  const double* tab = p->radial ? p->tab_rad : p->tab_mode;
+  const double invN = 1.0 / (double)p->N;
+  const int nb = grid_blocks(p->Nh);
+  hipLaunchKernelGGL(lb_cg_init_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->g_hat, x, r, pp, tab, p->radial,
+                     p->g, bk, p->scal, p->Nh, p->partials);
+  HIPCHK(p, hipGetLastError());
+  HIPCHK(p, finalize(p, nb, 2, FIN_STORE, SC_DF, invN));
+  int rc = read_scalars(p);
+  if (rc) return rc;
+  double rz = p->h_scal[SC_DF], rr = p->h_scal[SC_DF + 1];
+  int its = 0, hv = 0;
+  for (int k = 0; k < max_cg; ++k) {
+    if (!(std::sqrt(std::max(0.0, rr)) > tol_abs)) break;
+    rc = lb_hvp_hat(p, model, bk, pp, q);
+    if (rc) return rc;
+    ++hv;
+    hipLaunchKernelGGL(lb_dot_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, pp, q, p->g, p->Nh, p->partials);
+    HIPCHK(p, hipGetLastError());
+    HIPCHK(p, finalize(p, nb, 1, FIN_STORE, SC_PQ, invN));
+    rc = read_scalars(p);
+    if (rc) return rc;
+    const double pq = p->h_scal[SC_PQ];
+    if (!(pq > 0.0)) {
+      if (its == 0) HIPCHK(p, hipMemcpyAsync(x, pp, sizeof(cx<double>) * p->Nh, hipMemcpyDeviceToDevice, p->stream));
+      break;
+    }
+    const double alpha = rz / pq;
+    hipLaunchKernelGGL(lb_cg_update_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, x, r, pp, q, alpha, tab,
+                       p->radial, p->g, bk, p->scal, p->Nh, p->partials);
+    HIPCHK(p, hipGetLastError());
+    HIPCHK(p, finalize(p, nb, 2, FIN_STORE, SC_DF, invN));
+    rc = read_scalars(p);
+    if (rc) return rc;
+    ++its;
+    const double rz_new = p->h_scal[SC_DF];
+    rr = p->h_scal[SC_DF + 1];
+    if (!(std::sqrt(std::max(0.0, rr)) > tol_abs)) break;
+    const double beta = rz_new / rz;
+    rz = rz_new;
+    hipLaunchKernelGGL(lb_cg_dir_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, r, pp, beta, tab, p->radial, p->g,
+                       bk, p->scal, p->Nh);
+    HIPCHK(p, hipGetLastError());
+  }
+  *its_out = its;
+  *hv_out = hv;
+  return PL_OK;
+}
+
+// Armijo backtracking along x64 from s_hat (real field x_real): the decrease
+// a b + a^2 c / 2 + sum_i [nbar w_i dy_i - N_i log1p(dy_i / y_i)], with
+// dy = B (phi(x + a p) - phi(x)), against c1 a p^T g for a = 1, 1/2, ...
+// (at most 40 halvings).  *alpha = the step or -1; *descent = (p^T g < 0).
+int lb_line_search(pl_plan* p, int model, const double* bk, const double* x_real, const pl_solve_opts& o,
+                   double* alpha, bool* descent) {
+  const double invN = 1.0 / (double)p->N;
+  cx<double>* x = p->x64;
+  int rc = inv_c2r<double>(p, x, p->t64, p->preal);
+  if (rc) return rc;
+  hipLaunchKernelGGL((ls_dots_kernel<double>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, x, p->s_hat, p->g_hat,
+                     p->radial ? p->tab_rad : p->tab_mode, p->radial, p->g, p->Nh, (double)p->N * prior_mean(p),
+                     p->partials);
+  HIPCHK(p, hipGetLastError());
+  HIPCHK(p, finalize(p, NB_RED, 3, FIN_STORE, SC_LS_B, invN));
+  rc = read_scalars(p);
+  if (rc) return rc;
+  const double b = p->h_scal[SC_LS_B], c = p->h_scal[SC_LS_C], slope = p->h_scal[SC_LS_SLOPE];
+  *alpha = -1.0;
+  *descent = slope < 0.0;
+  if (!(slope < 0.0)) return PL_OK;
+  const int nb = grid_blocks(p->N);
+  double a = 1.0;
+  for (int j = 0; j < 40; ++j, a *= 0.5) {
+    hipLaunchKernelGGL(lb_phi_step_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, x_real, p->preal, a, model,
+                       p->s_ws, p->N);
+    HIPCHK(p, hipGetLastError());
+    rc = lb_conv(p, bk, p->s_ws, p->s_ws);
+    if (rc) return rc;
+    hipLaunchKernelGGL(lb_step_lik_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->s_ws, p->rtmp, p->prob.w,
+                       p->prob.counts, p->prob.nbar, p->N, p->partials);
+    HIPCHK(p, hipGetLastError());
+    HIPCHK(p, finalize(p, nb, 1, FIN_STORE, SC_DF, 1.0));
+    rc = read_scalars(p);
+    if (rc) return rc;
+    const double df = a * b + 0.5 * a * a * c + p->h_scal[SC_DF];
+    if (df <= o.ls_c1 * a * slope) {
+      *alpha = a;
+      break;
+    }
+  }
+  return PL_OK;
+}
+
+// Gradient at the spectral iterate s_hat: x_real = F^-1 s_hat, the
+// linearisation there, g_hat.
+int lb_grad_hat(pl_plan* p, int model, const double* bk, double* x_real) {
+  int rc = inv_c2r<double>(p, p->s_hat, p->t64, x_real);
+  if (rc) return rc;
+  rc = lb_linearize(p, model, bk, x_real);
+  if (rc) return rc;
+  return lb_assemble_grad(p, p->s_hat, p->g_hat);
+}
+
+int lb_newton_solve(pl_plan* p, int model, const double* bk, double* x_io, const pl_solve_opts& o,
+                    pl_solve_info* info) {
+  pl_solve_info inf{};
+  int rc = fwd_r2c<double>(p, x_io, p->s_hat);
+  if (rc) return rc;
+  rc = lb_grad_hat(p, model, bk, x_io);
+  if (rc) return rc;
+  rc = read_scalars(p);
+  if (rc) return rc;
+  const double g0 = std::sqrt(std::max(0.0, p->h_scal[SC_GG]));
+  double gn = g0;
+  double obj = 0.5 * p->h_scal[SC_PRIOR] + p->h_scal[SC_LIK];
+  inf.grad0 = g0;
+  inf.obj = obj;
+  if (!std::isfinite(g0) || !std::isfinite(obj)) {
+    if (info) *info = inf;
+    return fail(p, PL_ERR_DOMAIN, "the start is outside the domain (1 + B delta <= 0 in a cell with counts)");
+  }
+  int status = PL_OK;
+  if (g0 > 0.0) {
+    for (int it = 0;; ++it) {
+      if (gn <= o.rtol * g0) break;
+      if (it >= o.max_newton) {
+        status = PL_ERR_NOT_CONVERGED;
+        p->err = "Newton iteration cap reached";
+        break;
+      }
+      const double eta = std::min(o.eta_max, std::max(std::sqrt(gn / g0), 0.5 * o.rtol * g0 / gn));
+      rc = lb_precond(p, model);
+      if (rc) return rc;
+      int its = 0, hv = 0;
+      rc = lb_pcg(p, model, bk, eta * gn, o.max_cg, &its, &hv);
+      if (rc) return rc;
+      inf.cg_its += its;
+      inf.hvps += hv;
+      double alpha = -1.0;
+      bool descent = false;
+      rc = lb_line_search(p, model, bk, x_io, o, &alpha, &descent);
+      if (rc) return rc;
+      if (alpha < 0.0) {
+        status = PL_ERR_LINESEARCH;
+        p->err = descent ? "no step satisfies the Armijo condition" : "Newton direction is not a descent direction";
+        break;
+      }
+      hipLaunchKernelGGL((axpy_hat_kernel<double>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, p->s_hat, p->x64,
+                         alpha, p->Nh);
+      HIPCHK(p, hipGetLastError());
+      rc = lb_grad_hat(p, model, bk, x_io);
+      if (rc) return rc;
+      rc = read_scalars(p);
+      if (rc) return rc;
+      gn = std::sqrt(std::max(0.0, p->h_scal[SC_GG]));
+      obj = 0.5 * p->h_scal[SC_PRIOR] + p->h_scal[SC_LIK];
+      inf.newton_its = it + 1;
+      if (!std::isfinite(gn)) {
+        status = PL_ERR_DOMAIN;
+        p->err = "gradient became non-finite";
+        break;
+      }
+    }
+  }
+  inf.rel_grad = g0 > 0.0 ? gn / g0 : 0.0;
+  inf.obj = obj;
+  inf.status = status;
+  if (info) *info = inf;
+  return status;
+}
+
+static_assert(PL_MODEL_LOGNORMAL == MODEL_LOGNORMAL && PL_MODEL_GAUSSIAN == MODEL_GAUSSIAN, "model codes");
+
+int lb_check(pl_plan* p, int model, const double* bk) {
+  if (model != MODEL_LOGNORMAL && model != MODEL_GAUSSIAN) return fail(p, PL_ERR_INVALID_ARG, "unknown model");
+  if (!bk) return fail(p, PL_ERR_INVALID_ARG, "null b_hat table");
+  if (p->prob.beta != 1.0)
+    return fail(p, PL_ERR_INVALID_ARG, "the linear bias replaces the power-law bias: the problem needs beta = 1");
+  return check_finite(p, bk, p->Nh, "b_hat");
+}
+
+}  // namespace
+
+extern "C" {
+
+int pl_linear_bias_grad(pl_plan* p, int model, const double* bk, const double* x, double* grad_out,
+                        double* obj_out) {
+  int rc = check_ready(p);
+  if (rc) return rc;
+  if (!x || !grad_out) return fail(p, PL_ERR_INVALID_ARG, "null pointer");
+  rc = lb_check(p, model, bk);
+  if (rc) return rc;
+  p->model = model;
+  rc = fwd_r2c<double>(p, x, p->x64);
+  if (!rc) rc = lb_linearize(p, model, bk, x);
+  if (!rc) rc = lb_assemble_grad(p, p->x64, p->r64);
+  if (!rc) rc = inv_c2r<double>(p, p->r64, p->t64, grad_out);
+  p->model = MODEL_LOGNORMAL;
+  if (rc) return rc;
+  if (obj_out) {
+    rc = read_scalars(p);
+    if (rc) return rc;
+    *obj_out = 0.5 * p->h_scal[SC_PRIOR] + p->h_scal[SC_LIK];
+  }
+  return PL_OK;
+}
+
+int pl_linear_bias_hessvec(pl_plan* p, int model, const double* bk, const double* x, const double* v,
+                           double* hv_out) {
+  if (!p) return PL_ERR_INVALID_ARG;
+  const bool cached = p->lb_ready && p->lb_model == model && p->lb_bk == bk;
+  int rc = check_ready(p);
+  if (rc) return rc;
+  if (!v || !hv_out) return fail(p, PL_ERR_INVALID_ARG, "null pointer");
+  rc = lb_check(p, model, bk);
+  if (rc) return rc;
+  if (!x && !cached)
+    return fail(p, PL_ERR_NO_PROBLEM, "no linearisation to reuse: pass x or call pl_linear_bias_grad first");
+  if (x) {
+    rc = lb_linearize(p, model, bk, x);
+    if (rc) return rc;
+  }
+  p->model = model;
+  rc = fwd_r2c<double>(p, v, p->x64);
+  if (!rc) rc = lb_hvp_hat(p, model, bk, p->x64, p->r64);
+  if (!rc) rc = inv_c2r<double>(p, p->r64, p->t64, hv_out);
+  p->model = MODEL_LOGNORMAL;
+  if (rc) return rc;
+  p->lb_ready = true;
+  p->lb_model = model;
+  p->lb_bk = bk;
+  return PL_OK;
+}
+
+int pl_linear_bias_solve(pl_plan* p, int model, const double* bk, double* x_inout, const pl_solve_opts* opts,
+                         pl_solve_info* info) {
+  int rc = check_ready(p);
+  if (rc) return rc;
+  if (!x_inout) return fail(p, PL_ERR_INVALID_ARG, "null pointer");
+  pl_solve_opts o = resolve_opts(p, opts);
+  if (!(o.rtol >= 0.0) || o.max_newton < 0 || o.max_cg <= 0 || !(o.eta_max > 0.0) || !(o.ls_c1 > 0.0 && o.ls_c1 < 1.0))
+    return fail(p, PL_ERR_INVALID_ARG, "invalid solve options");
+  if (opts && opts->precision == PL_MIXED)
+    return fail(p, PL_ERR_INVALID_ARG, "the linear-bias solve runs in FP64 only");
+  rc = lb_check(p, model, bk);
+  if (rc) return rc;
+  rc = check_finite(p, x_inout, p->N, "x_inout");
+  if (rc) return rc;
+  p->model = model;
+  rc = lb_newton_solve(p, model, bk, x_inout, o, info);
+  p->model = MODEL_LOGNORMAL;
+  return rc;
 }
 
 }  // extern "C"
