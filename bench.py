@@ -19,6 +19,9 @@ Also reported (not part of `value`):
   adjoint       -- adjoint solve of L = sum (s* - s_true)^2 at the MAP
   nlcg          -- the paper-literal Krylov step (eq. New5 step length,
                    nonlinear-CG search vectors), FP64, same tolerance
+  linear_bias   -- the MAP with a non-local linear bias (a smoothing b_hat),
+                   lognormal and Gaussian priors: solve time and the
+                   real-space HVP with its byte model
   estimators    -- the paper's comparison estimators (Gaussian-prior MAP,
                    LSQ-Wiener filter, inverse weighting, lognormal prior
                    construction) with the correlation coefficient and
@@ -90,6 +93,23 @@ def hvp_bytes(n, p, spectral=True):
     if spectral:
         return p * N + 22 * p * Nh
     return 4 * p * N + 16 * p * Nh
+
+
+def linear_bias_hvp_bytes(n, lognormal):
+    """Algorithmic FP64 bytes of one real-space linear-bias HVP with a cached
+    linearisation (pl_linear_bias_hessvec, x = NULL): v to half spectrum (3
+    passes), the spectral HVP (back to real space, phi' times, two
+    convolutions B of 5 passes each with N / y^2 between them, phi'' B u and
+    phi' terms, forward with the prior added), and back to real space."""
+    N = n[0] * n[1] * n[2]
+    Nh = n[0] * n[1] * (n[2] // 2 + 1)
+    fwd = (8 * N + 16 * Nh) + 32 * Nh + 32 * Nh          # z r2c, y, x
+    inv = 32 * Nh + 32 * Nh + (16 * Nh + 8 * N)          # x, y, z c2r
+    conv = (8 * N + 16 * Nh) + 32 * Nh + 40 * Nh + 32 * Nh + (16 * Nh + 8 * N)  # x pass reads the b_hat table
+    hvp = inv + 2 * conv + 32 * N + (8 * N + 16 * Nh) + 32 * Nh + 48 * Nh  # weight; last z r2c, y, x + prior
+    if lognormal:
+        hvp += 24 * N + 40 * N  # phi' q; d1 q + phi' g2
+    return fwd + hvp + inv
 
 
 def main():
@@ -287,6 +307,40 @@ def main():
     print(f"# lsq fp64 {1e3 * t_lsq:.1f} ms ({linfo['cg_its']} its), mixed {1e3 * t_lsq32:.1f} ms "
           f"({linfo32['cg_its']} its); quality {quality}", file=sys.stderr, flush=True)
 
+    # ---------------- linear (non-local) bias (sections 2.2.1, 2.4.1) ----------------
+    # b_hat(k) = exp(-(1.5 cells k)^2 / 2): the galaxy field as the matter
+    # field smoothed over 1.5 cells; both priors, FP64, same tolerance
+    cell = inst["box"][0] / n[0]
+    bk = torch.from_numpy(synth.bias_multiplier_half(n, inst["box"], 1.0, 1.5 * cell)).to(dev)
+    linear_bias = {"b_hat": "exp(-(1.5 cells * k)^2 / 2)"}
+    v_real = torch.from_numpy(v).to(dev)
+    hv_real = torch.empty_like(v_real)
+    for model, x_lin in (("lognormal", s_true), ("gaussian", torch.expm1(s_true))):
+        plan.linear_bias_grad(model, bk, x_lin)
+        for _ in range(5):
+            plan.linear_bias_hessvec(model, bk, v_real, out=hv_real)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(21)]
+        ev[0].record(stream)
+        for i in range(20):
+            plan.linear_bias_hessvec(model, bk, v_real, out=hv_real)
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        ms_lb = float(np.median(sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(20))))
+        bytes_lb = linear_bias_hvp_bytes(n, model == "lognormal")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x_lb, lbinfo = plan.solve_linear_bias(model, bk, rtol=rtol, max_newton=200, max_cg=20000)
+        torch.cuda.synchronize()
+        t_lb = time.perf_counter() - t0
+        linear_bias[model] = {"solve_ms_fp64": 1e3 * t_lb, "newton_its": lbinfo["newton_its"],
+                              "cg_its": lbinfo["cg_its"], "hvps": lbinfo["hvps"], "status": lbinfo["status"],
+                              "rel_grad": lbinfo["rel_grad"], "hvp_real_ms": ms_lb,
+                              "hvp_real_bytes": bytes_lb, "hvp_real_gbs": bytes_lb / (ms_lb * 1e-3) / 1e9}
+        print(f"# linear bias {model}: solve {1e3 * t_lb:.1f} ms ({lbinfo['newton_its']} Newton, "
+              f"{lbinfo['cg_its']} CG, status {lbinfo['status']}), real-space HVP {ms_lb:.3f} ms "
+              f"({bytes_lb / (ms_lb * 1e-3) / 1e9:.0f} GB/s)", file=sys.stderr, flush=True)
+
     # ---------------- batched workload ----------------
     batch = None
     if not args.no_batch and args.workload == "sel256" and args.n is None:
@@ -391,6 +445,7 @@ def main():
                     "dL_dnbar": grads["nbar"]},
         "nlcg": nlcg,
         "estimators": estimators,
+        "linear_bias": linear_bias,
         "batched": batch,
         "cpu_baseline": cpu,
     }
