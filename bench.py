@@ -98,15 +98,18 @@ def hvp_bytes(n, p, spectral=True):
 def linear_bias_hvp_bytes(n, lognormal):
     """Algorithmic FP64 bytes of one real-space linear-bias HVP with a cached
     linearisation (pl_linear_bias_hessvec, x = NULL): v to half spectrum (3
-    passes), the spectral HVP (back to real space, phi' times, two
-    convolutions B of 5 passes each with N / y^2 between them, phi'' B u and
-    phi' terms, forward with the prior added), and back to real space."""
+    passes); the spectral HVP: back to real space (3), phi' times, z r2c, y,
+    x(b_hat), y^-1, the z pass c2r / times N/y^2 / r2c, y, x(b_hat), y^-1,
+    z c2r, phi'' B u q + phi' g2, forward with the prior added (3); and back
+    to real space (3)."""
     N = n[0] * n[1] * n[2]
     Nh = n[0] * n[1] * (n[2] // 2 + 1)
     fwd = (8 * N + 16 * Nh) + 32 * Nh + 32 * Nh          # z r2c, y, x
     inv = 32 * Nh + 32 * Nh + (16 * Nh + 8 * N)          # x, y, z c2r
-    conv = (8 * N + 16 * Nh) + 32 * Nh + 40 * Nh + 32 * Nh + (16 * Nh + 8 * N)  # x pass reads the b_hat table
-    hvp = inv + 2 * conv + 32 * N + (8 * N + 16 * Nh) + 32 * Nh + 48 * Nh  # weight; last z r2c, y, x + prior
+    xmul = 40 * Nh                                       # x pass, reads the b_hat table
+    gn = (8 * N + 16 * Nh) + 32 * Nh + xmul + 32 * Nh + (32 * Nh + 8 * N) + 32 * Nh + xmul + 32 * Nh \
+        + (16 * Nh + 8 * N)
+    hvp = inv + gn + (8 * N + 16 * Nh) + 32 * Nh + 48 * Nh
     if lognormal:
         hvp += 24 * N + 40 * N  # phi' q; d1 q + phi' g2
     return fwd + hvp + inv

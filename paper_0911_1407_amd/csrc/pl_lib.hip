@@ -2289,8 +2289,9 @@ const char* pl_batch_last_error(const pl_batch* b) {
 //   g = S^-1 (x - m) + phi' B u,                u = nbar w - N / y
 //   H = S^-1 + diag(phi'' B u) + diag(phi') B diag(N / y^2) B diag(phi')
 // (B = B^T for a real, even b_hat).  Real-field workspace during a solve:
-// e = phi' (lognormal), d = phi'' B u (lognormal), rtmp = y, s_ws the
-// pointwise chain, preal the real copy of a spectral operand.
+// e = phi' (lognormal), d = phi'' B u (lognormal), rtmp = N / y^2, s_ws the
+// pointwise chain, preal the real copy of a spectral operand.  The line
+// search holds B phi(x) in e while it runs.
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -2322,7 +2323,7 @@ int lb_conv(pl_plan* p, const double* bk, const double* in, double* out) {
   return PL_OK;
 }
 
-// Linearisation at the real field x: e = phi'(x) (lognormal), rtmp = y,
+// Linearisation at the real field x: e = phi'(x) (lognormal), rtmp = N / y^2,
 // SC_LIK = the likelihood sum, s_ws = l = phi' B u, d = phi'' B u (lognormal).
 int lb_linearize(pl_plan* p, int model, const double* bk, const double* x) {
   const int nb = grid_blocks(p->N);
@@ -2366,10 +2367,24 @@ int lb_assemble_grad(pl_plan* p, const cx<double>* x_hat, cx<double>* g_out) {
   return PL_OK;
 }
 
+// The x pass F_x^-1 diag(b_hat) F_x on a field already transformed along y and z
+int lb_xmul(pl_plan* p, const double* bk) {
+  ColArgs<double> ca = col_args<double>(p, 0, p->t64, p->t64);
+  ca.inv_lam = bk;
+  ca.radial = 0;
+  ca.k0_shift = 0.0;
+  HIPCHK(p, run_col_own_table(p, false, COL_PRIOR, ca, nullptr));
+  return PL_OK;
+}
+
 // out = H pin on half spectra at the current linearisation; out may be t64.
+// The Gauss-Newton part B diag(N/y^2) B runs as z r2c, y, x(b_hat), y^-1,
+// z (c2r, times N/y^2, r2c: the HVP z pass with rtmp as its diagonal), y,
+// x(b_hat), y^-1, z c2r.
 int lb_hvp_hat(pl_plan* p, int model, const double* bk, const cx<double>* pin, cx<double>* out) {
   const int nb = grid_blocks(p->N);
-  int rc = inv_c2r<double>(p, pin, p->t64, p->preal);  // q = F^-1 pin
+  cx<double>* t = p->t64;
+  int rc = inv_c2r<double>(p, pin, t, p->preal);  // q = F^-1 pin
   if (rc) return rc;
   const double* src = p->preal;
   if (model == MODEL_LOGNORMAL) {
@@ -2377,19 +2392,36 @@ int lb_hvp_hat(pl_plan* p, int model, const double* bk, const cx<double>* pin, c
     HIPCHK(p, hipGetLastError());
     src = p->s_ws;
   }
-  rc = lb_conv(p, bk, src, p->s_ws);
-  if (rc) return rc;
-  hipLaunchKernelGGL(lb_weight_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->s_ws, p->rtmp, p->prob.counts,
-                     p->N);
-  HIPCHK(p, hipGetLastError());
-  rc = lb_conv(p, bk, p->s_ws, p->s_ws);
-  if (rc) return rc;
+  {
+    RowArgs<double> ra = row_args<double>(p);
+    ra.in_r = src;
+    ra.out_c = t;
+    HIPCHK(p, run_row<double>(p, ROW_R2C, ra, nullptr));
+  }
+  HIPCHK(p, run_col<double>(p, 1, false, COL_PLAIN, col_args<double>(p, 1, t, t), nullptr));
+  if ((rc = lb_xmul(p, bk))) return rc;
+  HIPCHK(p, run_col<double>(p, 1, true, COL_PLAIN, col_args<double>(p, 1, t, t), nullptr));
+  {
+    RowArgs<double> ra = row_args<double>(p);
+    ra.in_c = t;
+    ra.out_c = t;
+    ra.d = p->rtmp;
+    HIPCHK(p, run_row<double>(p, ROW_HVP, ra, nullptr));
+  }
+  HIPCHK(p, run_col<double>(p, 1, false, COL_PLAIN, col_args<double>(p, 1, t, t), nullptr));
+  if ((rc = lb_xmul(p, bk))) return rc;
+  HIPCHK(p, run_col<double>(p, 1, true, COL_PLAIN, col_args<double>(p, 1, t, t), nullptr));
+  {
+    RowArgs<double> ra = row_args<double>(p);
+    ra.in_c = t;
+    ra.out_r = p->s_ws;
+    HIPCHK(p, run_row<double>(p, ROW_C2R, ra, nullptr));
+  }
   if (model == MODEL_LOGNORMAL) {
     hipLaunchKernelGGL(lb_combine_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->s_ws, p->preal, p->d, p->e,
                        p->N);
     HIPCHK(p, hipGetLastError());
   }
-  cx<double>* t = p->t64;
   RowArgs<double> ra = row_args<double>(p);
   ra.in_r = p->s_ws;
   ra.out_c = t;
@@ -2407,8 +2439,8 @@ int lb_hvp_hat(pl_plan* p, int model, const double* bk, const cx<double>* pin, c
 // power-law model.
 int lb_precond(pl_plan* p, int model) {
   const int nb = grid_blocks(p->N);
-  hipLaunchKernelGGL(lb_curv_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->e, p->rtmp, p->prob.counts, p->d,
-                     model, p->preal, p->N);
+  hipLaunchKernelGGL(lb_curv_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->e, p->rtmp, p->d, model, p->preal,
+                     p->N);
   HIPCHK(p, hipGetLastError());
   hipLaunchKernelGGL(sum_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->preal, p->N, p->partials);
   HIPCHK(p, hipGetLastError());
@@ -2492,6 +2524,13 @@ int lb_line_search(pl_plan* p, int model, const double* bk, const double* x_real
   *descent = slope < 0.0;
   if (!(slope < 0.0)) return PL_OK;
   const int nb = grid_blocks(p->N);
+  // B phi(x) into e (phi' is recomputed by the next gradient)
+  p->lb_ready = false;
+  hipLaunchKernelGGL(lb_phi_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, x_real, nullptr, 0.0, model, p->s_ws,
+                     nullptr, p->N);
+  HIPCHK(p, hipGetLastError());
+  rc = lb_conv(p, bk, p->s_ws, p->e);
+  if (rc) return rc;
   double a = 1.0;
   for (int j = 0; j < 40; ++j, a *= 0.5) {
     hipLaunchKernelGGL(lb_phi_step_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, x_real, p->preal, a, model,
@@ -2499,7 +2538,7 @@ int lb_line_search(pl_plan* p, int model, const double* bk, const double* x_real
     HIPCHK(p, hipGetLastError());
     rc = lb_conv(p, bk, p->s_ws, p->s_ws);
     if (rc) return rc;
-    hipLaunchKernelGGL(lb_step_lik_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->s_ws, p->rtmp, p->prob.w,
+    hipLaunchKernelGGL(lb_step_lik_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->s_ws, p->e, p->prob.w,
                        p->prob.counts, p->prob.nbar, p->N, p->partials);
     HIPCHK(p, hipGetLastError());
     HIPCHK(p, finalize(p, nb, 1, FIN_STORE, SC_DF, 1.0));

@@ -35,35 +35,37 @@ __global__ void __launch_bounds__(RED_THREADS) lb_phi_step_kernel(const double* 
     out[i] = model == MODEL_LOGNORMAL ? exp(s[i]) * expm1(a * x[i]) : a * x[i];
 }
 
-// From b = B phi: y = 1 + b (stored), the likelihood sum
+// From b = B phi, with y = 1 + b: the likelihood sum
 // sum_i [nbar w_i y_i - N_i ln y_i] (NaN or inf outside the domain y > 0 in
-// cells with counts) and u = nbar w - N / y, written over b.
+// cells with counts), the Poisson weight N / y^2 (stored) and
+// u = nbar w - N / y, written over b.
 __global__ void __launch_bounds__(RED_THREADS) lb_lik_kernel(double* __restrict__ b_u, const double* __restrict__ w,
                                                              const double* __restrict__ counts, double nbar,
-                                                             double* __restrict__ y_out, long n,
+                                                             double* __restrict__ wt_out, long n,
                                                              double* __restrict__ partials) {
   double acc[1] = {0.0};
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
     const double y = 1.0 + b_u[i], nw = nbar * w[i], c = counts[i];
-    y_out[i] = y;
+    const double iy = c > 0.0 ? 1.0 / y : 0.0;
+    wt_out[i] = c * iy * iy;
     acc[0] += nw * y - (c > 0.0 ? c * log(y) : 0.0);
-    b_u[i] = nw - (c > 0.0 ? c / y : 0.0);
+    b_u[i] = nw - c * iy;
   }
   block_reduce_store<1>(acc, partials, blockIdx.x);
 }
 
-// Likelihood part of f(x + a p) - f(x) from dy = B (phi(x + a p) - phi(x)):
-// sum_i [nbar w_i dy_i - N_i log1p(dy_i / y_i)]; NaN or inf (rejected by
-// the Armijo test) where the step leaves the domain.
+// Likelihood part of f(x + a p) - f(x) from dy = B (phi(x + a p) - phi(x))
+// and b0 = B phi(x) (y = 1 + b0): sum_i [nbar w_i dy_i - N_i log1p(dy_i / y_i)];
+// NaN or inf (rejected by the Armijo test) where the step leaves the domain.
 __global__ void __launch_bounds__(RED_THREADS) lb_step_lik_kernel(const double* __restrict__ dy,
-                                                                  const double* __restrict__ y,
+                                                                  const double* __restrict__ b0,
                                                                   const double* __restrict__ w,
                                                                   const double* __restrict__ counts, double nbar,
                                                                   long n, double* __restrict__ partials) {
   double acc[1] = {0.0};
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
     const double d = dy[i], c = counts[i];
-    acc[0] += nbar * w[i] * d - (c > 0.0 ? c * log1p(d / y[i]) : 0.0);
+    acc[0] += nbar * w[i] * d - (c > 0.0 ? c * log1p(d / (1.0 + b0[i])) : 0.0);
   }
   block_reduce_store<1>(acc, partials, blockIdx.x);
 }
@@ -89,15 +91,6 @@ __global__ void __launch_bounds__(RED_THREADS) lb_mul_kernel(const double* __res
     out[i] = a[i] * b[i];
 }
 
-// v <- (N / y^2) v  (the Poisson curvature in the galaxy field)
-__global__ void __launch_bounds__(RED_THREADS) lb_weight_kernel(double* __restrict__ v, const double* __restrict__ y,
-                                                                const double* __restrict__ counts, long n) {
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const double c = counts[i], yi = y[i];
-    v[i] = c > 0.0 ? c / (yi * yi) * v[i] : 0.0;
-  }
-}
-
 // g2 <- d1 q + phi' g2 (lognormal Hessian: diagonal part plus the outer
 // factor of the Gauss-Newton part)
 __global__ void __launch_bounds__(RED_THREADS) lb_combine_kernel(double* __restrict__ g2, const double* __restrict__ q,
@@ -108,15 +101,13 @@ __global__ void __launch_bounds__(RED_THREADS) lb_combine_kernel(double* __restr
 }
 
 // Representative curvature per cell for the preconditioner constant:
-// max(0, phi'^2 N / y^2 + d1) (lognormal), N / y^2 (Gaussian).
+// max(0, phi'^2 N / y^2 + d1) (lognormal), N / y^2 (Gaussian); wt = N / y^2.
 __global__ void __launch_bounds__(RED_THREADS) lb_curv_kernel(const double* __restrict__ dphi,
-                                                              const double* __restrict__ y,
-                                                              const double* __restrict__ counts,
+                                                              const double* __restrict__ wt,
                                                               const double* __restrict__ d1, int model,
                                                               double* __restrict__ out, long n) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const double c = counts[i], yi = y[i];
-    const double gn = c > 0.0 ? c / (yi * yi) : 0.0;
+    const double gn = wt[i];
     double v = gn;
     if (model == MODEL_LOGNORMAL) {
       const double a = dphi[i];
