@@ -401,7 +401,14 @@ def main():
             if time.perf_counter() - t0 > 15.0 or reps >= 40:
                 break
         t_cpu = (time.perf_counter() - t0) / reps
+        cpu_model = None
+        try:
+            with open("/proc/cpuinfo") as f:
+                cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+        except OSError:
+            pass
         cpu = {"value": 1.0 / t_cpu, "unit": "HVP/s", "cores": os.cpu_count(), "kind": "oracle",
+               "cpu_model": cpu_model,
                "sample": f"{reps} oracle spectral HVPs (scipy rfftn/irfftn, FP64) on the same "
                          f"{n[0]}^3 data at s = s_true; elementwise numpy single-threaded"}
         print(f"# cpu oracle HVP {1e3 * t_cpu:.0f} ms", file=sys.stderr, flush=True)
