@@ -203,3 +203,23 @@ def test_error_paths():
     # the plan still solves the power-law model afterwards
     s, info = plan.solve(rtol=1e-8, precision=0)
     assert info["status"] == 0
+
+
+@pytest.mark.parametrize("kind", [LN, GA])
+def test_no_data_returns_prior_mean(kind):
+    # w = 0 and N = 0 everywhere: the likelihood vanishes, the gradient at the
+    # prior mean is zero and the solve returns it after no iteration; from
+    # another start with inv_p0 > 0 it reaches the prior mean
+    inst = _inst((16, 16, 16), 4.0, inv_p0=0.5)
+    inst["w"] = np.zeros(inst["n"])
+    inst["counts"] = np.zeros(inst["n"])
+    bk = _bk(inst)
+    plan = _plan(inst)
+    m = inst["mu"] if kind == LN else 0.0
+    x, info = plan.solve_linear_bias(kind, bk, rtol=1e-10)
+    assert info["status"] == 0 and info["newton_its"] == 0, info
+    assert np.abs(x.cpu().numpy() - m).max() <= 1e-14
+    x0 = m + 0.1 * np.random.default_rng(4).standard_normal(inst["n"])
+    x, info = plan.solve_linear_bias(kind, bk, x0=x0, rtol=1e-12)
+    assert info["status"] == 0, info
+    assert np.abs(x.cpu().numpy() - m).max() <= 1e-10
