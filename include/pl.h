@@ -228,8 +228,8 @@ int pl_linear_bias_hessvec(pl_plan* plan, int model, const double* bk, const dou
 /* MAP by inexact Newton with a truncated PCG (stopped at the forcing
    tolerance or at the first direction of non-positive curvature; the
    preconditioned steepest-descent direction if that is the first one),
-   preconditioner 1/lambda_k + c bk_k^2 (c the 25th percentile of the
-   per-cell curvature), Armijo backtracking from a = 1 (at most 40 halvings)
+   preconditioner 1/lambda_k + c (c the 25th percentile of the per-cell
+   curvature), Armijo backtracking from a = 1 (at most 40 halvings)
    that keeps the iterate in the domain.  x_inout: device, N, the start on
    input (mu or 0, the prior mean, is the usual one) and the MAP on output.
    Options and info as pl_newton_krylov_solve; opts->precision must not be

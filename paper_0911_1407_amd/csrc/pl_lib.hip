@@ -2378,14 +2378,31 @@ int lb_xmul(pl_plan* p, const double* bk) {
 }
 
 // out = H pin on half spectra at the current linearisation; out may be t64.
-// The Gauss-Newton part B diag(N/y^2) B runs as z r2c, y, x(b_hat), y^-1,
-// z (c2r, times N/y^2, r2c: the HVP z pass with rtmp as its diagonal), y,
-// x(b_hat), y^-1, z c2r.
-int lb_hvp_hat(pl_plan* p, int model, const double* bk, const cx<double>* pin, cx<double>* out) {
+// With cg_r, the first x pass is the fused Krylov one: pin <- M^-1 cg_r +
+// beta pin (beta = scal[SC_BETA]) in place, then transformed.  The
+// Gauss-Newton part B diag(N/y^2) B runs as z r2c, y, x(b_hat), y^-1, z (c2r,
+// times N/y^2, r2c: the HVP z pass with rtmp as its diagonal), y, x(b_hat),
+// y^-1, z c2r.
+int lb_hvp_hat(pl_plan* p, int model, const double* bk, cx<double>* pin, cx<double>* out,
+               const cx<double>* cg_r = nullptr) {
   const int nb = grid_blocks(p->N);
   cx<double>* t = p->t64;
-  int rc = inv_c2r<double>(p, pin, t, p->preal);  // q = F^-1 pin
-  if (rc) return rc;
+  int rc;
+  if (cg_r) {
+    ColArgs<double> c1 = col_args<double>(p, 0, pin, t);
+    c1.cg_r = const_cast<cx<double>*>(cg_r);
+    c1.scal = p->scal;
+    HIPCHK(p, run_col<double>(p, 0, true, COL_CG_FIRST, c1, nullptr));
+  } else {
+    HIPCHK(p, run_col<double>(p, 0, true, COL_PLAIN, col_args<double>(p, 0, pin, t), nullptr));
+  }
+  HIPCHK(p, run_col<double>(p, 1, true, COL_PLAIN, col_args<double>(p, 1, t, t), nullptr));
+  {
+    RowArgs<double> ra = row_args<double>(p);
+    ra.in_c = t;
+    ra.out_r = p->preal;  // q = F^-1 pin
+    HIPCHK(p, run_row<double>(p, ROW_C2R, ra, nullptr));
+  }
   const double* src = p->preal;
   if (model == MODEL_LOGNORMAL) {
     hipLaunchKernelGGL(lb_mul_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->e, p->preal, p->s_ws, p->N);
@@ -2434,9 +2451,8 @@ int lb_hvp_hat(pl_plan* p, int model, const double* bk, const cx<double>* pin, c
   return PL_OK;
 }
 
-// Preconditioner constant c of M_k = 1/lambda_k + c b_hat_k^2: the 25th
-// percentile of the per-cell curvature (lb_curv_kernel), as for the
-// power-law model.
+// Preconditioner constant c of M_k = 1/lambda_k + c: the 25th percentile of
+// the per-cell curvature (lb_curv_kernel), as for the power-law model.
 int lb_precond(pl_plan* p, int model) {
   const int nb = grid_blocks(p->N);
   hipLaunchKernelGGL(lb_curv_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->e, p->rtmp, p->d, model, p->preal,
@@ -2450,24 +2466,27 @@ int lb_precond(pl_plan* p, int model) {
 
 // Truncated PCG on H x = -g (g_hat) into x64: stops at ||r|| <= tol_abs or at
 // the first direction of non-positive curvature; if that is the first
-// direction, x = M^-1 (-g) (preconditioned steepest descent).  Host-driven,
-// two scalar read-backs per iteration.
+// direction, x = M^-1 (-g) (preconditioned steepest descent).  The direction
+// update p = M^-1 r + beta p runs inside the first pass of each HVP.
+// Host-driven, two scalar read-backs per iteration.
 int lb_pcg(pl_plan* p, int model, const double* bk, double tol_abs, int max_cg, int* its_out, int* hv_out) {
   cx<double>*x = p->x64, *r = p->r64, *pp = p->p64, *q = p->t64;
-  const double* tab = p->radial ? p->tab_rad : p->tab_mode;
+  const int radial = p->radial && p->var[0][V_TAB_CG];  // the table the fused pass reads
+  const double* tab = View<double>::tab(p, radial);
   const double invN = 1.0 / (double)p->N;
   const int nb = grid_blocks(p->Nh);
-  hipLaunchKernelGGL(lb_cg_init_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->g_hat, x, r, pp, tab, p->radial,
-                     p->g, bk, p->scal, p->Nh, p->partials);
+  hipLaunchKernelGGL(lb_cg_init_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->g_hat, x, r, pp, tab, radial,
+                     p->g, p->scal, p->Nh, p->partials);
   HIPCHK(p, hipGetLastError());
   HIPCHK(p, finalize(p, nb, 2, FIN_STORE, SC_DF, invN));
+  HIPCHK(p, set_scalar(p, SC_BETA, 0.0));
   int rc = read_scalars(p);
   if (rc) return rc;
   double rz = p->h_scal[SC_DF], rr = p->h_scal[SC_DF + 1];
   int its = 0, hv = 0;
   for (int k = 0; k < max_cg; ++k) {
     if (!(std::sqrt(std::max(0.0, rr)) > tol_abs)) break;
-    rc = lb_hvp_hat(p, model, bk, pp, q);
+    rc = lb_hvp_hat(p, model, bk, pp, q, r);  // p = M^-1 r + beta p, q = H p
     if (rc) return rc;
     ++hv;
     hipLaunchKernelGGL(lb_dot_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, pp, q, p->g, p->Nh, p->partials);
@@ -2482,7 +2501,7 @@ int lb_pcg(pl_plan* p, int model, const double* bk, double tol_abs, int max_cg, 
     }
     const double alpha = rz / pq;
     hipLaunchKernelGGL(lb_cg_update_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, x, r, pp, q, alpha, tab,
-                       p->radial, p->g, bk, p->scal, p->Nh, p->partials);
+                       radial, p->g, p->scal, p->Nh, p->partials);
     HIPCHK(p, hipGetLastError());
     HIPCHK(p, finalize(p, nb, 2, FIN_STORE, SC_DF, invN));
     rc = read_scalars(p);
@@ -2491,11 +2510,8 @@ int lb_pcg(pl_plan* p, int model, const double* bk, double tol_abs, int max_cg, 
     const double rz_new = p->h_scal[SC_DF];
     rr = p->h_scal[SC_DF + 1];
     if (!(std::sqrt(std::max(0.0, rr)) > tol_abs)) break;
-    const double beta = rz_new / rz;
+    HIPCHK(p, set_scalar(p, SC_BETA, rz_new / rz));
     rz = rz_new;
-    hipLaunchKernelGGL(lb_cg_dir_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, r, pp, beta, tab, p->radial, p->g,
-                       bk, p->scal, p->Nh);
-    HIPCHK(p, hipGetLastError());
   }
   *its_out = its;
   *hv_out = hv;

@@ -118,34 +118,33 @@ __global__ void __launch_bounds__(RED_THREADS) lb_curv_kernel(const double* __re
 }
 
 // Preconditioner of the linear-bias Newton system on half spectra:
-// M_k = 1/lambda_k + c b_hat_k^2 (c = scal[SC_DBAR]); returns 1/M_k.
+// M_k = 1/lambda_k + c (c = scal[SC_DBAR]), the one the fused x pass
+// COL_CG_FIRST applies; returns 1/M_k.
 __device__ __forceinline__ double lb_minv(const double* __restrict__ tab, int radial, const Grid& g,
-                                          const double* __restrict__ bk, const double* __restrict__ scal, long i,
-                                          int& kz) {
+                                          const double* __restrict__ scal, long i, int& kz) {
   ModeIter mi{g};
   int kx, ky;
   mi.decompose(i, kx, ky, kz);
-  const double b = bk[i];
-  return precond_inv<double>(inv_lam_at(tab, radial, g, kx, ky, kz, i), scal[SC_DBAR] * b * b);
+  return precond_inv<double>(inv_lam_at(tab, radial, g, kx, ky, kz, i), scal[SC_DBAR]);
 }
 
-// CG start on H x = -g: x = 0, r = -g, p = M^-1 r; partials (r^H M^-1 r, r^H r)
+// CG start on H x = -g: x = 0, r = -g, p = 0 (the fused first pass of the
+// first HVP then forms p = M^-1 r); partials (r^H M^-1 r, r^H r)
 __global__ void __launch_bounds__(RED_THREADS) lb_cg_init_kernel(const cx<double>* __restrict__ g_hat,
                                                                  cx<double>* __restrict__ x, cx<double>* __restrict__ r,
                                                                  cx<double>* __restrict__ p,
                                                                  const double* __restrict__ tab, int radial, Grid g,
-                                                                 const double* __restrict__ bk,
                                                                  const double* __restrict__ scal, long nh,
                                                                  double* __restrict__ partials) {
   double acc[2] = {0.0, 0.0};
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nh; i += (long)gridDim.x * blockDim.x) {
     int kz;
-    const double mi = lb_minv(tab, radial, g, bk, scal, i, kz);
+    const double mi = lb_minv(tab, radial, g, scal, i, kz);
     const cx<double> rv = {-g_hat[i].x, -g_hat[i].y};
     const double hw = herm_w(kz, g), rr = rv.x * rv.x + rv.y * rv.y;
     x[i] = {0.0, 0.0};
     r[i] = rv;
-    p[i] = {mi * rv.x, mi * rv.y};
+    p[i] = {0.0, 0.0};
     acc[0] += hw * mi * rr;
     acc[1] += hw * rr;
   }
@@ -171,13 +170,12 @@ __global__ void __launch_bounds__(RED_THREADS) lb_cg_update_kernel(cx<double>* _
                                                                    const cx<double>* __restrict__ p,
                                                                    const cx<double>* __restrict__ q, double alpha,
                                                                    const double* __restrict__ tab, int radial, Grid g,
-                                                                   const double* __restrict__ bk,
                                                                    const double* __restrict__ scal, long nh,
                                                                    double* __restrict__ partials) {
   double acc[2] = {0.0, 0.0};
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nh; i += (long)gridDim.x * blockDim.x) {
     int kz;
-    const double mi = lb_minv(tab, radial, g, bk, scal, i, kz);
+    const double mi = lb_minv(tab, radial, g, scal, i, kz);
     const cx<double> pv = p[i], qv = q[i], xv = x[i], rv0 = r[i];
     x[i] = {xv.x + alpha * pv.x, xv.y + alpha * pv.y};
     const cx<double> rv = {rv0.x - alpha * qv.x, rv0.y - alpha * qv.y};
@@ -187,20 +185,6 @@ __global__ void __launch_bounds__(RED_THREADS) lb_cg_update_kernel(cx<double>* _
     acc[1] += hw * rr;
   }
   block_reduce_store<2>(acc, partials, blockIdx.x);
-}
-
-// p = M^-1 r + beta p
-__global__ void __launch_bounds__(RED_THREADS) lb_cg_dir_kernel(const cx<double>* __restrict__ r,
-                                                                cx<double>* __restrict__ p, double beta,
-                                                                const double* __restrict__ tab, int radial, Grid g,
-                                                                const double* __restrict__ bk,
-                                                                const double* __restrict__ scal, long nh) {
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nh; i += (long)gridDim.x * blockDim.x) {
-    int kz;
-    const double mi = lb_minv(tab, radial, g, bk, scal, i, kz);
-    const cx<double> rv = r[i], pv = p[i];
-    p[i] = {mi * rv.x + beta * pv.x, mi * rv.y + beta * pv.y};
-  }
 }
 
 }  // namespace pl
