@@ -197,8 +197,10 @@ def truncated_pcg(prob, bk, x, kind, g_hat, tol_abs, max_cg):
     """PCG on H p = -g in half-spectrum coordinates, stopped at ||r|| <= tol_abs
     or at the first direction of non-positive curvature.  If that happens
     before any step, the preconditioned steepest-descent direction M^-1 (-g)
-    is returned.  Preconditioner M_k = 1/lambda_k + c b_hat_k^2 with c the mean
-    of phi'^2 N / y^2 + phi'' B^T u (floored at 0)."""
+    is returned.  Preconditioner M_k = 1/lambda_k + c with c the 25th
+    percentile over the cells of max(0, phi'^2 N / y^2 + phi'' B^T u), floored
+    at 1e-3 times its mean (the constant only changes the iteration path, not
+    the minimiser reached)."""
     n, N = prob.n, prob.ncells
     cw = hermitian_weights(n)
     inv_lam = inv_lambda_half(prob)
@@ -206,7 +208,8 @@ def truncated_pcg(prob, bk, x, kind, g_hat, tol_abs, max_cg):
     u = prob.nbar * prob.w - np.where(prob.counts > 0, prob.counts / y, 0.0)
     a = dphi(kind, x)
     deff = a * a * np.where(prob.counts > 0, prob.counts / y ** 2, 0.0) + d2phi(kind, x) * bias_apply(bk, u)
-    M = inv_lam + max(float(np.mean(deff)), 0.0) * bk * bk
+    deff = np.maximum(deff, 0.0)
+    M = inv_lam + max(float(np.percentile(deff, 25)), 1e-3 * float(np.mean(deff)))
     Minv = np.where(M > 0, 1.0 / np.where(M > 0, M, 1.0), 0.0)
     sol = np.zeros_like(g_hat)
     r = -g_hat

@@ -223,3 +223,21 @@ def test_no_data_returns_prior_mean(kind):
     x, info = plan.solve_linear_bias(kind, bk, x0=x0, rtol=1e-12)
     assert info["status"] == 0, info
     assert np.abs(x.cpu().numpy() - m).max() <= 1e-10
+
+
+@pytest.mark.parametrize("kind", [LN, GA])
+def test_map_selection_workload_64_matches_oracle(kind):
+    # the selection workload's recipe at 64^3 (radial selection, masked 8^3
+    # blocks, nbar 0.5) with the benchmark's 1.5-cell smoothing multiplier;
+    # two oracle Newton paths with different preconditioners reach the same
+    # minimiser here (to 3e-10), so the comparison is of the MAP itself
+    inst = synth.config_instance("sel256", n=64)
+    P = oracle_problem(inst)
+    bk = _bk(inst, 1.0, 1.5)
+    print(f"linbias 64 kind={kind}: oracle", flush=True)
+    ref, oinfo = linbias.newton_spectral(P, bk, kind, rtol=1e-10)
+    assert oinfo["status"] == "ok", oinfo
+    plan = _plan(inst)
+    x, info = plan.solve_linear_bias(kind, bk, rtol=1e-10, max_cg=5000)
+    assert info["status"] == 0 and info["rel_grad"] <= 1e-10, info
+    assert _rel(x.cpu().numpy(), ref) <= 1e-7
