@@ -313,12 +313,18 @@ def main():
     # ---------------- linear (non-local) bias (sections 2.2.1, 2.4.1) ----------------
     # b_hat(k) = exp(-(1.5 cells k)^2 / 2): the galaxy field as the matter
     # field smoothed over 1.5 cells; both priors, FP64, same tolerance
-    cell = inst["box"][0] / n[0]
-    bk = torch.from_numpy(synth.bias_multiplier_half(n, inst["box"], 1.0, 1.5 * cell)).to(dev)
-    linear_bias = {"b_hat": "exp(-(1.5 cells * k)^2 / 2)"}
-    v_real = torch.from_numpy(v).to(dev)
-    hv_real = torch.empty_like(v_real)
-    for model, x_lin in (("lognormal", s_true), ("gaussian", torch.expm1(s_true))):
+    # (selection workload at its own size only)
+    linear_bias = None
+    lb_models = (("lognormal", s_true), ("gaussian", torch.expm1(s_true)))
+    if args.workload != "sel256" or args.n is not None:
+        lb_models = ()
+    else:
+        cell = inst["box"][0] / n[0]
+        bk = torch.from_numpy(synth.bias_multiplier_half(n, inst["box"], 1.0, 1.5 * cell)).to(dev)
+        linear_bias = {"b_hat": "exp(-(1.5 cells * k)^2 / 2)"}
+        v_real = torch.from_numpy(v).to(dev)
+        hv_real = torch.empty_like(v_real)
+    for model, x_lin in lb_models:
         plan.linear_bias_grad(model, bk, x_lin)
         for _ in range(5):
             plan.linear_bias_hessvec(model, bk, v_real, out=hv_real)
