@@ -98,20 +98,20 @@ def hvp_bytes(n, p, spectral=True):
 def linear_bias_hvp_bytes(n, lognormal):
     """Algorithmic FP64 bytes of one real-space linear-bias HVP with a cached
     linearisation (pl_linear_bias_hessvec, x = NULL): v to half spectrum (3
-    passes); the spectral HVP: back to real space (3), phi' times, z r2c, y,
-    x(b_hat), y^-1, the z pass c2r / times N/y^2 / r2c, y, x(b_hat), y^-1,
-    z c2r, phi'' B u q + phi' g2, forward with the prior added (3); and back
-    to real space (3)."""
+    passes), the spectral HVP, back to real space (3).  Lognormal prior: x^-1,
+    y^-1, z (keeps q, times phi'), y, x(b_hat), y^-1, z (times N/y^2), y,
+    x(b_hat), y^-1, z (phi' g + phi'' B u q), y, x + prior.  Gaussian prior:
+    x^-1, x(b_hat), y^-1, z (times N/y^2), y, x(b_hat), x + prior."""
     N = n[0] * n[1] * n[2]
     Nh = n[0] * n[1] * (n[2] // 2 + 1)
     fwd = (8 * N + 16 * Nh) + 32 * Nh + 32 * Nh          # z r2c, y, x
     inv = 32 * Nh + 32 * Nh + (16 * Nh + 8 * N)          # x, y, z c2r
-    xmul = 40 * Nh                                       # x pass, reads the b_hat table
-    gn = (8 * N + 16 * Nh) + 32 * Nh + xmul + 32 * Nh + (32 * Nh + 8 * N) + 32 * Nh + xmul + 32 * Nh \
-        + (16 * Nh + 8 * N)
-    hvp = inv + gn + (8 * N + 16 * Nh) + 32 * Nh + 48 * Nh
+    col, xmul, xadd = 32 * Nh, 40 * Nh, 48 * Nh          # plain, x(b_hat) (+ table), x + prior
+    zhvp = 32 * Nh + 8 * N                               # z pass with a diagonal
     if lognormal:
-        hvp += 24 * N + 40 * N  # phi' q; d1 q + phi' g2
+        hvp = 7 * col + 2 * xmul + xadd + (32 * Nh + 16 * N) + zhvp + (32 * Nh + 24 * N)
+    else:
+        hvp = col + 2 * xmul + col + zhvp + col + xadd
     return fwd + hvp + inv
 
 

@@ -436,8 +436,10 @@ enum RowOp {
   ROW_GRAD = 3,        // half (s_hat) -> s -> likelihood gradient l -> half;
                        // writes s, e, d; partials sum(e - beta N s), sum(d)
   ROW_C2R_DIAG = 4,    // half -> real: scale * x + d * v
-  ROW_C2R_GRADLIK = 5  // half -> real: scale * x + beta (nbar w e^{beta s} - N);
-                       // writes d; partials sum(e - beta N s)
+  ROW_C2R_GRADLIK = 5,  // half -> real: scale * x + beta (nbar w e^{beta s} - N);
+                        // writes d; partials sum(e - beta N s)
+  ROW_LB_IN = 6,        // half -> real q (stored to out_r), times d, -> half
+  ROW_LB_OUT = 7        // half -> real g, d g + lb_d1 lb_q, -> half (double only)
 };
 
 template <typename T>
@@ -464,6 +466,8 @@ struct RowArgs {
   const double* skip;  // if non-null and *skip != 0 the launch does nothing
   int nt;              // NT_* bits: operands loaded / stored non-temporally
   int model;           // ROW_GRAD likelihood: MODEL_LOGNORMAL or MODEL_GAUSSIAN
+  const double* lb_d1;  // ROW_LB_OUT: the curvature diagonal and the kept field q
+  const double* lb_q;
 };
 
 template <int N, int V = 0>
@@ -535,10 +539,11 @@ __device__ __forceinline__ void row_body(const RowArgs<T>& a, int ublock, cx<T>*
 
   double acc[2] = {0.0, 0.0};
 
-  // ROW_HVP: the Hessian diagonal at the positions this thread multiplies,
-  // loaded before the transforms so that its latency overlaps them
-  T pre_dA[ROW_HVP == OP ? W : 1], pre_dB[ROW_HVP == OP ? W : 1];
-  if constexpr (OP == ROW_HVP) {
+  // ROW_HVP / ROW_LB_IN: the diagonal at the positions this thread
+  // multiplies, loaded before the transforms so that its latency overlaps them
+  constexpr bool PRE_D = OP == ROW_HVP || OP == ROW_LB_IN;
+  T pre_dA[PRE_D ? W : 1], pre_dB[PRE_D ? W : 1];
+  if constexpr (PRE_D) {
 #pragma unroll
     for (int q = 0; q < W / RL; ++q)
 #pragma unroll
@@ -623,6 +628,40 @@ __device__ __forceinline__ void row_body(const RowArgs<T>& a, int ublock, cx<T>*
             T va = z.x * a.scale, vb = z.y * a.scale;
             acc[0] += (double)dA * va * va + (double)dB * vb * vb;
             v[q * RL + m] = {va * dA, vb * dB};
+          }
+      } else if constexpr (OP == ROW_LB_IN) {
+        // keep q = F^-1 p (real) for the output pass, go on with d q
+#pragma unroll
+        for (int q = 0; q < W / RL; ++q)
+#pragma unroll
+          for (int m = 0; m < RL; ++m) {
+            const int e = out_pos<PL, PL::NS - 1>(t, q, m);
+            cx<T> z = v[q * RL + m];
+            const T va = z.x * a.scale, vb = z.y * a.scale;
+            if (valid) {
+              a.out_r[rowA * N + e] = va;
+              a.out_r[rowB * N + e] = vb;
+            }
+            v[q * RL + m] = {va * pre_dA[q * RL + m], vb * pre_dB[q * RL + m]};
+          }
+      } else if constexpr (OP == ROW_LB_OUT) {
+        // d g + d1 q at each real position
+#pragma unroll
+        for (int q = 0; q < W / RL; ++q)
+#pragma unroll
+          for (int m = 0; m < RL; ++m) {
+            const int e = out_pos<PL, PL::NS - 1>(t, q, m);
+            cx<T> z = v[q * RL + m];
+            T o[2] = {T(0), T(0)};
+            if (valid) {
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                const long i = (h ? rowB : rowA) * N + e;
+                const T g = (h ? z.y : z.x) * a.scale;
+                o[h] = (T)(a.d[i] * g + a.lb_d1[i] * a.lb_q[i]);
+              }
+            }
+            v[q * RL + m] = {o[0], o[1]};
           }
       } else {  // ROW_GRAD (double only)
 #pragma unroll

@@ -2380,12 +2380,12 @@ int lb_xmul(pl_plan* p, const double* bk) {
 // out = H pin on half spectra at the current linearisation; out may be t64.
 // With cg_r, the first x pass is the fused Krylov one: pin <- M^-1 cg_r +
 // beta pin (beta = scal[SC_BETA]) in place, then transformed.  The
-// Gauss-Newton part B diag(N/y^2) B runs as z r2c, y, x(b_hat), y^-1, z (c2r,
-// times N/y^2, r2c: the HVP z pass with rtmp as its diagonal), y, x(b_hat),
-// y^-1, z c2r.
+// Gauss-Newton part B diag(N/y^2) B runs as y, x(b_hat), y^-1, the z pass
+// with rtmp (N/y^2) as its diagonal, y, x(b_hat), y^-1 between the z passes
+// that apply phi' (lognormal prior; both x(b_hat) passes multiply along the
+// same half spectrum).
 int lb_hvp_hat(pl_plan* p, int model, const double* bk, cx<double>* pin, cx<double>* out,
                const cx<double>* cg_r = nullptr) {
-  const int nb = grid_blocks(p->N);
   cx<double>* t = p->t64;
   int rc;
   if (cg_r) {
@@ -2396,24 +2396,39 @@ int lb_hvp_hat(pl_plan* p, int model, const double* bk, cx<double>* pin, cx<doub
   } else {
     HIPCHK(p, run_col<double>(p, 0, true, COL_PLAIN, col_args<double>(p, 0, pin, t), nullptr));
   }
+  if (model == MODEL_GAUSSIAN) {
+    // phi' = 1, phi'' = 0: H p = b_hat F[(N/y^2) F^-1 (b_hat p)] + p/lambda, as
+    // x^-1, x(b_hat), y^-1, the z pass with N/y^2, y, x(b_hat), x + prior.
+    // Each x(b_hat) pass meets an unnormalised x transform of the opposite
+    // sense, a factor nx: the z pass and the last x pass take 1/nx each.
+    const double inv_nx = 1.0 / (double)p->n[0];
+    if ((rc = lb_xmul(p, bk))) return rc;
+    HIPCHK(p, run_col<double>(p, 1, true, COL_PLAIN, col_args<double>(p, 1, t, t), nullptr));
+    RowArgs<double> ra = row_args<double>(p);
+    ra.in_c = t;
+    ra.out_c = t;
+    ra.d = p->rtmp;
+    ra.scale *= inv_nx;
+    HIPCHK(p, run_row<double>(p, ROW_HVP, ra, nullptr));
+    HIPCHK(p, run_col<double>(p, 1, false, COL_PLAIN, col_args<double>(p, 1, t, t), nullptr));
+    if ((rc = lb_xmul(p, bk))) return rc;
+    ColArgs<double> ca = col_args<double>(p, 0, t, out);
+    ca.base = pin;
+    ca.k0_shift = 0.0;
+    ca.out_scale = inv_nx;
+    HIPCHK(p, run_col<double>(p, 0, false, COL_ADDPRIOR, ca, nullptr));
+    return PL_OK;
+  }
+  // lognormal: the z passes keep q = F^-1 p (ROW_LB_IN, also forming phi' q)
+  // and form phi' g2 + d1 q (ROW_LB_OUT) between their c2r and r2c
   HIPCHK(p, run_col<double>(p, 1, true, COL_PLAIN, col_args<double>(p, 1, t, t), nullptr));
   {
     RowArgs<double> ra = row_args<double>(p);
     ra.in_c = t;
-    ra.out_r = p->preal;  // q = F^-1 pin
-    HIPCHK(p, run_row<double>(p, ROW_C2R, ra, nullptr));
-  }
-  const double* src = p->preal;
-  if (model == MODEL_LOGNORMAL) {
-    hipLaunchKernelGGL(lb_mul_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->e, p->preal, p->s_ws, p->N);
-    HIPCHK(p, hipGetLastError());
-    src = p->s_ws;
-  }
-  {
-    RowArgs<double> ra = row_args<double>(p);
-    ra.in_r = src;
     ra.out_c = t;
-    HIPCHK(p, run_row<double>(p, ROW_R2C, ra, nullptr));
+    ra.out_r = p->preal;
+    ra.d = p->e;
+    HIPCHK(p, run_row<double>(p, ROW_LB_IN, ra, nullptr));
   }
   HIPCHK(p, run_col<double>(p, 1, false, COL_PLAIN, col_args<double>(p, 1, t, t), nullptr));
   if ((rc = lb_xmul(p, bk))) return rc;
@@ -2431,18 +2446,12 @@ int lb_hvp_hat(pl_plan* p, int model, const double* bk, cx<double>* pin, cx<doub
   {
     RowArgs<double> ra = row_args<double>(p);
     ra.in_c = t;
-    ra.out_r = p->s_ws;
-    HIPCHK(p, run_row<double>(p, ROW_C2R, ra, nullptr));
+    ra.out_c = t;
+    ra.d = p->e;
+    ra.lb_d1 = p->d;
+    ra.lb_q = p->preal;
+    HIPCHK(p, run_row<double>(p, ROW_LB_OUT, ra, nullptr));
   }
-  if (model == MODEL_LOGNORMAL) {
-    hipLaunchKernelGGL(lb_combine_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->s_ws, p->preal, p->d, p->e,
-                       p->N);
-    HIPCHK(p, hipGetLastError());
-  }
-  RowArgs<double> ra = row_args<double>(p);
-  ra.in_r = p->s_ws;
-  ra.out_c = t;
-  HIPCHK(p, run_row<double>(p, ROW_R2C, ra, nullptr));
   HIPCHK(p, run_col<double>(p, 1, false, COL_PLAIN, col_args<double>(p, 1, t, t), nullptr));
   ColArgs<double> ca = col_args<double>(p, 0, t, out);
   ca.base = pin;

@@ -83,23 +83,6 @@ __global__ void __launch_bounds__(RED_THREADS) lb_grad_pointwise_kernel(double* 
   }
 }
 
-// out = a * b
-__global__ void __launch_bounds__(RED_THREADS) lb_mul_kernel(const double* __restrict__ a,
-                                                             const double* __restrict__ b, double* __restrict__ out,
-                                                             long n) {
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-    out[i] = a[i] * b[i];
-}
-
-// g2 <- d1 q + phi' g2 (lognormal Hessian: diagonal part plus the outer
-// factor of the Gauss-Newton part)
-__global__ void __launch_bounds__(RED_THREADS) lb_combine_kernel(double* __restrict__ g2, const double* __restrict__ q,
-                                                                 const double* __restrict__ d1,
-                                                                 const double* __restrict__ dphi, long n) {
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-    g2[i] = d1[i] * q[i] + dphi[i] * g2[i];
-}
-
 // Representative curvature per cell for the preconditioner constant:
 // max(0, phi'^2 N / y^2 + d1) (lognormal), N / y^2 (Gaussian); wt = N / y^2.
 __global__ void __launch_bounds__(RED_THREADS) lb_curv_kernel(const double* __restrict__ dphi,

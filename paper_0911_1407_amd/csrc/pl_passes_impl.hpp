@@ -46,6 +46,8 @@ static hipError_t row_launch_n(int op, const RowArgs<T>& a, hipStream_t st, int*
     case ROW_C2R_GRADLIK:
       hipLaunchKernelGGL((row_kernel<T, N, ROW_C2R_GRADLIK, V>), grid, dim3(S::THREADS), 0, st, a);
       break;
+    case ROW_LB_IN: hipLaunchKernelGGL((row_kernel<T, N, ROW_LB_IN, V>), grid, dim3(S::THREADS), 0, st, a); break;
+    case ROW_LB_OUT: hipLaunchKernelGGL((row_kernel<T, N, ROW_LB_OUT, V>), grid, dim3(S::THREADS), 0, st, a); break;
 #endif
     default: return hipErrorInvalidValue;
   }
