@@ -1,0 +1,41 @@
+"""Host logic of the benchmark's reporting: the algorithmic byte models and
+the guard that reports measured traffic only for the profiled kernels."""
+import bench
+
+
+def test_hvp_byte_model():
+    n = (256, 256, 256)
+    N, Nh = 256 ** 3, 256 * 256 * 129
+    assert bench.hvp_bytes(n, 8) == 8 * N + 22 * 8 * Nh == 1622147072
+    assert bench.hvp_bytes(n, 4) == 4 * N + 22 * 4 * Nh
+    assert bench.hvp_bytes(n, 8, spectral=False) == 4 * 8 * N + 16 * 8 * Nh
+    # per-pass sum: four column / row passes read and write the half
+    # spectrum, the z pass also reads d, the last pass reads X and p, writes H p
+    assert 4 * (2 * 16 * Nh) + 8 * N + 3 * 16 * Nh == bench.hvp_bytes(n, 8)
+
+
+def test_linear_bias_byte_model():
+    for n in ((256, 256, 256), (32, 48, 64)):
+        N = n[0] * n[1] * n[2]
+        Nh = n[0] * n[1] * (n[2] // 2 + 1)
+        assert bench.linear_bias_hvp_bytes(n, True) == 64 * N + 608 * Nh
+        assert bench.linear_bias_hvp_bytes(n, False) == 24 * N + 416 * Nh
+    # the Gaussian prior's operator is the lognormal one without the phi'
+    # product, the two kept-field z passes and their real-field traffic
+    n = (256, 256, 256)
+    assert bench.linear_bias_hvp_bytes(n, False) < bench.linear_bias_hvp_bytes(n, True)
+
+
+def test_measured_traffic_only_for_the_profiled_kernels():
+    m = bench.MEASURED_TRAFFIC["sel256"]
+    sched = m["fp64_schedule"]
+    if m["src_sha"] == bench.kernel_sources_sha():
+        assert bench.measured_traffic("sel256", sched) == m["bytes_per_hvp"]
+    else:
+        assert bench.measured_traffic("sel256", sched) is None
+    other = list(sched)
+    other[0] = 1 - other[0]
+    assert bench.measured_traffic("sel256", other) is None
+    assert bench.measured_traffic("big512", sched) is None
+    # within a few percent of the algorithmic bytes: no wasted re-reads
+    assert 1.0 <= m["bytes_per_hvp"] / bench.hvp_bytes((256, 256, 256), 8) < 1.1
