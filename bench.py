@@ -99,8 +99,8 @@ def linear_bias_hvp_bytes(n, lognormal):
     """Algorithmic FP64 bytes of one real-space linear-bias HVP with a cached
     linearisation (pl_linear_bias_hessvec, x = NULL): v to half spectrum (3
     passes), the spectral HVP, back to real space (3).  Lognormal prior: x^-1,
-    y^-1, z (keeps q, times phi'), y, x(b_hat), y^-1, z (times N/y^2), y,
-    x(b_hat), y^-1, z (phi' g + phi'' B u q), y, x + prior.  Gaussian prior:
+    y^-1, z (keeps q, times phi', sums phi'' B u q^2), y, x(b_hat), y^-1,
+    z (times N/y^2), y, x(b_hat), y^-1, z (phi' g + phi'' B u q), y, x + prior.  Gaussian prior:
     x^-1, x(b_hat), y^-1, z (times N/y^2), y, x(b_hat), x + prior."""
     N = n[0] * n[1] * n[2]
     Nh = n[0] * n[1] * (n[2] // 2 + 1)
@@ -109,7 +109,7 @@ def linear_bias_hvp_bytes(n, lognormal):
     col, xmul, xadd = 32 * Nh, 40 * Nh, 48 * Nh          # plain, x(b_hat) (+ table), x + prior
     zhvp = 32 * Nh + 8 * N                               # z pass with a diagonal
     if lognormal:
-        hvp = 7 * col + 2 * xmul + xadd + (32 * Nh + 16 * N) + zhvp + (32 * Nh + 24 * N)
+        hvp = 7 * col + 2 * xmul + xadd + (32 * Nh + 24 * N) + zhvp + (32 * Nh + 24 * N)
     else:
         hvp = col + 2 * xmul + col + zhvp + col + xadd
     return fwd + hvp + inv

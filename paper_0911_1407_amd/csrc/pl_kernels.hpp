@@ -138,6 +138,7 @@ enum Scal {
   SC_LS_B = 16, SC_LS_C = 17, SC_LS_SLOPE = 18,
   SC_DF = 20,     // 4 slots
   SC_ADJ = 26,    // adjoint sums (4 slots)
+  SC_LB_DQ = 30,  // linear-bias Krylov step: sum of phi'' B u q^2 (the diagonal part of p^H H p)
   SC_COUNT = 32
 };
 
@@ -630,7 +631,8 @@ __device__ __forceinline__ void row_body(const RowArgs<T>& a, int ublock, cx<T>*
             v[q * RL + m] = {va * dA, vb * dB};
           }
       } else if constexpr (OP == ROW_LB_IN) {
-        // keep q = F^-1 p (real) for the output pass, go on with d q
+        // keep q = F^-1 p (real) for the output pass, go on with d q;
+        // partial sums of lb_d1 q^2
 #pragma unroll
         for (int q = 0; q < W / RL; ++q)
 #pragma unroll
@@ -641,6 +643,7 @@ __device__ __forceinline__ void row_body(const RowArgs<T>& a, int ublock, cx<T>*
             if (valid) {
               a.out_r[rowA * N + e] = va;
               a.out_r[rowB * N + e] = vb;
+              acc[0] += a.lb_d1[rowA * N + e] * (double)va * va + a.lb_d1[rowB * N + e] * (double)vb * vb;
             }
             v[q * RL + m] = {va * pre_dA[q * RL + m], vb * pre_dB[q * RL + m]};
           }
@@ -742,7 +745,8 @@ __device__ __forceinline__ void row_body(const RowArgs<T>& a, int ublock, cx<T>*
       }
     }
   }
-  if constexpr (OP == ROW_GRAD || OP == ROW_HVP) block_reduce_store<2>(acc, a.partials, block_linear);
+  if constexpr (OP == ROW_GRAD || OP == ROW_HVP || OP == ROW_LB_IN)
+    block_reduce_store<2>(acc, a.partials, block_linear);
 }
 
 template <typename T, int N, int OP, int V>
@@ -806,7 +810,7 @@ __global__ void __launch_bounds__(RED_THREADS) cg_init_kernel(const cx<double>* 
 }
 
 #ifdef PL_OPS_KERNELS
-enum FinKind { FIN_STORE = 0, FIN_CG_INIT = 1, FIN_CG_ALPHA = 2, FIN_CG_BETA = 3, FIN_DBAR = 4 };
+enum FinKind { FIN_STORE = 0, FIN_CG_INIT = 1, FIN_CG_ALPHA = 2, FIN_CG_BETA = 3, FIN_DBAR = 4, FIN_CG_ALPHA_ADD = 5 };
 
 // Sum partials[nb][K] in a fixed order; then scalar bookkeeping.
 // kind FIN_CG_ALPHA: p^H H p = scale2 * sum(partials2[nb2]) (prior part from
@@ -882,9 +886,10 @@ __device__ __forceinline__ void finalize_body(const double* __restrict__ partial
       scal[SC_ALPHA] = 0.0;
       scal[SC_BETA] = 0.0;
       break;
-    case FIN_CG_ALPHA: {
+    case FIN_CG_ALPHA:
+    case FIN_CG_ALPHA_ADD: {  // _ADD: p^H H p also holds scal[dst]
       if (scal[SC_DONE] != 0.0) break;  // iteration skipped
-      const double pq = v[0] + extra;
+      const double pq = v[0] + extra + (kind == FIN_CG_ALPHA_ADD ? scal[dst] : 0.0);
       scal[SC_PQ] = pq;
       double al = 0.0;
       if (scal[SC_DONE] == 0.0 && pq > 0.0) al = scal[SC_RZ] / pq;

@@ -2367,12 +2367,16 @@ int lb_assemble_grad(pl_plan* p, const cx<double>* x_hat, cx<double>* g_out) {
   return PL_OK;
 }
 
-// The x pass F_x^-1 diag(b_hat) F_x on a field already transformed along y and z
-int lb_xmul(pl_plan* p, const double* bk) {
+// The x pass F_x^-1 diag(b_hat) F_x on a field already transformed along y and
+// z.  It also leaves per-block partial sums (unused here) in `scratch`
+// (default: the start of the partials buffer).
+int lb_xmul(pl_plan* p, const double* bk, const double* skip = nullptr, double* scratch = nullptr) {
   ColArgs<double> ca = col_args<double>(p, 0, p->t64, p->t64);
   ca.inv_lam = bk;
   ca.radial = 0;
   ca.k0_shift = 0.0;
+  ca.skip = skip;
+  if (scratch) ca.partials = scratch;
   HIPCHK(p, run_col_own_table(p, false, COL_PRIOR, ca, nullptr));
   return PL_OK;
 }
@@ -2428,6 +2432,7 @@ int lb_hvp_hat(pl_plan* p, int model, const double* bk, cx<double>* pin, cx<doub
     ra.out_c = t;
     ra.out_r = p->preal;
     ra.d = p->e;
+    ra.lb_d1 = p->d;
     HIPCHK(p, run_row<double>(p, ROW_LB_IN, ra, nullptr));
   }
   HIPCHK(p, run_col<double>(p, 1, false, COL_PLAIN, col_args<double>(p, 1, t, t), nullptr));
@@ -2527,6 +2532,106 @@ int lb_pcg(pl_plan* p, int model, const double* bk, double tol_abs, int max_cg, 
   return PL_OK;
 }
 
+// Lognormal prior: the same truncated PCG with the Krylov updates fused into
+// the operator's first and last x passes, as the power-law solve does:
+// COL_CG_FIRST forms p = M^-1 r + beta p before the inverse transform,
+// COL_CG_LAST forms H p = X + p/lambda and updates r and x in place.  The
+// step length comes from device partials: p^H Lambda^-1 p (COL_CG_FIRST),
+// sum phi'' B u q^2 (ROW_LB_IN, stored to SC_LB_DQ) and sum (N/y^2)(B phi' q)^2
+// (the ROW_HVP z pass); a non-positive p^H H p stops the iteration
+// (SC_DONE = 2).  Launched in chunks of check_every iterations, each
+// iteration after convergence exiting at once; the host reads the scalars
+// once per chunk.
+int lb_pcg_fused(pl_plan* p, const double* bk, double tol_abs, int max_cg, int check_every, int* its_out,
+                 int* hv_out) {
+  cx<double>*x = p->x64, *r = p->r64, *pp = p->p64, *t = p->t64;
+  const double invN = 1.0 / (double)p->N;
+  double* part_a = p->partials;
+  double* part_b = p->partials + p->partials_len;
+  // the x(b_hat) passes' own partial sums go to the second half of region a,
+  // clear of the COL_CG_FIRST sums (first half) that the step length reads
+  double* part_x = part_a + p->partials_len / 2;
+  HIPCHK(p, set_scalar(p, SC_TOL2, tol_abs * tol_abs));
+  hipLaunchKernelGGL((cg_init_kernel<double>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, p->g_hat, -1.0, x, r,
+                     pp, View<double>::tab(p), p->radial, p->g, p->Nh, p->scal, p->partials);
+  HIPCHK(p, hipGetLastError());
+  HIPCHK(p, finalize(p, NB_RED, 2, FIN_CG_INIT, 0, invN));
+  const double* skip = p->scal + SC_DONE;
+  int launched = 0;
+  while (launched < max_cg) {
+    const int chunk = std::min(check_every, max_cg - launched);
+    for (int k = 0; k < chunk; ++k) {
+      int nb1 = 0, nbq = 0, nbz = 0, nb5 = 0;
+      ColArgs<double> c1 = col_args<double>(p, 0, pp, t);
+      c1.cg_r = r;
+      c1.scal = p->scal;
+      c1.partials = part_a;
+      c1.skip = skip;
+      HIPCHK(p, run_col<double>(p, 0, true, COL_CG_FIRST, c1, &nb1));
+      ColArgs<double> cy = col_args<double>(p, 1, t, t);
+      cy.skip = skip;
+      HIPCHK(p, run_col<double>(p, 1, true, COL_PLAIN, cy, nullptr));
+      RowArgs<double> r1 = row_args<double>(p);
+      r1.in_c = t;
+      r1.out_c = t;
+      r1.out_r = p->preal;
+      r1.d = p->e;
+      r1.lb_d1 = p->d;
+      r1.partials = part_b;
+      r1.skip = skip;
+      HIPCHK(p, run_row<double>(p, ROW_LB_IN, r1, &nbq));
+      HIPCHK(p, finalize(p, nbq, 2, FIN_STORE, SC_LB_DQ, 1.0, 0.0, part_b));
+      HIPCHK(p, run_col<double>(p, 1, false, COL_PLAIN, cy, nullptr));
+      int rc = lb_xmul(p, bk, skip, part_x);
+      if (rc) return rc;
+      HIPCHK(p, run_col<double>(p, 1, true, COL_PLAIN, cy, nullptr));
+      RowArgs<double> r2 = row_args<double>(p);
+      r2.in_c = t;
+      r2.out_c = t;
+      r2.d = p->rtmp;
+      r2.partials = part_b;
+      r2.skip = skip;
+      HIPCHK(p, run_row<double>(p, ROW_HVP, r2, &nbz));
+      HIPCHK(p, run_col<double>(p, 1, false, COL_PLAIN, cy, nullptr));
+      if ((rc = lb_xmul(p, bk, skip, part_x))) return rc;
+      HIPCHK(p, run_col<double>(p, 1, true, COL_PLAIN, cy, nullptr));
+      RowArgs<double> r3 = row_args<double>(p);
+      r3.in_c = t;
+      r3.out_c = t;
+      r3.d = p->e;
+      r3.lb_d1 = p->d;
+      r3.lb_q = p->preal;
+      r3.skip = skip;
+      HIPCHK(p, run_row<double>(p, ROW_LB_OUT, r3, nullptr));
+      HIPCHK(p, run_col<double>(p, 1, false, COL_PLAIN, cy, nullptr));
+      HIPCHK(p, finalize(p, nbz, 2, FIN_CG_ALPHA_ADD, SC_LB_DQ, 1.0, 0.0, part_b, part_a, nb1, invN));
+      ColArgs<double> c5 = col_args<double>(p, 0, t, t);
+      c5.base = pp;
+      c5.cg_r = r;
+      c5.cg_x = x;
+      c5.scal = p->scal;
+      c5.partials = part_a;
+      c5.skip = skip;
+      HIPCHK(p, run_col<double>(p, 0, false, COL_CG_LAST, c5, &nb5));
+      HIPCHK(p, finalize(p, nb5, 2, FIN_CG_BETA, 0, invN, (double)max_cg, part_a));
+    }
+    launched += chunk;
+    int rc = read_scalars(p);
+    if (rc) return rc;
+    if (p->h_scal[SC_DONE] != 0.0) break;
+  }
+  int rc = read_scalars(p);
+  if (rc) return rc;
+  const int its = (int)p->h_scal[SC_ITS];
+  const bool breakdown = p->h_scal[SC_DONE] == 2.0;
+  // non-positive curvature along the first direction: take p = M^-1 (-g)
+  if (breakdown && its == 0)
+    HIPCHK(p, hipMemcpyAsync(x, pp, sizeof(cx<double>) * p->Nh, hipMemcpyDeviceToDevice, p->stream));
+  *its_out = its;
+  *hv_out = its + (breakdown ? 1 : 0);
+  return PL_OK;
+}
+
 // Armijo backtracking along x64 from s_hat (real field x_real): the decrease
 // a b + a^2 c / 2 + sum_i [nbar w_i dy_i - N_i log1p(dy_i / y_i)], with
 // dy = B (phi(x + a p) - phi(x)), against c1 a p^T g for a = 1, 1/2, ...
@@ -2619,7 +2724,8 @@ int lb_newton_solve(pl_plan* p, int model, const double* bk, double* x_io, const
       rc = lb_precond(p, model);
       if (rc) return rc;
       int its = 0, hv = 0;
-      rc = lb_pcg(p, model, bk, eta * gn, o.max_cg, &its, &hv);
+      rc = model == MODEL_LOGNORMAL ? lb_pcg_fused(p, bk, eta * gn, o.max_cg, o.check_every, &its, &hv)
+                                    : lb_pcg(p, model, bk, eta * gn, o.max_cg, &its, &hv);
       if (rc) return rc;
       inf.cg_its += its;
       inf.hvps += hv;

@@ -18,7 +18,7 @@ def test_linear_bias_byte_model():
     for n in ((256, 256, 256), (32, 48, 64)):
         N = n[0] * n[1] * n[2]
         Nh = n[0] * n[1] * (n[2] // 2 + 1)
-        assert bench.linear_bias_hvp_bytes(n, True) == 64 * N + 608 * Nh
+        assert bench.linear_bias_hvp_bytes(n, True) == 72 * N + 608 * Nh
         assert bench.linear_bias_hvp_bytes(n, False) == 24 * N + 416 * Nh
     # the Gaussian prior's operator is the lognormal one without the phi'
     # product, the two kept-field z passes and their real-field traffic
