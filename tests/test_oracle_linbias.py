@@ -136,3 +136,33 @@ def test_likelihood_is_poisson_with_biased_rate(rng):
 
     assert linbias.likelihood(p, linbias.galaxy_field(p, bk, x1, LN)) - linbias.likelihood(
         p, linbias.galaxy_field(p, bk, x2, LN)) == pytest.approx(nll(x1) - nll(x2), rel=1e-10)
+
+
+def test_white_prior_root_at_unit_bias_matches_closed_forms():
+    # b0 = 1 is the unit bias: the bisection root equals the Lambert-W closed
+    # form of the lognormal model and the quadratic root of the Gaussian one
+    from oracle import closed_form
+    rng = np.random.default_rng(7)
+    shape = (6, 5, 4)
+    w = rng.uniform(0.05, 1.0, shape)
+    w[0, 0, :] = 0.0
+    counts = np.where(w > 0, rng.poisson(3.0, shape), 0).astype(np.float64)
+    sigma2, mu, nbar = 0.7, -0.35, 1.4
+    ln = linbias.white_prior_map(LN, sigma2, mu, 1.0, nbar, w, counts)
+    ref_ln = closed_form.white_prior_map(mu=mu, sigma2=sigma2, beta=1.0, nbar=nbar, w=w, counts=counts)
+    assert np.abs(ln - ref_ln).max() <= 1e-12 * max(1.0, np.abs(ref_ln).max())
+    ga = linbias.white_prior_map(GA, sigma2, 0.0, 1.0, nbar, w, counts)
+    ref_ga = gaussian.white_prior_map(sigma2, nbar, w, counts)
+    assert np.abs(ga - ref_ga).max() <= 1e-12 * max(1.0, np.abs(ref_ga).max())
+
+
+def test_bias_multiplier_is_even_so_B_is_symmetric():
+    # b_hat(-k) = b_hat(k) on the stored half spectrum (kz = 0 and Nyquist
+    # planes hold both k and -k), which makes B a symmetric matrix
+    for n in ((8, 8, 8), (6, 10, 4)):
+        bk = synth.bias_multiplier_half(n, tuple(3.0 * v for v in n), 0.8, 2.5)
+        full = linbias.bias_full(bk, n)
+        neg = full[(-np.arange(n[0])) % n[0]][:, (-np.arange(n[1])) % n[1]][:, :, (-np.arange(n[2])) % n[2]]
+        assert np.array_equal(full, neg)
+        B = linbias.bias_matrix(bk, n)
+        assert np.abs(B - B.T).max() <= 1e-14
