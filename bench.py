@@ -115,6 +115,46 @@ def linear_bias_hvp_bytes(n, lognormal):
     return fwd + hvp + inv
 
 
+def batched_workload(dev, rtol):
+    """64 independent reconstructions (n in {32, 48, 64, 96}) solved together
+    in mixed precision, against sequential plain-FP64 single-grid solves of
+    the same instances."""
+    import torch
+    from paper_0911_1407_amd import synth
+    from paper_0911_1407_amd.binding import Batch, Plan, make_opts, pl_newton_krylov_solve
+    t0 = time.time()
+    insts = synth.batch_instances(count=64)
+    print(f"# generated 64 batch instances in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    bt = Batch(insts, precision="mixed", device=dev)
+    bt.solve(rtol=rtol)  # warm-up (also builds the CG graph)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, binfos = bt.solve(rtol=rtol)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    nconv = sum(1 for i in binfos if i["status"] == 0)
+    # sequential plain FP64 single-grid solves of the same instances
+    t_seq = 0.0
+    for it in insts:
+        pp = Plan(it["n"], it["box"], precision="fp64", device=dev)
+        pp.set_instance(it)
+        s0 = torch.full(it["n"], float(it["mu"]), dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pl_newton_krylov_solve(pp.h, s0, make_opts(rtol=rtol))
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - t0
+        pp.close()
+    batch = {"instances": len(insts), "converged": nconv, "ms_batched_mixed": 1e3 * t_batch,
+             "instances_per_s_batched": len(insts) / t_batch,
+             "ms_sequential_fp64": 1e3 * t_seq, "instances_per_s_sequential_fp64": len(insts) / t_seq,
+             "speedup": t_seq / t_batch,
+             "cg_its_total": sum(i["cg_its"] for i in binfos)}
+    print(f"# batch: {1e3 * t_batch:.0f} ms batched mixed vs {1e3 * t_seq:.0f} ms sequential fp64 "
+          f"({nconv}/64 converged)", file=sys.stderr, flush=True)
+    return batch
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +164,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--only-hvp", action="store_true", help="profiling aid: only the isolated HVP loop")
+    ap.add_argument("--only-batch", action="store_true", help="profiling aid: only the batched workload")
     ap.add_argument("--n", type=int, default=None, help="override the grid length (same cell size)")
     ap.add_argument("--workload", default="sel256", choices=["sel256", "bias256", "big512"],
                     help="sel256: 256^3 selection workload (default); bias256: beta = 1.5, nbar = 2 "
@@ -143,6 +184,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.only_batch:
+        print(json.dumps(batched_workload(dev, 1e-6)))
+        return
     t0 = time.time()
     inst = synth.config_instance(args.workload, n=args.n)
     print(f"# generated inputs n={inst['n']} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
@@ -353,38 +397,7 @@ def main():
     # ---------------- batched workload ----------------
     batch = None
     if not args.no_batch and args.workload == "sel256" and args.n is None:
-        from paper_0911_1407_amd.binding import Batch
-        t0 = time.time()
-        insts = synth.batch_instances(count=64)
-        print(f"# generated 64 batch instances in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
-        bt = Batch(insts, precision="mixed", device=dev)
-        bt.solve(rtol=rtol)  # warm-up (also builds the CG graph)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, binfos = bt.solve(rtol=rtol)
-        torch.cuda.synchronize()
-        t_batch = time.perf_counter() - t0
-        nconv = sum(1 for i in binfos if i["status"] == 0)
-        # sequential plain FP64 single-grid solves of the same instances
-        t_seq = 0.0
-        for it in insts:
-            pp = Plan(it["n"], it["box"], precision="fp64", device=dev)
-            pp.set_instance(it)
-            s0 = torch.full(it["n"], float(it["mu"]), dtype=torch.float64, device=dev)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            from paper_0911_1407_amd.binding import make_opts, pl_newton_krylov_solve
-            pl_newton_krylov_solve(pp.h, s0, make_opts(rtol=rtol))
-            torch.cuda.synchronize()
-            t_seq += time.perf_counter() - t0
-            pp.close()
-        batch = {"instances": len(insts), "converged": nconv, "ms_batched_mixed": 1e3 * t_batch,
-                 "instances_per_s_batched": len(insts) / t_batch,
-                 "ms_sequential_fp64": 1e3 * t_seq, "instances_per_s_sequential_fp64": len(insts) / t_seq,
-                 "speedup": t_seq / t_batch,
-                 "cg_its_total": sum(i["cg_its"] for i in binfos)}
-        print(f"# batch: {1e3 * t_batch:.0f} ms batched mixed vs {1e3 * t_seq:.0f} ms sequential fp64 "
-              f"({nconv}/64 converged)", file=sys.stderr, flush=True)
+        batch = batched_workload(dev, rtol)
 
     # ---------------- CPU oracle baseline ----------------
     cpu = None
