@@ -517,7 +517,20 @@ int line_search(pl_plan* p, cx<T>* x, double a_start, const pl_solve_opts& o, do
                      p->partials);
   HIPCHK(p, hipGetLastError());
   HIPCHK(p, finalize(p, NB_RED, 3, FIN_STORE, SC_LS_B, invN));
-  rc = read_scalars(p);
+  // the first batch of trial steps does not depend on the dots: it is
+  // launched before the one read-back that returns both
+  auto eval_batch = [&](double a0) -> int {
+    if (p->model == MODEL_GAUSSIAN)
+      hipLaunchKernelGGL((ls_eval_gauss_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream,
+                         View<T>::preal(p), p->e, p->prob.w, p->prob.counts, p->prob.nbar, a0, p->N, p->partials);
+    else
+      hipLaunchKernelGGL((ls_eval_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, View<T>::preal(p),
+                         p->e, p->prob.counts, p->prob.beta, a0, p->N, p->partials);
+    HIPCHK(p, hipGetLastError());
+    HIPCHK(p, finalize(p, NB_RED, 4, FIN_STORE, SC_DF, 1.0));
+    return read_scalars(p);
+  };
+  rc = eval_batch(a_start);
   if (rc) return rc;
   const double b = p->h_scal[SC_LS_B], c = p->h_scal[SC_LS_C], slope = p->h_scal[SC_LS_SLOPE];
   *alpha = -1.0;
@@ -525,16 +538,10 @@ int line_search(pl_plan* p, cx<T>* x, double a_start, const pl_solve_opts& o, do
   if (slope < 0.0) {
     double a0 = a_start;
     for (int batch = 0; batch < 8 && *alpha < 0.0; ++batch) {
-      if (p->model == MODEL_GAUSSIAN)
-        hipLaunchKernelGGL((ls_eval_gauss_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream,
-                           View<T>::preal(p), p->e, p->prob.w, p->prob.counts, p->prob.nbar, a0, p->N, p->partials);
-      else
-        hipLaunchKernelGGL((ls_eval_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, View<T>::preal(p),
-                           p->e, p->prob.counts, p->prob.beta, a0, p->N, p->partials);
-      HIPCHK(p, hipGetLastError());
-      HIPCHK(p, finalize(p, NB_RED, 4, FIN_STORE, SC_DF, 1.0));
-      rc = read_scalars(p);
-      if (rc) return rc;
+      if (batch > 0) {
+        rc = eval_batch(a0);
+        if (rc) return rc;
+      }
       double a = a0;
       for (int j = 0; j < 4; ++j, a *= 0.5) {
         double df = a * b + 0.5 * a * a * c + p->h_scal[SC_DF + j];
@@ -2647,12 +2654,6 @@ int lb_line_search(pl_plan* p, int model, const double* bk, const double* x_real
                      p->partials);
   HIPCHK(p, hipGetLastError());
   HIPCHK(p, finalize(p, NB_RED, 3, FIN_STORE, SC_LS_B, invN));
-  rc = read_scalars(p);
-  if (rc) return rc;
-  const double b = p->h_scal[SC_LS_B], c = p->h_scal[SC_LS_C], slope = p->h_scal[SC_LS_SLOPE];
-  *alpha = -1.0;
-  *descent = slope < 0.0;
-  if (!(slope < 0.0)) return PL_OK;
   const int nb = grid_blocks(p->N);
   // B phi(x) into e (phi' is recomputed by the next gradient)
   p->lb_ready = false;
@@ -2661,19 +2662,32 @@ int lb_line_search(pl_plan* p, int model, const double* bk, const double* x_real
   HIPCHK(p, hipGetLastError());
   rc = lb_conv(p, bk, p->s_ws, p->e);
   if (rc) return rc;
-  double a = 1.0;
-  for (int j = 0; j < 40; ++j, a *= 0.5) {
+  // one trial step a: its likelihood difference into SC_DF, then the
+  // read-back (the first trial goes out with the dots)
+  auto trial = [&](double a) -> int {
     hipLaunchKernelGGL(lb_phi_step_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, x_real, p->preal, a, model,
                        p->s_ws, p->N);
     HIPCHK(p, hipGetLastError());
-    rc = lb_conv(p, bk, p->s_ws, p->s_ws);
-    if (rc) return rc;
+    int trc = lb_conv(p, bk, p->s_ws, p->s_ws);
+    if (trc) return trc;
     hipLaunchKernelGGL(lb_step_lik_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->s_ws, p->e, p->prob.w,
                        p->prob.counts, p->prob.nbar, p->N, p->partials);
     HIPCHK(p, hipGetLastError());
     HIPCHK(p, finalize(p, nb, 1, FIN_STORE, SC_DF, 1.0));
-    rc = read_scalars(p);
-    if (rc) return rc;
+    return read_scalars(p);
+  };
+  rc = trial(1.0);
+  if (rc) return rc;
+  const double b = p->h_scal[SC_LS_B], c = p->h_scal[SC_LS_C], slope = p->h_scal[SC_LS_SLOPE];
+  *alpha = -1.0;
+  *descent = slope < 0.0;
+  if (!(slope < 0.0)) return PL_OK;
+  double a = 1.0;
+  for (int j = 0; j < 40; ++j, a *= 0.5) {
+    if (j > 0) {
+      rc = trial(a);
+      if (rc) return rc;
+    }
     const double df = a * b + 0.5 * a * a * c + p->h_scal[SC_DF];
     if (df <= o.ls_c1 * a * slope) {
       *alpha = a;
