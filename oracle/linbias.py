@@ -193,14 +193,16 @@ def _dot(c, N, a, b):
     return float(np.sum(c * (np.conj(a) * b).real) / N)
 
 
-def truncated_pcg(prob, bk, x, kind, g_hat, tol_abs, max_cg):
+def truncated_pcg(prob, bk, x, kind, g_hat, tol_abs, max_cg, precond="p25"):
     """PCG on H p = -g in half-spectrum coordinates, stopped at ||r|| <= tol_abs
     or at the first direction of non-positive curvature.  If that happens
     before any step, the preconditioned steepest-descent direction M^-1 (-g)
-    is returned.  Preconditioner M_k = 1/lambda_k + c with c the 25th
-    percentile over the cells of max(0, phi'^2 N / y^2 + phi'' B^T u), floored
-    at 1e-3 times its mean (the constant only changes the iteration path, not
-    the minimiser reached)."""
+    is returned.  Preconditioner M_k = 1/lambda_k + c with c, over the cells
+    of deff = max(0, phi'^2 N / y^2 + phi'' B^T u), either the 25th
+    percentile floored at 1e-3 times the mean (precond="p25") or the mean
+    itself (precond="mean").  The paper gives no preconditioner; the constant
+    changes the iteration path, and the tests check that the minimiser
+    reached from the prior mean does not depend on it."""
     n, N = prob.n, prob.ncells
     cw = hermitian_weights(n)
     inv_lam = inv_lambda_half(prob)
@@ -209,7 +211,11 @@ def truncated_pcg(prob, bk, x, kind, g_hat, tol_abs, max_cg):
     a = dphi(kind, x)
     deff = a * a * np.where(prob.counts > 0, prob.counts / y ** 2, 0.0) + d2phi(kind, x) * bias_apply(bk, u)
     deff = np.maximum(deff, 0.0)
-    M = inv_lam + max(float(np.percentile(deff, 25)), 1e-3 * float(np.mean(deff)))
+    if precond == "mean":
+        c = float(np.mean(deff))
+    else:
+        c = max(float(np.percentile(deff, 25)), 1e-3 * float(np.mean(deff)))
+    M = inv_lam + c
     Minv = np.where(M > 0, 1.0 / np.where(M > 0, M, 1.0), 0.0)
     sol = np.zeros_like(g_hat)
     r = -g_hat
@@ -273,9 +279,10 @@ def _armijo(prob, bk, x, p, b, c, slope, kind, c1=1e-4, max_halvings=60):
     return None
 
 
-def newton_spectral(prob, bk, kind, rtol=1e-12, max_newton=200, max_cg=20000, eta_max=0.5):
-    """Inexact Newton with the truncated PCG, from x0 = m (uniform), the
-    iterate held as its half spectrum.  Returns (x, info) with info =
+def newton_spectral(prob, bk, kind, rtol=1e-12, max_newton=200, max_cg=20000, eta_max=0.5, precond="p25"):
+    """Inexact Newton with the truncated PCG (preconditioner constant as in
+    ``truncated_pcg``), from x0 = m (uniform), the iterate held as its half
+    spectrum.  Returns (x, info) with info =
     dict(newton_its, cg_its, status, rel_grad); norms are those of the
     spectral gradient (Parseval)."""
     n, N = prob.n, prob.ncells
@@ -293,7 +300,7 @@ def newton_spectral(prob, bk, kind, rtol=1e-12, max_newton=200, max_cg=20000, et
         if gn <= rtol * g0:
             break
         eta = min(eta_max, max(np.sqrt(gn / g0), 0.5 * rtol * g0 / gn))
-        p_hat, its = truncated_pcg(prob, bk, x, kind, g_hat, eta * gn, max_cg)
+        p_hat, its = truncated_pcg(prob, bk, x, kind, g_hat, eta * gn, max_cg, precond)
         info["cg_its"] += its
         Sp = inv_lam * p_hat
         b = _dot(cw, N, Sp, x_hat - m_hat)
