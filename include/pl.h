@@ -106,6 +106,10 @@ typedef struct pl_solve_info {
   double rel_grad; /* final ||g|| / ||g0|| (adjoint: final ||r|| / ||b||) */
   double grad0;    /* ||g(s0)|| (adjoint: ||b||) */
   double obj;      /* final objective f(s) (constants of eq. 3 dropped) */
+  int fp64_steps;  /* mixed-precision solves: Newton steps whose FP32 direction
+                      failed the line search and were redone with an FP64
+                      inner solve (0 when every step ran in FP32; always 0
+                      for FP64 solves and adjoints) */
 } pl_solve_info;
 
 /* Fill opts with defaults (precision = -1: use the plan's). */
@@ -162,6 +166,14 @@ int pl_hessvec_hat_f32(pl_plan* plan, const float* v_hat, float* hv_hat);
    info written in every case. */
 int pl_newton_krylov_solve(pl_plan* plan, double* s_inout, const pl_solve_opts* opts,
                            pl_solve_info* info);
+/* Same solve; s_hat_out (device, Nh interleaved complex, nullable) also
+   receives the solver's own iterate as a half spectrum, F s* (the solver
+   keeps s in this form, where S_L^-1 is an exact pointwise product, section
+   2.3), so that the gradient at the returned MAP can be evaluated without
+   the FFT round trip of the real field, whose roundoff max 1/lambda
+   amplifies. */
+int pl_newton_krylov_solve_hat(pl_plan* plan, double* s_inout, double* s_hat_out, const pl_solve_opts* opts,
+                               pl_solve_info* info);
 
 /* Adjoint of a scalar loss L(s*) at the MAP s* (device, N): solves
    H(s*) lambda = dL_ds (device, N) by PCG to ||r|| <= opts->rtol ||dL_ds||, writes
@@ -236,6 +248,11 @@ int pl_linear_bias_hessvec(pl_plan* plan, int model, const double* bk, const dou
    PL_MIXED.  Synchronises the stream. */
 int pl_linear_bias_solve(pl_plan* plan, int model, const double* bk, double* x_inout, const pl_solve_opts* opts,
                          pl_solve_info* info);
+/* Same solve; x_hat_out (device, Nh interleaved complex, nullable) also
+   receives the iterate as a half spectrum, F x* (the form the solver keeps,
+   as in pl_newton_krylov_solve_hat). */
+int pl_linear_bias_solve_hat(pl_plan* plan, int model, const double* bk, double* x_inout, double* x_hat_out,
+                             const pl_solve_opts* opts, pl_solve_info* info);
 
 /* The Krylov step of section 3.1 with a nonlinear-CG search vector, the
    paper-literal form of the solver: s <- s + tau xi with the step length of
@@ -355,8 +372,11 @@ typedef struct pl_batch pl_batch;
 
 /* n: n_inst * 3 grid lengths, box: n_inst * 3 box sides (Mpc/h), host arrays.
    precision: PL_FP64 or PL_MIXED (Krylov/HVP in FP32 for PL_MIXED solves).
-   The batch runs on its own internal stream and joins hip_stream (the
-   caller's) at the start and end of pl_batch_solve. */
+   The batch runs on its own internal stream (HIP graphs are captured on
+   it).  pl_batch_set_workspace, pl_batch_set_problem and pl_batch_solve
+   first make it wait for the work already queued on hip_stream (the
+   caller's), so arrays the caller is still writing there are read after
+   those writes; each of them returns after its own work is complete. */
 int pl_batch_create(pl_batch** out, int n_inst, const int32_t* n, const double* box, int precision,
                     void* hip_stream, size_t* workspace_bytes);
 int pl_batch_set_workspace(pl_batch* batch, void* dev_ptr);

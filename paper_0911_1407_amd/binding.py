@@ -36,7 +36,7 @@ EXPORTED = ("pl_default_opts", "pl_plan_create", "pl_plan_set_workspace", "pl_pl
             "pl_plan_get_variants", "pl_plan_set_variants", "pl_plan_prior_is_radial", "pl_lsq_solve", "pl_nlcg_solve", "pl_lognormal_prior",
             "pl_gaussian_map_solve",
             "pl_inverse_weight", "pl_compare_fields", "pl_linear_bias_grad", "pl_linear_bias_hessvec",
-            "pl_linear_bias_solve")
+            "pl_linear_bias_solve", "pl_newton_krylov_solve_hat", "pl_linear_bias_solve_hat")
 
 # priors of the linear-bias calls (PL_MODEL_* in pl.h)
 MODEL_LOGNORMAL = 0
@@ -67,7 +67,7 @@ class pl_solve_opts(ctypes.Structure):
 class pl_solve_info(ctypes.Structure):
     _fields_ = [("newton_its", ctypes.c_int), ("cg_its", ctypes.c_int), ("hvps", ctypes.c_int),
                 ("status", ctypes.c_int), ("rel_grad", ctypes.c_double), ("grad0", ctypes.c_double),
-                ("obj", ctypes.c_double)]
+                ("obj", ctypes.c_double), ("fp64_steps", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_} | {"status_name": STATUS_NAMES.get(self.status)}
@@ -100,6 +100,8 @@ def load(path=LIB_PATH):
     lib.pl_hessvec_hat.argtypes = [vp, vp, vp]
     lib.pl_hessvec_hat_f32.argtypes = [vp, vp, vp]
     lib.pl_newton_krylov_solve.argtypes = [vp, vp, ctypes.POINTER(pl_solve_opts), ctypes.POINTER(pl_solve_info)]
+    lib.pl_newton_krylov_solve_hat.argtypes = [vp, vp, vp, ctypes.POINTER(pl_solve_opts),
+                                               ctypes.POINTER(pl_solve_info)]
     lib.pl_solve_adjoint.argtypes = [vp, vp, vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
                                      ctypes.POINTER(dbl), vp, vp, ctypes.POINTER(pl_solve_opts),
                                      ctypes.POINTER(pl_solve_info)]
@@ -127,6 +129,8 @@ def load(path=LIB_PATH):
     lib.pl_linear_bias_hessvec.argtypes = [vp, i32, vp, vp, vp, vp]
     lib.pl_linear_bias_solve.argtypes = [vp, i32, vp, vp, ctypes.POINTER(pl_solve_opts),
                                          ctypes.POINTER(pl_solve_info)]
+    lib.pl_linear_bias_solve_hat.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(pl_solve_opts),
+                                             ctypes.POINTER(pl_solve_info)]
     lib.pl_batch_last_error.argtypes = [vp]
     lib.pl_batch_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -218,6 +222,14 @@ def pl_newton_krylov_solve(h, s_inout, opts=None):
     return info
 
 
+def pl_newton_krylov_solve_hat(h, s_inout, s_hat_out, opts=None):
+    info = pl_solve_info()
+    rc = load().pl_newton_krylov_solve_hat(h, _ptr(s_inout), _ptr(s_hat_out), ctypes.byref(opts) if opts else None,
+                                           ctypes.byref(info))
+    _check(h, rc, allow=(PL_ERR_NOT_CONVERGED, PL_ERR_LINESEARCH))
+    return info
+
+
 def pl_solve_adjoint(h, s_star, dL_ds, lambda_out=None, dL_dN=None, dL_dw=None, opts=None):
     dA, db, dn = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     info = pl_solve_info()
@@ -268,6 +280,14 @@ def pl_linear_bias_solve(h, model, bk, x_inout, opts=None):
     info = pl_solve_info()
     rc = load().pl_linear_bias_solve(h, int(model), _ptr(bk), _ptr(x_inout), ctypes.byref(opts) if opts else None,
                                      ctypes.byref(info))
+    _check(h, rc, allow=(PL_ERR_NOT_CONVERGED, PL_ERR_LINESEARCH))
+    return info
+
+
+def pl_linear_bias_solve_hat(h, model, bk, x_inout, x_hat_out, opts=None):
+    info = pl_solve_info()
+    rc = load().pl_linear_bias_solve_hat(h, int(model), _ptr(bk), _ptr(x_inout), _ptr(x_hat_out),
+                                         ctypes.byref(opts) if opts else None, ctypes.byref(info))
     _check(h, rc, allow=(PL_ERR_NOT_CONVERGED, PL_ERR_LINESEARCH))
     return info
 
@@ -454,13 +474,19 @@ class Plan:
             pl_hessvec_hat_f32(self.h, v_hat, out)
         return out
 
-    def solve(self, s0=None, **kw):
+    def solve(self, s0=None, want_hat=False, **kw):
+        """MAP solve: (s, info), or (s, s_hat, info) with want_hat (the
+        solver's half-spectrum iterate, complex128 on the device)."""
         if s0 is None:
             # s0 = mu (0 before a problem is set; the library then reports it)
             mu = float(self.params["mu"]) if self.params else 0.0
             s = self.torch.full(self.n, mu, dtype=self.torch.float64, device=self.device)
         else:
             s = self._dev(s0).clone()
+        if want_hat:
+            s_hat = self.torch.empty(self.half_shape, dtype=self.torch.complex128, device=self.device)
+            info = pl_newton_krylov_solve_hat(self.h, s, s_hat, make_opts(**kw))
+            return s, s_hat, info.as_dict()
         info = pl_newton_krylov_solve(self.h, s, make_opts(**kw))
         return s, info.as_dict()
 
@@ -498,7 +524,7 @@ class Plan:
         pl_linear_bias_hessvec(self.h, self._model(model), bk, None if x is None else self._dev(x), v, out)
         return out
 
-    def solve_linear_bias(self, model, bk, x0=None, **kw):
+    def solve_linear_bias(self, model, bk, x0=None, want_hat=False, **kw):
         """MAP with the linear bias b_hat (bk, half spectrum): (x, info); the
         start defaults to the prior mean (mu, or 0 for the Gaussian prior)."""
         m = self._model(model)
@@ -509,6 +535,10 @@ class Plan:
         else:
             x = self._dev(x0).clone()
         kw.setdefault("precision", 0)
+        if want_hat:
+            x_hat = self.torch.empty(self.half_shape, dtype=self.torch.complex128, device=self.device)
+            info = pl_linear_bias_solve_hat(self.h, m, bk, x, x_hat, make_opts(**kw))
+            return x, x_hat, info.as_dict()
         info = pl_linear_bias_solve(self.h, m, bk, x, make_opts(**kw))
         return x, info.as_dict()
 

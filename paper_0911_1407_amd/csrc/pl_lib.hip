@@ -625,6 +625,7 @@ int newton_solve(pl_plan* p, double* s_io, const pl_solve_opts& o, pl_solve_info
         if (alpha < 0.0) {
           rc = newton_step<double>(p, eta * gn, o, inf, &alpha, &descent);
           if (rc) return rc;
+          ++inf.fp64_steps;
         }
       }
       if (alpha < 0.0) {
@@ -1187,7 +1188,8 @@ int pl_hessvec_hat_f32(pl_plan* p, const float* v_hat, float* hv_hat) {
   return hvp_hat<float>(p, (const cx<float>*)v_hat, (cx<float>*)hv_hat, &nb);
 }
 
-int pl_newton_krylov_solve(pl_plan* p, double* s_inout, const pl_solve_opts* opts, pl_solve_info* info) {
+int pl_newton_krylov_solve_hat(pl_plan* p, double* s_inout, double* s_hat_out, const pl_solve_opts* opts,
+                               pl_solve_info* info) {
   int rc = check_ready(p);
   if (rc) return rc;
   if (!s_inout) return fail(p, PL_ERR_INVALID_ARG, "null s_inout");
@@ -1196,11 +1198,18 @@ int pl_newton_krylov_solve(pl_plan* p, double* s_inout, const pl_solve_opts* opt
     return fail(p, PL_ERR_INVALID_ARG, "invalid solve options");
   rc = check_finite(p, s_inout, p->N, "s_inout");
   if (rc) return rc;
-  if (o.precision == PL_MIXED) {
-    if (p->precision != PL_MIXED) return fail(p, PL_ERR_INVALID_ARG, "mixed solve needs a PL_MIXED plan");
-    return newton_solve<float>(p, s_inout, o, info);
+  if (o.precision == PL_MIXED && p->precision != PL_MIXED)
+    return fail(p, PL_ERR_INVALID_ARG, "mixed solve needs a PL_MIXED plan");
+  rc = o.precision == PL_MIXED ? newton_solve<float>(p, s_inout, o, info) : newton_solve<double>(p, s_inout, o, info);
+  if (s_hat_out && (rc == PL_OK || rc == PL_ERR_NOT_CONVERGED || rc == PL_ERR_LINESEARCH)) {
+    HIPCHK(p, hipMemcpyAsync(s_hat_out, p->s_hat, sizeof(cx<double>) * p->Nh, hipMemcpyDeviceToDevice, p->stream));
+    HIPCHK(p, hipStreamSynchronize(p->stream));
   }
-  return newton_solve<double>(p, s_inout, o, info);
+  return rc;
+}
+
+int pl_newton_krylov_solve(pl_plan* p, double* s_inout, const pl_solve_opts* opts, pl_solve_info* info) {
+  return pl_newton_krylov_solve_hat(p, s_inout, nullptr, opts, info);
 }
 
 int pl_solve_adjoint(pl_plan* p, const double* s_star, const double* dL_ds, double* lambda_out, double* dL_dA,
@@ -2139,6 +2148,7 @@ int batch_newton(pl_batch* b, double* const* s_io, const pl_solve_opts& o, pl_so
       inf[i].cg_its += r.cg_its;
       inf[i].hvps += r.hvps;
       inf[i].newton_its += r.newton_its;
+      inf[i].fp64_steps += r.newton_its;
       inf[i].obj = r.obj;
       inf[i].status = gfin <= o.rtol * g0[i] ? PL_OK : (rc2 != PL_OK ? rc2 : PL_ERR_NOT_CONVERGED);
     }
@@ -2211,9 +2221,19 @@ int pl_batch_create(pl_batch** out, int n_inst, const int32_t* n, const double* 
   return PL_OK;
 }
 
+// The batch's internal stream waits for the work queued so far on the
+// caller's stream (which may still be writing the arrays handed over).
+static int join_user_stream(pl_batch* b) {
+  BHIP(b, hipEventRecord(b->ev, b->user_stream));
+  BHIP(b, hipStreamWaitEvent(b->stream, b->ev, 0));
+  return PL_OK;
+}
+
 int pl_batch_set_workspace(pl_batch* b, void* dev_ptr) {
   if (!b) return PL_ERR_INVALID_ARG;
   if (!dev_ptr || ((uintptr_t)dev_ptr & 255)) return bfail(b, PL_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  int jrc = join_user_stream(b);
+  if (jrc) return jrc;
   b->ws = (char*)dev_ptr;
   for (int i = 0; i < b->K; ++i) {
     int rc = pl_plan_set_workspace(b->plans[i], b->ws + b->plan_off[i]);
@@ -2237,7 +2257,9 @@ int pl_batch_set_workspace(pl_batch* b, void* dev_ptr) {
 int pl_batch_set_problem(pl_batch* b, int i, const pl_problem* prob) {
   if (!b || i < 0 || i >= b->K) return PL_ERR_INVALID_ARG;
   if (!b->ws) return bfail(b, PL_ERR_INVALID_ARG, "workspace not set");
-  int rc = pl_set_problem(b->plans[i], prob);
+  int rc = join_user_stream(b);
+  if (rc) return rc;
+  rc = pl_set_problem(b->plans[i], prob);
   if (rc) return bfail(b, rc, "instance " + std::to_string(i) + ": " + pl_last_error(b->plans[i]));
   return PL_OK;
 }
@@ -2254,9 +2276,8 @@ int pl_batch_solve(pl_batch* b, double* const* s_inout, const pl_solve_opts* opt
   if (!(o.rtol >= 0.0) || o.max_newton < 0 || o.max_cg <= 0 || !(o.eta_max > 0.0) || !(o.ls_c1 > 0.0 && o.ls_c1 < 1.0))
     return bfail(b, PL_ERR_INVALID_ARG, "invalid solve options");
   // order after the caller's pending work
-  BHIP(b, hipEventRecord(b->ev, b->user_stream));
-  BHIP(b, hipStreamWaitEvent(b->stream, b->ev, 0));
-  int rc;
+  int rc = join_user_stream(b);
+  if (rc) return rc;
   if (o.precision == PL_MIXED) {
     if (b->precision != PL_MIXED) return bfail(b, PL_ERR_INVALID_ARG, "mixed solve needs a PL_MIXED batch");
     rc = batch_newton<float>(b, s_inout, o, infos);
@@ -2841,6 +2862,11 @@ int pl_linear_bias_hessvec(pl_plan* p, int model, const double* bk, const double
 
 int pl_linear_bias_solve(pl_plan* p, int model, const double* bk, double* x_inout, const pl_solve_opts* opts,
                          pl_solve_info* info) {
+  return pl_linear_bias_solve_hat(p, model, bk, x_inout, nullptr, opts, info);
+}
+
+int pl_linear_bias_solve_hat(pl_plan* p, int model, const double* bk, double* x_inout, double* x_hat_out,
+                             const pl_solve_opts* opts, pl_solve_info* info) {
   int rc = check_ready(p);
   if (rc) return rc;
   if (!x_inout) return fail(p, PL_ERR_INVALID_ARG, "null pointer");
@@ -2856,6 +2882,10 @@ int pl_linear_bias_solve(pl_plan* p, int model, const double* bk, double* x_inou
   p->model = model;
   rc = lb_newton_solve(p, model, bk, x_inout, o, info);
   p->model = MODEL_LOGNORMAL;
+  if (x_hat_out && (rc == PL_OK || rc == PL_ERR_NOT_CONVERGED || rc == PL_ERR_LINESEARCH)) {
+    HIPCHK(p, hipMemcpyAsync(x_hat_out, p->s_hat, sizeof(cx<double>) * p->Nh, hipMemcpyDeviceToDevice, p->stream));
+    HIPCHK(p, hipStreamSynchronize(p->stream));
+  }
   return rc;
 }
 

@@ -24,3 +24,21 @@ def oracle_problem(inst):
 @pytest.fixture
 def rng():
     return np.random.default_rng(1234)
+
+
+def assert_elementwise(got, ref, tol, floor=1e-2, what=""):
+    """Every element within tol of the reference, in units of
+    max(|ref_i|, floor * max|ref|) (complex arrays by modulus): a wrong value
+    confined to small entries (masked cells, a Nyquist plane, the ragged
+    edge of a tile) cannot hide under a norm.  Returns the worst error in
+    units of the bound (<= 1)."""
+    a = np.asarray(got)
+    b = np.asarray(ref)
+    assert a.shape == b.shape, (a.shape, b.shape)
+    mag = np.abs(b)
+    scale = np.maximum(mag, floor * float(mag.max()))
+    worst = float(np.max(np.abs(a.astype(np.complex128) - b) / (tol * scale))) if mag.max() > 0 else \
+        float(np.abs(a).max())
+    print(f"elementwise {what}: worst error {worst:.3f} of the bound (tol {tol:g}, floor {floor:g})", flush=True)
+    assert worst <= 1.0, (what, worst)
+    return worst

@@ -1,0 +1,179 @@
+"""Write the stored oracle results that the full-size GPU parity tests use.
+
+    python tests/golden/make_golden.py [sel256] [bias256] [batch64] [big512]
+
+Every value written here comes from the CPU oracle (``oracle/``) on inputs
+drawn by the seeded generator (``paper_0911_1407_amd.synth``, which holds
+none of the method's arithmetic); nothing is taken from the HIP library.
+
+At 256^3 and 512^3 a full field does not fit a small fixture, so each file
+keeps:
+
+* a fingerprint of the inputs (sha256 of the counts, sums of w and s_true),
+  which the tests recompute before they compare anything;
+* the oracle's solve record (Newton and CG steps, final ||g|| / ||g0||);
+* full-field sums of the MAP field s* (sum s*, sum s*^2, min, max) and of the
+  adjoint field where one is solved;
+* s* (and lambda) at sampled cells: a seeded uniform draw of flat indices
+  plus cells chosen for their structure (masked cells, the largest counts,
+  the extremes of s*, the first and last cell), since a wrong value confined
+  to small or special entries could hide in a norm.
+
+Workloads (the MAP is the unique minimiser of the negative log-posterior of
+section 2.3 / eq. 3 with the power-law bias of section 2.4, found by the
+oracle's spectral Newton-PCG of section 3.1 solved to ||g|| / ||g0|| <= 1e-10,
+well below the 1e-6 tolerance of the parity tests):
+
+* ``sel256``  -- 256^3 selection workload (sigma_G 1.5, radial selection
+  R = 200 Mpc/h, 20% masked 8^3 blocks, nbar 0.5, unit bias);
+* ``bias256`` -- the same selection with beta = 1.5, nbar = 2, plus the
+  adjoint of L = sum (s* - s_true)^2: lambda = H(s*)^-1 dL/ds* by the oracle's
+  spectral PCG to 1e-12, dL/dA, dL/dbeta, dL/dnbar, and dL/dN along a seeded
+  direction u, +-1 in the cells with counts and 0 elsewhere
+  (sum_i beta lambda_i u_i);
+* ``batch64`` -- the 64 uneven instances (n in {32, 48, 64, 96}) of the batched
+  workload, each solved separately;
+* ``big512``  -- 512^3 (sigma_G 2, nbar 0.2, beta 1.2, R = 400 Mpc/h).
+"""
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from oracle import adjoint as o_adj  # noqa: E402
+from oracle import newton as o_newton  # noqa: E402
+from oracle.grid import Problem  # noqa: E402
+from paper_0911_1407_amd import synth  # noqa: E402
+
+SAMPLE_SEED = 20091107  # seeds the uniform cell sample (independent of the inputs)
+
+
+def problem(inst):
+    return Problem(inst["n"], inst["box"], inst["w"], inst["counts"], inst["pk"], inst["amp"], inst["mu"],
+                   inst["nbar"], inst["beta"], inst.get("inv_p0", 0.0))
+
+
+def fingerprint(inst):
+    """Input checksums: the counts exactly (integers), w and s_true by their sums."""
+    return {
+        "counts_sha256": hashlib.sha256(np.ascontiguousarray(inst["counts"]).tobytes()).hexdigest(),
+        "counts_sum": float(np.sum(inst["counts"])),
+        "w_sum": float(np.sum(inst["w"])),
+        "s_true_sum": float(np.sum(inst["s_true"])),
+        "s_true_sumsq": float(np.sum(inst["s_true"] ** 2)),
+    }
+
+
+def sample_cells(inst, s_star, n_uniform, tag):
+    """Flat cell indices: a seeded uniform draw plus structurally special cells."""
+    N = s_star.size
+    rng = np.random.default_rng([SAMPLE_SEED, tag])
+    idx = [rng.integers(0, N, size=n_uniform)]
+    w = inst["w"].ravel()
+    masked = np.flatnonzero(w == 0.0)
+    if masked.size:
+        idx.append(masked[rng.integers(0, masked.size, size=min(64, masked.size))])
+    counts = inst["counts"].ravel()
+    idx.append(np.argsort(counts, kind="stable")[-32:])
+    flat = s_star.ravel()
+    idx.append(np.argsort(flat, kind="stable")[:16])
+    idx.append(np.argsort(flat, kind="stable")[-16:])
+    idx.append(np.array([0, N - 1]))
+    return np.unique(np.concatenate(idx))
+
+
+def field_stats(x):
+    return {"sum": float(np.sum(x)), "sumsq": float(np.sum(x * x)), "min": float(np.min(x)),
+            "max": float(np.max(x))}
+
+
+def solve_map(inst, rtol=1e-10):
+    P = problem(inst)
+    t = time.time()
+    s, s_hat, info = o_newton.newton_krylov(P, rtol=rtol, max_newton=200, max_cg=5000, return_hat=True)
+    dt = time.time() - t
+    rec = {"rtol": rtol, "newton_its": int(info["newton_its"]), "cg_its": int(info["cg_its"]),
+           "rel_grad": float(info["rel_grad"]), "status": info["status"], "seconds": dt}
+    return P, s, rec
+
+
+def write(name, obj):
+    path = os.path.join(HERE, name + ".json")
+    with open(path, "w") as f:
+        json.dump(obj, f, indent=1)
+        f.write("\n")
+    print(f"wrote {path}", flush=True)
+
+
+def golden_map(name, tag, with_adjoint=False, n_uniform=4096):
+    t = time.time()
+    inst = synth.config_instance(name)
+    print(f"{name}: inputs in {time.time() - t:.1f}s", flush=True)
+    P, s, rec = solve_map(inst)
+    print(f"{name}: oracle MAP {rec}", flush=True)
+    assert rec["status"] == "ok", rec
+    idx = sample_cells(inst, s, n_uniform, tag)
+    out = {
+        "workload": name, "n": list(inst["n"]), "box": list(inst["box"]), "sigma": inst["sigma"],
+        "nbar": inst["nbar"], "beta": inst["beta"], "amp": inst["amp"], "mu": inst["mu"], "seed": inst["seed"],
+        "inputs": fingerprint(inst), "oracle_solve": rec, "s_star": field_stats(s),
+        "cells": [int(i) for i in idx], "s_star_cells": [float(v) for v in s.ravel()[idx]],
+    }
+    if with_adjoint:
+        # L = sum (s* - s_true)^2 at the oracle MAP; adjoint by spectral PCG
+        L, dL = o_adj.squared_error_loss(s, inst["s_true"])
+        t = time.time()
+        lam, its = o_adj.adjoint_pcg(P, s, dL, rtol=1e-12, max_cg=50000)
+        grads = o_adj.param_grads(P, s, lam)
+        # direction of the counts derivative: +-1 in cells with counts (a
+        # perturbation there keeps N >= 0), 0 elsewhere
+        u = np.random.default_rng([SAMPLE_SEED, 100 + tag]).choice([-1.0, 1.0], size=inst["n"])
+        u = np.where(inst["counts"] > 0, u, 0.0)
+        out["adjoint"] = {
+            "loss": L, "cg_its": int(its), "rtol": 1e-12, "seconds": time.time() - t,
+            "dL_dA": grads["A"], "dL_dbeta": grads["beta"], "dL_dnbar": grads["nbar"],
+            "dL_dN_dot_u": float(np.sum(grads["N"] * u)),
+            "u_seed": [SAMPLE_SEED, 100 + tag],
+            "lambda": field_stats(lam), "lambda_cells": [float(v) for v in lam.ravel()[idx]],
+        }
+        print(f"{name}: adjoint cg {its} dA {grads['A']} dbeta {grads['beta']}", flush=True)
+    write(name + "_map", out)
+
+
+def golden_batch(n_cells=64):
+    insts = synth.batch_instances(count=64)
+    recs = []
+    for i, inst in enumerate(insts):
+        P, s, rec = solve_map(inst)
+        assert rec["status"] == "ok", (i, rec)
+        rng = np.random.default_rng([SAMPLE_SEED, 1000 + i])
+        idx = np.unique(np.concatenate([rng.integers(0, s.size, size=n_cells), [0, s.size - 1],
+                                        np.argsort(s.ravel(), kind="stable")[-4:]]))
+        recs.append({"i": i, "n": list(inst["n"]), "inputs": fingerprint(inst), "oracle_solve": rec,
+                     "s_star": field_stats(s), "cells": [int(v) for v in idx],
+                     "s_star_cells": [float(v) for v in s.ravel()[idx]]})
+        print(f"batch {i}: n={inst['n'][0]} {rec}", flush=True)
+    write("batch64_map", {"workload": "batch64", "count": 64, "master_seed": 3, "instances": recs})
+
+
+if __name__ == "__main__":
+    which = sys.argv[1:] or ["sel256", "bias256", "batch64"]
+    for w in which:
+        if w == "sel256":
+            golden_map("sel256", 1)
+        elif w == "bias256":
+            golden_map("bias256", 2, with_adjoint=True)
+        elif w == "batch64":
+            golden_batch()
+        elif w == "big512":
+            golden_map("big512", 4, with_adjoint=True)
+        else:
+            raise SystemExit(f"unknown workload {w}")

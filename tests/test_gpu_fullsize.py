@@ -2,21 +2,23 @@
 configuration the benchmark uses.
 
 The operators (the spectral HVP in FP64 and FP32, at the linearisation the
-gradient pipeline caches) are compared element by element with the oracle's
-FFT-based HVP at 256^3 and 512^3, with the tuned schedule the benchmark
-loads.  A full oracle solve at 256^3 takes tens of minutes of host CPU, and
-the MAP cannot be computed cell by cell, so for the solves at 256^3 and
-512^3 the checks use properties that hold at any size: the white-prior Lambert-W closed form cell
-by cell, the sum of expected counts equal to the sum of counts at the MAP
-(the k = 0 component of the gradient), mixed vs FP64 agreement, and adjoint
-derivatives against central differences through GPU solves.  Oracle parity
-of the MAP on the selection workload runs at 128^3 (same cells, selection
-radius and mask scaled with the box).
+gradient pipeline caches) are compared with the oracle's FFT-based HVP at
+256^3 and 512^3 as a whole (relative L2) and element by element (every
+output entry within the tolerance, in units of max(|ref|, 1e-2 max|ref|)),
+with the tuned schedule the benchmark loads.  The MAP and adjoint at the
+256^3 workloads are compared with stored oracle results in
+``test_gpu_golden.py``.  At 512^3 a full oracle solve takes hours of host
+CPU, so the solves there are checked by properties that hold at any size:
+the oracle's own spectral gradient at the solver's returned spectral
+iterate (``pl_newton_krylov_solve_hat``) below rtol ||g0||, the white-prior
+Lambert-W closed form cell by cell, the sum of expected counts equal to the
+sum of counts at the MAP (the k = 0 component of the gradient), and adjoint
+derivatives against central differences through GPU solves.
 """
 import numpy as np
 import pytest
 
-from conftest import oracle_problem
+from conftest import assert_elementwise, oracle_problem
 from oracle import closed_form
 from oracle import newton as o_newton
 from paper_0911_1407_amd import synth
@@ -58,8 +60,10 @@ def test_operators_full_size_match_oracle(name):
     print(f"{name}: GPU HVP", flush=True)
     out = plan.hessvec_hat(vt).cpu().numpy()
     assert _rel(out, ref) <= 1e-10
+    assert_elementwise(out, ref, 1e-9, what=f"{name} spectral HVP")
     out32 = plan.hessvec_hat(vt.to(torch.complex64)).cpu().numpy()
     assert _rel(out32, ref) <= 5e-5
+    assert_elementwise(out32, ref, 5e-4, what=f"{name} spectral FP32 HVP")
 
 
 def test_map_selection_workload_128_matches_oracle():
@@ -74,6 +78,7 @@ def test_map_selection_workload_128_matches_oracle():
         s, info = plan.solve(rtol=rtol, precision=0 if prec == "fp64" else 1, max_cg=2000)
         assert info["status"] == 0 and info["rel_grad"] <= rtol, info
         assert _rel(s.cpu().numpy(), ref) <= tol, prec
+        assert_elementwise(s.cpu().numpy(), ref, tol, what=f"MAP 128 {prec}")
 
 
 def _ksum_bound(info, inst, got):
@@ -150,17 +155,30 @@ def test_map_512_bias_workload_mixed(big512):
     inst = big512
     plan = Plan(inst["n"], inst["box"], precision="mixed")
     plan.set_instance(inst)
-    plan.autotune()
-    s, info = plan.solve(rtol=1e-6, precision=1)
+    plan.autotune(TUNE_CACHE)
+    s, s_hat, info = plan.solve(want_hat=True, rtol=1e-6, precision=1)
     print("mixed", info, flush=True)
     assert info["status"] == 0 and info["rel_grad"] <= 1e-6, info
+    assert info["fp64_steps"] == 0, info
     got = s.cpu().numpy()
     assert np.all(np.isfinite(got))
     diff, bound = _ksum_bound(info, inst, got)
     assert diff <= bound
-    s64, info64 = plan.solve(rtol=1e-6, precision=0)
+    # the oracle's spectral gradient at the returned iterate (no FFT round
+    # trip of the real field, so no roundoff floor): the MAP to rtol
+    P = oracle_problem(inst)
+    ops = o_newton.SpectralOps(P)
+    g0 = ops.norm(ops.grad(ops.fwd(np.full(P.n, P.mu)))[2])
+    rg = ops.norm(ops.grad(s_hat.cpu().numpy())[2]) / g0
+    print(f"512 mixed: oracle ||g||/||g0|| at the returned iterate {rg:.3e}", flush=True)
+    assert rg <= 1.05e-6
+    del s_hat
+    s64, s64_hat, info64 = plan.solve(want_hat=True, rtol=1e-6, precision=0)
     print("fp64", info64, flush=True)
     assert info64["status"] == 0
+    rg64 = ops.norm(ops.grad(s64_hat.cpu().numpy())[2]) / g0
+    print(f"512 fp64: oracle ||g||/||g0|| at the returned iterate {rg64:.3e}", flush=True)
+    assert rg64 <= 1.05e-6
     assert _rel(got, s64.cpu().numpy()) <= 1e-4
 
 
@@ -179,24 +197,30 @@ def test_adjoint_512_matches_central_fd_beta(big512):
                    nbar=inst["nbar"], beta=inst["beta"])
         prm.update(over)
         plan.set_problem(**prm)
-        s, info = plan.solve(rtol=1e-10, precision=0, max_newton=200, max_cg=5000)
-        print("solve", over, info["newton_its"], info["cg_its"], flush=True)
+        s, info = plan.solve(rtol=1e-12, precision=0, max_newton=200, max_cg=10000)
+        print("solve", over, info["newton_its"], info["cg_its"], info["rel_grad"], flush=True)
         assert info["status"] == 0, info
         return s
 
     s = solve()
     L = lambda x: float(torch.sum((x - st) ** 2))
-    grads, ainfo = plan.adjoint(s, 2.0 * (s - st), want_fields=False, rtol=1e-8, precision=0, max_cg=20000)
+    grads, ainfo = plan.adjoint(s, 2.0 * (s - st), want_fields=False, rtol=1e-10, precision=0, max_cg=40000)
     print("adjoint", ainfo, flush=True)
     assert ainfo["status"] == 0, ainfo
     for key, name in (("beta", "beta"), ("amp", "A")):
         h = 1e-5 * inst[key]
         fd = (L(solve(**{key: inst[key] + h})) - L(solve(**{key: inst[key] - h}))) / (2 * h)
-        print(name, grads[name], fd, flush=True)
-        assert abs(grads[name] - fd) <= 1e-3 * abs(fd), (name, grads[name], fd)
-    # the mixed adjoint agrees with the FP64 one to the mixed tolerance
+        print(f"512 dL/d{name}: adjoint {grads[name]:.10e} central FD {fd:.10e} "
+              f"rel {abs(grads[name] - fd) / abs(fd):.2e}", flush=True)
+        assert abs(grads[name] - fd) <= 1e-4 * abs(fd), (name, grads[name], fd)
+    # the mixed adjoint (FP32 sweeps refined against the FP64 residual)
+    # agrees with the FP64 one to the mixed tolerance 1e-4, at the
+    # benchmark's rtol 1e-6 and tighter
     plan.set_instance(inst)
-    g32, a32 = plan.adjoint(s, 2.0 * (s - st), want_fields=False, rtol=1e-6, precision=1, max_cg=20000)
-    print("adjoint mixed", a32, flush=True)
-    for name in ("A", "beta"):
-        assert abs(g32[name] - grads[name]) <= 1e-3 * abs(grads[name]), name
+    for rt in (1e-6, 1e-8):
+        g32, a32 = plan.adjoint(s, 2.0 * (s - st), want_fields=False, rtol=rt, precision=1, max_cg=20000)
+        print(f"adjoint mixed rtol {rt:g}", a32, {k: abs(g32[k] - grads[k]) / abs(grads[k]) for k in ("A", "beta")},
+              flush=True)
+        assert a32["status"] == 0, a32
+        for name in ("A", "beta"):
+            assert abs(g32[name] - grads[name]) <= 1e-4 * abs(grads[name]), (rt, name)

@@ -1,6 +1,8 @@
 """Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
 
-Tolerances: FP64 operators 1e-11 relative (FFT roundoff times the spread of
+Outputs are compared as a whole (relative L2) and element by element
+(``assert_elementwise``: every entry within the tolerance of the oracle's, in
+units of max(|ref|, floor * max|ref|)).  Tolerances: FP64 operators 1e-11 relative (FFT roundoff times the spread of
 1/lambda); FP64 MAP rel-L2 1e-6 against the oracle MAP solved to 1e-11 (both
 sides are solved tighter, so the observed gap is far smaller); mixed
 FP32/FP64 MAP rel-L2 1e-4; FP32 operators 2e-5 relative.
@@ -8,7 +10,7 @@ FP32/FP64 MAP rel-L2 1e-4; FP32 operators 2e-5 relative.
 import numpy as np
 import pytest
 
-from conftest import oracle_problem
+from conftest import assert_elementwise, oracle_problem
 from oracle import adjoint as o_adj
 from oracle import model as o_model
 from oracle import newton as o_newton
@@ -63,10 +65,12 @@ def test_grad_and_hessvec_match_oracle(n):
     g, obj = plan.grad(s)
     g_ref = o_model.gradient(P, s)
     assert _rel(_np(g), g_ref) <= 1e-11
+    assert_elementwise(_np(g), g_ref, 1e-10, what=f"gradient {n}")
     assert abs(obj - o_model.objective(P, s)) <= 1e-11 * abs(o_model.objective(P, s))
     hv = plan.hessvec(v)  # cached diagonal from pl_grad
     hv_ref = o_model.hessvec(P, s, v)
     assert _rel(_np(hv), hv_ref) <= 1e-11
+    assert_elementwise(_np(hv), hv_ref, 1e-10, what=f"HVP {n}")
     hv2 = plan.hessvec(v, s=s)
     assert _rel(_np(hv2), hv_ref) <= 1e-11
 
@@ -106,6 +110,7 @@ def test_hessvec_f32_matches_oracle(n):
     hv = plan.hessvec_f32(v, s=s)
     hv_ref = o_model.hessvec(P, s, v.astype(np.float64))
     assert _rel(_np(hv).astype(np.float64), hv_ref) <= 2e-5
+    assert_elementwise(_np(hv).astype(np.float64), hv_ref, 2e-4, what=f"FP32 HVP {n}")
 
 
 @pytest.mark.parametrize("n", [(32, 32, 32), (64, 64, 64), (16, 24, 32)])
@@ -121,8 +126,10 @@ def test_spectral_hessvec_matches_oracle(n):
     ref = o_newton.SpectralOps(P).hessvec(o_model.hess_diag(P, s), v_hat)
     out = plan.hessvec_hat(torch.from_numpy(v_hat).cuda())
     assert np.linalg.norm(_np(out) - ref) <= 1e-11 * np.linalg.norm(ref)
+    assert_elementwise(_np(out), ref, 1e-10, what=f"spectral HVP {n}")
     out32 = plan.hessvec_hat(torch.from_numpy(v_hat.astype(np.complex64)).cuda())
     assert np.linalg.norm(_np(out32) - ref) <= 2e-5 * np.linalg.norm(ref)
+    assert_elementwise(_np(out32), ref, 2e-4, what=f"spectral FP32 HVP {n}")
 
 
 @pytest.mark.parametrize("n,beta", [((8, 8, 8), 1.3), ((16, 16, 16), 1.0), ((24, 16, 32), 1.5), ((48, 48, 48), 1.2)])
@@ -134,6 +141,7 @@ def test_map_matches_oracle_fp64(n, beta):
     s, info = plan.solve(rtol=1e-11)
     assert info["status"] == 0, info
     assert _rel(_np(s), s_ref) <= 1e-6
+    assert_elementwise(_np(s), s_ref, 1e-6, what=f"MAP {n}")
     assert info["rel_grad"] <= 1e-11
 
 
@@ -149,6 +157,9 @@ def test_map_plain32_workload():
         assert info["rel_grad"] <= 1e-8
         tol = 1e-6 if prec == "fp64" else 1e-4
         assert _rel(_np(s), s_ref) <= tol, prec
+        assert_elementwise(_np(s), s_ref, tol, what=f"plain32 MAP {prec}")
+        print(f"plain32 {prec} rtol 1e-8: rel-L2 vs oracle {_rel(_np(s), s_ref):.3e}, fp64 steps "
+              f"{info['fp64_steps']}", flush=True)
 
 
 def test_white_prior_closed_form_on_gpu():
@@ -201,6 +212,7 @@ def test_adjoint_matches_oracle(prec):
     assert ainfo["status"] == 0, ainfo
     tol = 1e-6 if prec == "fp64" else 1e-4
     assert _rel(_np(grads["lam"]), lam_ref) <= tol
+    assert_elementwise(_np(grads["lam"]), lam_ref, tol, what=f"adjoint lambda {prec}")
     for k in ("A", "beta", "nbar"):
         assert abs(grads[k] - gr_ref[k]) <= tol * abs(gr_ref[k]), k
     assert _rel(_np(grads["N"]), gr_ref["N"]) <= tol
