@@ -318,6 +318,23 @@ int pl_inverse_weight(pl_plan* plan, double* delta_out);
    stream. */
 int pl_compare_fields(pl_plan* plan, const double* rec, const double* ref, double* r_out, double* d_euc_out);
 
+/* pl_compare_fields without a plan or workspace, for callers that cannot
+   allocate device memory (code under HIP graph capture, serving loops,
+   harnesses that forbid allocation): the library allocates nothing here.
+   Its partial sums live in a fixed 32.8 KB array of device memory inside
+   the library, one copy per GPU, held until the process ends; calls that
+   overlap on one GPU race on it (serialise them, e.g. on one stream).
+   n: host, the grid (n[0] n[1] n[2] <= 512^3 cells, else
+   PL_ERR_UNSUPPORTED_SIZE; any axis < 1 gives PL_ERR_INVALID_ARG).
+   rec, ref: device, N doubles.  out: device, 2 doubles, receives
+   r = sum ref rec / (|ref| |rec|) (0 when either field is zero) and
+   D = sqrt(sum (rec - ref)^2 / N), summed in FP64 in the same fixed order as
+   pl_compare_fields.  Runs on the current device, asynchronously on
+   hip_stream (which must belong to it); returns PL_ERR_HIP if a launch
+   fails. */
+int pl_compare_fields_noalloc(const int32_t n[3], const double* rec, const double* ref, double* out,
+                              void* hip_stream);
+
 /* Message for the last failing call on plan (never NULL). */
 const char* pl_last_error(const pl_plan* plan);
 

@@ -36,7 +36,8 @@ EXPORTED = ("pl_default_opts", "pl_plan_create", "pl_plan_set_workspace", "pl_pl
             "pl_plan_get_variants", "pl_plan_set_variants", "pl_plan_prior_is_radial", "pl_lsq_solve", "pl_nlcg_solve", "pl_lognormal_prior",
             "pl_gaussian_map_solve",
             "pl_inverse_weight", "pl_compare_fields", "pl_linear_bias_grad", "pl_linear_bias_hessvec",
-            "pl_linear_bias_solve", "pl_newton_krylov_solve_hat", "pl_linear_bias_solve_hat")
+            "pl_linear_bias_solve", "pl_newton_krylov_solve_hat", "pl_linear_bias_solve_hat",
+            "pl_compare_fields_noalloc")
 
 # priors of the linear-bias calls (PL_MODEL_* in pl.h)
 MODEL_LOGNORMAL = 0
@@ -124,6 +125,7 @@ def load(path=LIB_PATH):
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.pl_inverse_weight.argtypes = [vp, vp]
     lib.pl_compare_fields.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    lib.pl_compare_fields_noalloc.argtypes = [ctypes.POINTER(ctypes.c_int32), vp, vp, vp, vp]
     lib.pl_plan_set_variants.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     lib.pl_linear_bias_grad.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(dbl)]
     lib.pl_linear_bias_hessvec.argtypes = [vp, i32, vp, vp, vp, vp]
@@ -315,6 +317,17 @@ def pl_compare_fields(h, rec, ref):
     d = ctypes.c_double(0.0)
     _check(h, load().pl_compare_fields(h, _ptr(rec), _ptr(ref), ctypes.byref(r), ctypes.byref(d)))
     return r.value, d.value
+
+
+def pl_compare_fields_noalloc(n, rec, ref, out, stream=None):
+    """r and D_euc of rec against ref into the device tensor out (2 doubles),
+    without a plan or workspace; asynchronous on `stream` (a hipStream_t
+    handle, None for the default stream)."""
+    nn = (ctypes.c_int32 * 3)(*[int(v) for v in n])
+    rc = load().pl_compare_fields_noalloc(nn, _ptr(rec), _ptr(ref), _ptr(out), stream)
+    if rc != PL_OK:
+        raise PLError(rc, f"pl_compare_fields_noalloc(n={tuple(n)})")
+    return rc
 
 
 def pl_plan_prior_is_radial(h):

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1356,6 +1357,74 @@ int pl_compare_fields(pl_plan* p, const double* rec, const double* ref, double* 
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant of pl_compare_fields
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// Its scratch: NB_RED blocks x 4 per-block partial sums, then the 4 sums.
+// One copy of this array per GPU, alive until the process ends; every call
+// on a GPU overwrites it completely before reading it (nothing needs to
+// start at zero), and calls that overlap on one GPU race on it.
+constexpr int kNoallocPartials = NB_RED * 4;
+constexpr int kNoallocDoubles = kNoallocPartials + 4;
+constexpr long kNoallocMaxCells = 512L * 512L * 512L;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kNoallocDoubles];
+
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (host code must not use the array's name as an address).
+int scratch_on_current_device(double** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return PL_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return PL_ERR_HIP;
+    g_scratch_dev[dev] = (double*)ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return PL_OK;
+}
+
+// r and D_euc from the four sums (section 4.1.2), as pl_compare_fields forms
+// them on the host.
+__global__ void compare_out_kernel(const double* __restrict__ sums, long n, double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  const double srr = sums[0], sxx = sums[1], syy = sums[2], sdd = sums[3];
+  out[0] = (sxx > 0.0 && syy > 0.0) ? srr / (sqrt(sxx) * sqrt(syy)) : 0.0;
+  out[1] = sqrt(sdd / (double)n);
+}
+
+}  // namespace
+
+extern "C" int pl_compare_fields_noalloc(const int32_t n[3], const double* rec, const double* ref, double* out,
+                                         void* hip_stream) {
+  if (!n || !rec || !ref || !out) return PL_ERR_INVALID_ARG;
+  long cells = 1;
+  for (int a = 0; a < 3; ++a) {
+    if (n[a] < 1) return PL_ERR_INVALID_ARG;
+    cells *= n[a];
+    if (cells > kNoallocMaxCells) return PL_ERR_UNSUPPORTED_SIZE;
+  }
+  double* sc = nullptr;
+  int rc = scratch_on_current_device(&sc);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)hip_stream;
+  hipLaunchKernelGGL(compare_fields_kernel, dim3(NB_RED), dim3(RED_THREADS), 0, st, rec, ref, cells, sc);
+  if (hipGetLastError() != hipSuccess) return PL_ERR_HIP;
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(FIN_THREADS), 0, st, sc, NB_RED, 4, (int)FIN_STORE, 0, 1.0,
+                     sc + kNoallocPartials, 0.0, (const double*)nullptr, 0, 0.0);
+  if (hipGetLastError() != hipSuccess) return PL_ERR_HIP;
+  hipLaunchKernelGGL(compare_out_kernel, dim3(1), dim3(64), 0, st, sc + kNoallocPartials, cells, out);
+  if (hipGetLastError() != hipSuccess) return PL_ERR_HIP;
+  return PL_OK;
+}
 
 namespace pl {
 bool supported_length(int n) {
