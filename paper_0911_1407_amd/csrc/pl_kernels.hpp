@@ -232,6 +232,12 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
   constexpr int R0 = PL::R0;
   constexpr int RL = LastStage<PL>::R;
   using MAP = LdsMap<B, false>;
+  // The x passes that add (1/lambda) times a second operand load it and the
+  // table before the transform, so that their latency overlaps it, unless
+  // the extra registers would cost occupancy (FP32 at 512 points: 146
+  // instead of about 90 VGPRs, 3 instead of 4 waves per SIMD); FP64 passes
+  // are held to 2 waves per SIMD by their LDS either way.
+  constexpr bool PRELOAD = !(sizeof(T) == 4 && N >= 512);
 
   const bool active = (int)threadIdx.x < ColShape<T, N, V>::THREADS;
   const int cl = threadIdx.x % B;
@@ -313,17 +319,19 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
     // p and 1/lambda at the output positions are loaded before the
     // transform so that their latency overlaps it.
     const int ky = c / a.g.h, kz = c % a.g.h;
-    cx<T> pre_p[W];
-    T pre_il[W];
+    cx<T> pre_p[PRELOAD ? W : 1];
+    T pre_il[PRELOAD ? W : 1];
+    if constexpr (PRELOAD) {
 #pragma unroll
-    for (int q = 0; q < W / RL; ++q)
+      for (int q = 0; q < W / RL; ++q)
 #pragma unroll
-      for (int m = 0; m < RL; ++m) {
-        int kx = out_pos<PL, PL::NS - 1>(t, q, m);
-        long mode = (long)kx * a.g.nyh + c;
-        pre_p[q * RL + m] = valid ? ld_stream(a.base + mode, a.nt & NT_P) : cx<T>{T(0), T(0)};
-        pre_il[q * RL + m] = valid ? inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_TAB) : T(0);
-      }
+        for (int m = 0; m < RL; ++m) {
+          int kx = out_pos<PL, PL::NS - 1>(t, q, m);
+          long mode = (long)kx * a.g.nyh + c;
+          pre_p[q * RL + m] = valid ? ld_stream(a.base + mode, a.nt & NT_P) : cx<T>{T(0), T(0)};
+          pre_il[q * RL + m] = valid ? inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_TAB) : T(0);
+        }
+    }
     fft_thread<PL, false, MAP>(v, t, lds, a.tw, active);
     const double hw = herm_w(kz, a.g);
     const double alpha = a.scal[SC_ALPHA], dbar = a.scal[SC_DBAR];
@@ -336,8 +344,15 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
         long mode = (long)kx * a.g.nyh + c;
         if (valid) {
           // vector arithmetic in the Krylov vectors' precision, sums in FP64
-          cx<T> pv = pre_p[q * RL + m];
-          T il = pre_il[q * RL + m];
+          cx<T> pv;
+          T il;
+          if constexpr (PRELOAD) {
+            pv = pre_p[q * RL + m];
+            il = pre_il[q * RL + m];
+          } else {
+            pv = ld_stream(a.base + mode, a.nt & NT_P);
+            il = inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_TAB);
+          }
           cx<T> x = v[q * RL + m];
           const T qx = x.x + il * pv.x, qy = x.y + il * pv.y, al = (T)alpha;
           cx<T> rv = ld_stream(a.cg_r + mode, a.nt & NT_R), xv = ld_stream(a.cg_x + mode, a.nt & NT_X);
@@ -355,17 +370,19 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
     // forward transform; out = scale * X + (1/lambda) (base - shift at mode 0);
     // base and 1/lambda are loaded before the transform (latency overlap)
     const int ky = c / a.g.h, kz = c % a.g.h;
-    cx<T> pre_b[W];
-    T pre_il[W];
+    cx<T> pre_b[PRELOAD ? W : 1];
+    T pre_il[PRELOAD ? W : 1];
+    if constexpr (PRELOAD) {
 #pragma unroll
-    for (int q = 0; q < W / RL; ++q)
+      for (int q = 0; q < W / RL; ++q)
 #pragma unroll
-      for (int m = 0; m < RL; ++m) {
-        int kx = out_pos<PL, PL::NS - 1>(t, q, m);
-        long mode = (long)kx * a.g.nyh + c;
-        pre_b[q * RL + m] = valid ? ld_stream(a.base + mode, a.nt & NT_P) : cx<T>{T(0), T(0)};
-        pre_il[q * RL + m] = valid ? inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_TAB) : T(0);
-      }
+        for (int m = 0; m < RL; ++m) {
+          int kx = out_pos<PL, PL::NS - 1>(t, q, m);
+          long mode = (long)kx * a.g.nyh + c;
+          pre_b[q * RL + m] = valid ? ld_stream(a.base + mode, a.nt & NT_P) : cx<T>{T(0), T(0)};
+          pre_il[q * RL + m] = valid ? inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_TAB) : T(0);
+        }
+    }
     fft_thread<PL, false, MAP>(v, t, lds, a.tw, active);
     double acc[3] = {0.0, 0.0, 0.0};
     const double hw = herm_w(kz, a.g);
@@ -376,10 +393,17 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
         int kx = out_pos<PL, PL::NS - 1>(t, q, m);
         long mode = (long)kx * a.g.nyh + c;
         if (valid) {
-          cx<T> b = pre_b[q * RL + m];
+          cx<T> b;
+          T il;
+          if constexpr (PRELOAD) {
+            b = pre_b[q * RL + m];
+            il = pre_il[q * RL + m];
+          } else {
+            b = ld_stream(a.base + mode, a.nt & NT_P);
+            il = inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_TAB);
+          }
           cx<T> bs = b;
           if (mode == 0) bs.x -= (T)a.k0_shift;
-          T il = pre_il[q * RL + m];
           cx<T> x = v[q * RL + m];
           cx<T> o = {x.x * a.out_scale + il * bs.x, x.y * a.out_scale + il * bs.y};
           v[q * RL + m] = o;
