@@ -137,6 +137,7 @@ enum Scal {
   SC_INACTIVE = 15,  // batched solves: instance finished, every pass skips it
   SC_LS_B = 16, SC_LS_C = 17, SC_LS_SLOPE = 18,
   SC_DF = 20,     // 4 slots
+  SC_LS_ALPHA = 24,  // step the device-side Armijo test accepted (-1: none)
   SC_ADJ = 26,    // adjoint sums (4 slots)
   SC_LB_DQ = 30,  // linear-bias Krylov step: sum of phi'' B u q^2 (the diagonal part of p^H H p)
   SC_COUNT = 32
@@ -192,6 +193,13 @@ struct ColArgs {
   const double* scal;  // device scalars (SC_*)
   const double* skip;  // if non-null and *skip != 0 the launch does nothing
   int nt;              // NT_* bits: operands loaded / stored non-temporally
+  // First CG iteration (cg_first != 0): COL_CG_FIRST forms the initial
+  // residual r = cg_rhs_sign * cg_rhs itself (stored to cg_r), x = 0 (stored
+  // to cg_x) and p = M^-1 r, with partials (p^H Lambda^-1 p, r^H M^-1 r,
+  // r^H r).
+  int cg_first;
+  const cx<double>* cg_rhs;
+  double cg_rhs_sign;
 };
 
 // Column tile width B: 256 threads per block where possible, at most 64 KB
@@ -255,28 +263,62 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
     const double beta = a.scal[SC_BETA], dbar = a.scal[SC_DBAR];
     const int ky = c / a.g.h, kz = c % a.g.h;
     const double hw = herm_w(kz, a.g);
-    double acc[1] = {0.0};
+    const bool first = a.cg_first != 0;
+    double acc[3] = {0.0, 0.0, 0.0};
     cx<T>* pio = const_cast<cx<T>*>(a.in);
+    if (first) {  // uniform over the launch: one loop or the other
 #pragma unroll
-    for (int q = 0; q < W / R0; ++q)
+      for (int q = 0; q < W / R0; ++q)
 #pragma unroll
-      for (int r = 0; r < R0; ++r) {
-        int kx = in_pos<PL, 0>(t, q, r);
-        long idx = base_off + (long)kx * a.row_stride;
-        cx<T> pn = {T(0), T(0)};
-        if (valid) {
-          cx<T> po = ld_stream(pio + idx, a.nt & NT_P), rv = ld_stream(a.cg_r + idx, a.nt & NT_R);
-          long mode = (long)kx * a.g.nyh + c;
-          const T il = inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_TAB);
-          const T mi = precond_inv<T>(il, dbar), bt = (T)beta;
-          pn = {mi * rv.x + bt * po.x, mi * rv.y + bt * po.y};
-          st_stream(pio + idx, pn, a.nt & NT_P);
-          acc[0] += hw * (double)(il * (pn.x * pn.x + pn.y * pn.y));
+        for (int r = 0; r < R0; ++r) {
+          int kx = in_pos<PL, 0>(t, q, r);
+          long idx = base_off + (long)kx * a.row_stride;
+          cx<T> pn = {T(0), T(0)};
+          if (valid) {
+            // r0 = sign * rhs; p = M^-1 r0 (no previous direction)
+            long mode = (long)kx * a.g.nyh + c;
+            const T il = inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_TAB);
+            const T mi = precond_inv<T>(il, dbar);
+            const cx<double> b = a.cg_rhs[idx];
+            const cx<T> rv = {(T)(a.cg_rhs_sign * b.x), (T)(a.cg_rhs_sign * b.y)};
+            st_stream(a.cg_r + idx, rv, a.nt & NT_R);
+            st_stream(a.cg_x + idx, cx<T>{T(0), T(0)}, a.nt & NT_X);  // x0 = 0
+            pn = {mi * rv.x, mi * rv.y};
+            const double rr = (double)rv.x * rv.x + (double)rv.y * rv.y;
+            acc[1] += hw * (double)mi * rr;
+            acc[2] += hw * rr;
+            st_stream(pio + idx, pn, a.nt & NT_P);
+            acc[0] += hw * (double)(il * (pn.x * pn.x + pn.y * pn.y));
+          }
+          v[q * R0 + r] = pn;
         }
-        v[q * R0 + r] = pn;
-      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < W / R0; ++q)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+          int kx = in_pos<PL, 0>(t, q, r);
+          long idx = base_off + (long)kx * a.row_stride;
+          cx<T> pn = {T(0), T(0)};
+          if (valid) {
+            cx<T> po = ld_stream(pio + idx, a.nt & NT_P), rv = ld_stream(a.cg_r + idx, a.nt & NT_R);
+            long mode = (long)kx * a.g.nyh + c;
+            const T il = inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_TAB);
+            const T mi = precond_inv<T>(il, dbar), bt = (T)beta;
+            pn = {mi * rv.x + bt * po.x, mi * rv.y + bt * po.y};
+            st_stream(pio + idx, pn, a.nt & NT_P);
+            acc[0] += hw * (double)(il * (pn.x * pn.x + pn.y * pn.y));
+          }
+          v[q * R0 + r] = pn;
+        }
+    }
     fft_thread<PL, true, MAP>(v, t, lds, a.tw, active);
-    block_reduce_store<1>(acc, a.partials, block_linear);
+    if (first) {  // uniform over the launch
+      block_reduce_store<3>(acc, a.partials, block_linear);
+    } else {
+      double acc1[1] = {acc[0]};
+      block_reduce_store<1>(acc1, a.partials, block_linear);
+    }
   } else {
 #pragma unroll
   for (int q = 0; q < W / R0; ++q)
@@ -834,7 +876,8 @@ __global__ void __launch_bounds__(RED_THREADS) cg_init_kernel(const cx<double>* 
 }
 
 #ifdef PL_OPS_KERNELS
-enum FinKind { FIN_STORE = 0, FIN_CG_INIT = 1, FIN_CG_ALPHA = 2, FIN_CG_BETA = 3, FIN_DBAR = 4, FIN_CG_ALPHA_ADD = 5 };
+enum FinKind { FIN_STORE = 0, FIN_CG_INIT = 1, FIN_CG_ALPHA = 2, FIN_CG_BETA = 3, FIN_DBAR = 4, FIN_CG_ALPHA_ADD = 5,
+               FIN_CG_ALPHA_FIRST = 6 };
 
 // Sum partials[nb][K] in a fixed order; then scalar bookkeeping.
 // kind FIN_CG_ALPHA: p^H H p = scale2 * sum(partials2[nb2]) (prior part from
@@ -891,10 +934,14 @@ __device__ __forceinline__ void finalize_body(const double* __restrict__ partial
     default: fin_sums<NT, 4>(partials, nb, v); break;
   }
   double extra = 0.0;
+  double e3[3] = {0.0, 0.0, 0.0};
   if (partials2) {
-    double e[1];
-    fin_sums<NT, 1>(partials2, nb2, e);
-    extra = e[0] * scale2;
+    if (kind == FIN_CG_ALPHA_FIRST) {
+      fin_sums<NT, 3>(partials2, nb2, e3);
+    } else {
+      fin_sums<NT, 1>(partials2, nb2, e3);
+    }
+    extra = e3[0] * scale2;
   }
   if (threadIdx.x != 0) return;
   for (int k = 0; k < K; ++k) v[k] *= scale;
@@ -919,6 +966,27 @@ __device__ __forceinline__ void finalize_body(const double* __restrict__ partial
       if (scal[SC_DONE] == 0.0 && pq > 0.0) al = scal[SC_RZ] / pq;
       if (scal[SC_DONE] == 0.0 && !(pq > 0.0)) scal[SC_DONE] = 2.0;  // breakdown
       scal[SC_ALPHA] = al;
+      break;
+    }
+    case FIN_CG_ALPHA_FIRST: {
+      // first iteration, whose first pass also formed r0 = sign * rhs:
+      // partials2 = (p^H Lambda^-1 p, r^H M^-1 r, r^H r) of that pass
+      const double rz = e3[1] * scale2, rr = e3[2] * scale2;
+      scal[SC_RZ] = rz;
+      scal[SC_RR] = rr;
+      scal[SC_ITS] = 0.0;
+      scal[SC_BETA] = 0.0;
+      scal[SC_ALPHA] = 0.0;
+      if (rr <= scal[SC_TOL2]) {
+        scal[SC_DONE] = 1.0;  // converged at the start: x stays 0
+        break;
+      }
+      const double pq = v[0] + extra;
+      scal[SC_PQ] = pq;
+      if (pq > 0.0)
+        scal[SC_ALPHA] = rz / pq;
+      else
+        scal[SC_DONE] = 2.0;  // breakdown
       break;
     }
     case FIN_CG_BETA: {
@@ -1106,6 +1174,18 @@ __global__ void set_scalar_kernel(double* scal, int idx, double value) {
   if (threadIdx.x == 0 && blockIdx.x == 0) scal[idx] = value;
 }
 
+// Start of a CG solve whose first iteration forms the initial residual
+// itself (cg_first): stopping threshold, iteration count and state.
+__global__ void cg_start_kernel(double* scal, double tol2) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    scal[SC_TOL2] = tol2;
+    scal[SC_DONE] = 0.0;
+    scal[SC_ITS] = 0.0;
+    scal[SC_BETA] = 0.0;
+    scal[SC_ALPHA] = 0.0;
+  }
+}
+
 #endif  // PL_OPS_KERNELS
 
 // s_hat += alpha x  (alpha from the host)
@@ -1118,6 +1198,46 @@ __global__ void __launch_bounds__(RED_THREADS) axpy_hat_kernel(cx<double>* __res
     y[i] = {yv.x + alpha * (double)xv.x, yv.y + alpha * (double)xv.y};
   }
 }
+
+// s_hat += alpha x with alpha read from the device (a step the line search
+// accepted on the device); nothing when alpha <= 0 (no step accepted)
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS) axpy_hat_dev_kernel(cx<double>* __restrict__ y,
+                                                                   const cx<T>* __restrict__ x,
+                                                                   const double* __restrict__ alpha_p, long nh) {
+  const double alpha = *alpha_p;
+  if (!(alpha > 0.0)) return;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nh; i += (long)gridDim.x * blockDim.x) {
+    cx<T> xv = x[i];
+    cx<double> yv = y[i];
+    y[i] = {yv.x + alpha * (double)xv.x, yv.y + alpha * (double)xv.y};
+  }
+}
+
+#ifdef PL_OPS_KERNELS
+// Armijo test of the first batch of trial steps a0, a0/2, a0/4, a0/8 on the
+// device: decrease a b + a^2 c / 2 + sum_i [...] (slots SC_LS_B, SC_LS_C,
+// SC_DF + j) against c1 a slope; the first accepted step goes to
+// SC_LS_ALPHA, -1 if none (or if the direction does not descend).  Written
+// with rounded (unfused) operations, the arithmetic the host test uses.
+__global__ void ls_select_kernel(double* scal, double a0, double c1) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double b = scal[SC_LS_B], c = scal[SC_LS_C], slope = scal[SC_LS_SLOPE];
+  double alpha = -1.0;
+  if (slope < 0.0) {
+    double a = a0;
+    for (int j = 0; j < 4; ++j, a *= 0.5) {
+      const double df = __dadd_rn(__dadd_rn(__dmul_rn(a, b), __dmul_rn(__dmul_rn(__dmul_rn(0.5, a), a), c)),
+                                  scal[SC_DF + j]);
+      if (df <= __dmul_rn(__dmul_rn(c1, a), slope)) {
+        alpha = a;
+        break;
+      }
+    }
+  }
+  scal[SC_LS_ALPHA] = alpha;
+}
+#endif
 
 // Line-search dots on half spectra: b = <p, S^-1 (s - mu)>, c = <p, S^-1 p>,
 // slope = <g, p> (times N; the finalize applies 1/N).

@@ -398,21 +398,32 @@ int ensure_d32(pl_plan* p) {
 // at once on the device (the passes read the done flag).
 // *its receives iterations that changed x, *hvps the Hessian products run.
 // ---------------------------------------------------------------------------
+// With tol_rel_of_rhs == 0 (an absolute tolerance known in advance) the
+// first iteration's first pass forms the initial residual itself
+// (COL_CG_FIRST with cg_first), so no separate initialisation pass runs;
+// with a tolerance relative to ||rhs|| an initialisation pass and one
+// read-back of ||rhs|| come first.  first_chunk (> 0) sets how many
+// iterations are queued before the first host check (later checks come
+// every check_every iterations).
 template <typename T>
 int pcg(pl_plan* p, const cx<double>* rhs, double sign, double tol_abs, double tol_rel_of_rhs, int max_cg,
-        int check_every, int* its, int* hvps, double* rel_res, double* rhs_norm) {
+        int check_every, int* its, int* hvps, double* rel_res, double* rhs_norm, int first_chunk = 0) {
   cx<T>*x = View<T>::x(p), *r = View<T>::r(p), *pp = View<T>::pv(p), *t = View<T>::t(p);
   const T* tab = View<T>::tab(p);
   const double invN = 1.0 / (double)p->N;
   double* part_a = p->partials;
   double* part_b = p->partials + p->partials_len;
-  HIPCHK(p, set_scalar(p, SC_TOL2, tol_abs * tol_abs));
-  hipLaunchKernelGGL((cg_init_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, rhs, sign, x, r, pp, tab,
-                     p->radial, p->g, p->Nh, p->scal, p->partials);
-  HIPCHK(p, hipGetLastError());
-  HIPCHK(p, finalize(p, NB_RED, 2, FIN_CG_INIT, 0, invN));
+  const bool fused = !(tol_rel_of_rhs > 0.0);
   double rr0 = 0.0;
-  if (tol_rel_of_rhs > 0.0) {
+  if (fused) {
+    hipLaunchKernelGGL(cg_start_kernel, dim3(1), dim3(64), 0, p->stream, p->scal, tol_abs * tol_abs);
+    HIPCHK(p, hipGetLastError());
+  } else {
+    HIPCHK(p, set_scalar(p, SC_TOL2, tol_abs * tol_abs));
+    hipLaunchKernelGGL((cg_init_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, rhs, sign, x, r, pp, tab,
+                       p->radial, p->g, p->Nh, p->scal, p->partials);
+    HIPCHK(p, hipGetLastError());
+    HIPCHK(p, finalize(p, NB_RED, 2, FIN_CG_INIT, 0, invN));
     int rc = read_scalars(p);
     if (rc) return rc;
     rr0 = p->h_scal[SC_RR];
@@ -422,15 +433,21 @@ int pcg(pl_plan* p, const cx<double>* rhs, double sign, double tol_abs, double t
   }
   int launched = 0;
   while (launched < max_cg) {
-    int chunk = std::min(check_every, max_cg - launched);
+    const int want = (launched == 0 && first_chunk > 0) ? first_chunk : check_every;
+    int chunk = std::min(want, max_cg - launched);
     for (int k = 0; k < chunk; ++k) {
       int nb1 = 0, nb3 = 0, nb5 = 0;
+      const bool first = fused && launched == 0 && k == 0;
       const double* skip = p->scal + SC_DONE;
       ColArgs<T> c1 = col_args<T>(p, 0, pp, t);
       c1.cg_r = r;
       c1.scal = p->scal;
       c1.partials = part_a;
       c1.skip = skip;
+      c1.cg_first = first ? 1 : 0;
+      c1.cg_rhs = rhs;
+      c1.cg_rhs_sign = sign;
+      c1.cg_x = x;
       HIPCHK(p, run_col<T>(p, 0, true, COL_CG_FIRST, c1, &nb1));
       ColArgs<T> c2 = col_args<T>(p, 1, t, t);
       c2.skip = skip;
@@ -441,7 +458,8 @@ int pcg(pl_plan* p, const cx<double>* rhs, double sign, double tol_abs, double t
       ra.partials = part_b;
       ra.skip = skip;
       HIPCHK(p, run_row<T>(p, ROW_HVP, ra, &nb3));
-      HIPCHK(p, finalize(p, nb3, 2, FIN_CG_ALPHA, 0, 1.0, 0.0, part_b, part_a, nb1, invN));
+      HIPCHK(p, finalize(p, nb3, 2, first ? FIN_CG_ALPHA_FIRST : FIN_CG_ALPHA, 0, 1.0, 0.0, part_b, part_a, nb1,
+                         invN));
       ColArgs<T> c4 = col_args<T>(p, 1, t, t);
       c4.skip = skip;
       HIPCHK(p, run_col<T>(p, 1, false, COL_PLAIN, c4, nullptr));
@@ -460,12 +478,12 @@ int pcg(pl_plan* p, const cx<double>* rhs, double sign, double tol_abs, double t
     if (rc) return rc;
     if (p->h_scal[SC_DONE] != 0.0) break;
   }
-  int rc = read_scalars(p);
-  if (rc) return rc;
   *its = (int)p->h_scal[SC_ITS];
   // Hessian products that ran: one per counted iteration, plus the partial
-  // one of a breakdown; queued iterations after convergence exit at once
-  *hvps = *its + (p->h_scal[SC_DONE] == 2.0 ? 1 : 0);
+  // one of a breakdown (or of a fused first iteration whose residual was
+  // already below the tolerance); queued iterations after convergence exit
+  // at once
+  *hvps = *its + ((p->h_scal[SC_DONE] == 2.0 || (fused && *its == 0)) ? 1 : 0);
   if (rel_res) *rel_res = std::sqrt(std::max(0.0, p->h_scal[SC_RR]));
   if (rhs_norm) *rhs_norm = std::sqrt(rr0);
   return PL_OK;
@@ -499,15 +517,14 @@ pl_solve_opts resolve_opts(pl_plan* p, const pl_solve_opts* o) {
   return r;
 }
 
-// One Newton step at the current spectral iterate: inner PCG on
-// H p = -g in T precision, then the Armijo line search along p.  Returns
-// PL_OK with *alpha > 0 on success, *alpha < 0 if no step was found.
 // Armijo backtracking along the spectral direction x from s_hat (section
 // 3.1 gives the step; the globalisation is this build's reading): the
 // decrease f(s + a p) - f(s) = a b + a^2 c / 2 + sum_i [e_i expm1(a beta p_i)
 // - a beta N_i p_i] (b = p^T S^-1 (s - mu), c = p^T S^-1 p, p = F^-1 x) is
 // tested against c1 a p^T g for a = a0, a0/2, a0/4, ... (4 per pass, at
 // most 32).  *alpha = the accepted step or -1; *descent = (p^T g < 0).
+// Host-driven form (the nonlinear-CG solve); the Newton solve queues the
+// same test on the device (newton_step_queue / newton_step_finish).
 template <typename T>
 int line_search(pl_plan* p, cx<T>* x, double a_start, const pl_solve_opts& o, double* alpha, bool* descent) {
   const double invN = 1.0 / (double)p->N;
@@ -557,38 +574,121 @@ int line_search(pl_plan* p, cx<T>* x, double a_start, const pl_solve_opts& o, do
   return PL_OK;
 }
 
+// Trial steps a0, a0/2, a0/4, a0/8 of the line search along the real
+// direction preal from the current linearisation (e), queued with their
+// finalize into SC_DF..SC_DF+3.
 template <typename T>
-int newton_step(pl_plan* p, double eta_gn, const pl_solve_opts& o, pl_solve_info& inf, double* alpha,
-                bool* descent) {
+int ls_eval_queue(pl_plan* p, double a0) {
+  if (p->model == MODEL_GAUSSIAN)
+    hipLaunchKernelGGL((ls_eval_gauss_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream,
+                       View<T>::preal(p), p->e, p->prob.w, p->prob.counts, p->prob.nbar, a0, p->N, p->partials);
+  else
+    hipLaunchKernelGGL((ls_eval_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, View<T>::preal(p), p->e,
+                       p->prob.counts, p->prob.beta, a0, p->N, p->partials);
+  HIPCHK(p, hipGetLastError());
+  HIPCHK(p, finalize(p, NB_RED, 4, FIN_STORE, SC_DF, 1.0));
+  return PL_OK;
+}
+
+// One Newton step at the current spectral iterate, queued on the stream:
+// the inner PCG on H x = -g in T precision (the host checks convergence
+// between chunks of CG steps, the first chunk sized by first_chunk), then
+// the Armijo line search of line_search's first batch (a = 1, 1/2, 1/4,
+// 1/8) with the test itself on the device (ls_select_kernel ->
+// SC_LS_ALPHA), and s_hat += alpha x on the device when a step was
+// accepted.  The gradient that follows and its one read-back tell the host
+// the outcome (newton_step_finish).  *its: CG iterations of the step.
+template <typename T>
+int newton_step_queue(pl_plan* p, double eta_gn, const pl_solve_opts& o, pl_solve_info& inf, int first_chunk,
+                      int* its_out) {
   int rc;
   if constexpr (sizeof(T) == 4) {
     rc = ensure_d32(p);
     if (rc) return rc;
   }
   int its = 0, hv = 0;
-  rc = pcg<T>(p, p->g_hat, -1.0, eta_gn, 0.0, o.max_cg, o.check_every, &its, &hv, nullptr, nullptr);
+  rc = pcg<T>(p, p->g_hat, -1.0, eta_gn, 0.0, o.max_cg, o.check_every, &its, &hv, nullptr, nullptr, first_chunk);
   if (rc) return rc;
   inf.cg_its += its;
   inf.hvps += hv;
-  // line search along the Newton direction x (spectral) / preal (real)
+  *its_out = its;
   cx<T>* x = View<T>::x(p);
-  rc = line_search<T>(p, x, 1.0, o, alpha, descent);
+  const double invN = 1.0 / (double)p->N;
+  rc = inv_c2r<T>(p, x, View<T>::t(p), View<T>::preal(p));
   if (rc) return rc;
+  hipLaunchKernelGGL((ls_dots_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, x, p->s_hat, p->g_hat,
+                     p->radial ? p->tab_rad : p->tab_mode, p->radial, p->g, p->Nh, (double)p->N * prior_mean(p),
+                     p->partials);
+  HIPCHK(p, hipGetLastError());
+  HIPCHK(p, finalize(p, NB_RED, 3, FIN_STORE, SC_LS_B, invN));
+  rc = ls_eval_queue<T>(p, 1.0);
+  if (rc) return rc;
+  hipLaunchKernelGGL(ls_select_kernel, dim3(1), dim3(64), 0, p->stream, p->scal, 1.0, o.ls_c1);
+  HIPCHK(p, hipGetLastError());
+  hipLaunchKernelGGL((axpy_hat_dev_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, p->s_hat, x,
+                     p->scal + SC_LS_ALPHA, p->Nh);
+  HIPCHK(p, hipGetLastError());
+  return PL_OK;
+}
+
+// After a queued Newton step and the gradient that follows it have been
+// read back (h_scal current): the step the device accepted, or, if the
+// first batch of trial steps accepted none along a descent direction, the
+// rest of the backtracking on the host (batches from 1/16, at most 32
+// trial steps in all), the step applied and the gradient recomputed.
+// *alpha = the accepted step or -1; *descent = (p^T g < 0).
+template <typename T>
+int newton_step_finish(pl_plan* p, double* s_io, const pl_solve_opts& o, double* alpha, bool* descent) {
+  *alpha = p->h_scal[SC_LS_ALPHA];
+  const double b = p->h_scal[SC_LS_B], c = p->h_scal[SC_LS_C], slope = p->h_scal[SC_LS_SLOPE];
+  *descent = slope < 0.0;
+  if (*alpha > 0.0 || !*descent) return PL_OK;
+  *alpha = -1.0;
+  double a0 = 1.0 / 16.0;
+  for (int batch = 1; batch < 8 && *alpha < 0.0; ++batch) {
+    // the direction and the linearisation at the (unchanged) iterate are
+    // still in preal and e
+    int rc = ls_eval_queue<T>(p, a0);
+    if (rc) return rc;
+    rc = read_scalars(p);
+    if (rc) return rc;
+    double a = a0;
+    for (int j = 0; j < 4; ++j, a *= 0.5) {
+      double df = a * b + 0.5 * a * a * c + p->h_scal[SC_DF + j];
+      if (df <= o.ls_c1 * a * slope) {
+        *alpha = a;
+        break;
+      }
+    }
+    a0 *= 1.0 / 16.0;
+  }
   if (*alpha > 0.0) {
-    hipLaunchKernelGGL((axpy_hat_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, p->s_hat, x, *alpha,
-                       p->Nh);
+    hipLaunchKernelGGL((axpy_hat_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, p->s_hat, View<T>::x(p),
+                       *alpha, p->Nh);
     HIPCHK(p, hipGetLastError());
+    int rc = grad_hat(p, s_io);
+    if (rc) return rc;
+    rc = read_scalars(p);
+    if (rc) return rc;
   }
   return PL_OK;
 }
 
-// Inexact Newton-Krylov from the current s_io.  In mixed precision (T =
-// float) a step whose FP32 direction fails the line search is redone with an
-// FP64 inner solve (refinement against the FP64 gradient).
+// CG iterations queued before the first host check of a Newton step: most
+// of the previous step's count (the counts grow slowly as the forcing term
+// tightens), at least 4.  Each check costs a host round trip; each
+// iteration queued past convergence costs its launches, which exit at once.
+int first_cg_chunk(int prev_its) { return std::max(4, prev_its - prev_its / 8); }
+
+// Inexact Newton-Krylov from the current s_io.  Each Newton step is queued
+// whole (CG, line search, the accepted update and the next gradient) and
+// read back once, besides the checks between CG chunks.  In mixed
+// precision (T = float) a step whose FP32 direction fails the line search
+// is redone with an FP64 inner solve (refinement against the FP64
+// gradient), and counted in info->fp64_steps.
 template <typename T>
 int newton_solve(pl_plan* p, double* s_io, const pl_solve_opts& o, pl_solve_info* info) {
   pl_solve_info inf{};
-  const double invN = 1.0 / (double)p->N;
   int rc = fwd_r2c<double>(p, s_io, p->s_hat);
   if (rc) return rc;
   rc = grad_hat(p, s_io);
@@ -605,6 +705,7 @@ int newton_solve(pl_plan* p, double* s_io, const pl_solve_opts& o, pl_solve_info
     return fail(p, PL_ERR_DOMAIN, "gradient at the starting point is not finite");
   }
   int status = PL_OK;
+  int prev_its = 0;
   if (g0 > 0.0) {
     for (int it = 0;; ++it) {
       if (gn <= o.rtol * g0) break;
@@ -618,26 +719,38 @@ int newton_solve(pl_plan* p, double* s_io, const pl_solve_opts& o, pl_solve_info
       const double eta = std::min(o.eta_max, std::max(std::sqrt(gn / g0), 0.5 * o.rtol * g0 / gn));
       rc = set_precond_constant(p);
       if (rc) return rc;
+      int its = 0;
+      rc = newton_step_queue<T>(p, eta * gn, o, inf, first_cg_chunk(prev_its), &its);
+      if (rc) return rc;
+      rc = grad_hat(p, s_io);
+      if (rc) return rc;
+      rc = read_scalars(p);
+      if (rc) return rc;
       double alpha = -1.0;
       bool descent = false;
-      rc = newton_step<T>(p, eta * gn, o, inf, &alpha, &descent);
+      rc = newton_step_finish<T>(p, s_io, o, &alpha, &descent);
       if (rc) return rc;
       if constexpr (sizeof(T) == 4) {
         if (alpha < 0.0) {
-          rc = newton_step<double>(p, eta * gn, o, inf, &alpha, &descent);
+          // the iterate, its gradient and Hessian diagonal are unchanged
+          int its64 = 0;
+          rc = newton_step_queue<double>(p, eta * gn, o, inf, first_cg_chunk(prev_its), &its64);
+          if (rc) return rc;
+          rc = grad_hat(p, s_io);
+          if (rc) return rc;
+          rc = read_scalars(p);
+          if (rc) return rc;
+          rc = newton_step_finish<double>(p, s_io, o, &alpha, &descent);
           if (rc) return rc;
           ++inf.fp64_steps;
         }
       }
+      prev_its = its;
       if (alpha < 0.0) {
         status = PL_ERR_LINESEARCH;
         p->err = descent ? "no step satisfies the Armijo condition" : "Newton direction is not a descent direction";
         break;
       }
-      rc = grad_hat(p, s_io);
-      if (rc) return rc;
-      rc = read_scalars(p);
-      if (rc) return rc;
       gn = std::sqrt(std::max(0.0, p->h_scal[SC_GG]));
       obj = 0.5 * p->h_scal[SC_PRIOR] + p->h_scal[SC_LIK];
       inf.newton_its = it + 1;
