@@ -115,10 +115,19 @@ def linear_bias_hvp_bytes(n, lognormal):
     return fwd + hvp + inv
 
 
+def cg_step_bytes(n, p):
+    """Algorithmic bytes of one fused CG step (five passes with the Krylov
+    updates): p N + 32 p Nh."""
+    N = n[0] * n[1] * n[2]
+    Nh = n[0] * n[1] * (n[2] // 2 + 1)
+    return p * N + 32 * p * Nh
+
+
 def batched_workload(dev, rtol):
-    """64 independent reconstructions (n in {32, 48, 64, 96}) solved together
-    in mixed precision, against sequential plain-FP64 single-grid solves of
-    the same instances."""
+    """64 independent reconstructions (n in {32, 48, 64, 96}) solved together,
+    in mixed precision and in plain FP64, against sequential single-grid
+    solves of the same instances in the same two precisions (so that the
+    gain of batching and the gain of precision are reported apart)."""
     import torch
     from paper_0911_1407_amd import synth
     from paper_0911_1407_amd.binding import Batch, Plan, make_opts, pl_newton_krylov_solve
@@ -126,33 +135,53 @@ def batched_workload(dev, rtol):
     insts = synth.batch_instances(count=64)
     print(f"# generated 64 batch instances in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     bt = Batch(insts, precision="mixed", device=dev)
-    bt.solve(rtol=rtol)  # warm-up (also builds the CG graph)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, binfos = bt.solve(rtol=rtol)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
-    nconv = sum(1 for i in binfos if i["status"] == 0)
-    # sequential plain FP64 single-grid solves of the same instances
-    t_seq = 0.0
-    for it in insts:
-        pp = Plan(it["n"], it["box"], precision="fp64", device=dev)
-        pp.set_instance(it)
-        s0 = torch.full(it["n"], float(it["mu"]), dtype=torch.float64, device=dev)
+    bt.autotune(TUNE_CACHE)
+
+    def run_batch(prec):
+        bt.solve(rtol=rtol, precision=prec)  # warm-up (also builds the CG graph)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        pl_newton_krylov_solve(pp.h, s0, make_opts(rtol=rtol))
+        _, infos = bt.solve(rtol=rtol, precision=prec)
         torch.cuda.synchronize()
-        t_seq += time.perf_counter() - t0
-        pp.close()
-    batch = {"instances": len(insts), "converged": nconv, "ms_batched_mixed": 1e3 * t_batch,
-             "instances_per_s_batched": len(insts) / t_batch,
-             "ms_sequential_fp64": 1e3 * t_seq, "instances_per_s_sequential_fp64": len(insts) / t_seq,
-             "speedup": t_seq / t_batch,
-             "cg_its_total": sum(i["cg_its"] for i in binfos)}
-    print(f"# batch: {1e3 * t_batch:.0f} ms batched mixed vs {1e3 * t_seq:.0f} ms sequential fp64 "
-          f"({nconv}/64 converged)", file=sys.stderr, flush=True)
-    return batch
+        return time.perf_counter() - t0, infos
+
+    def run_sequential(prec):
+        t = 0.0
+        infos = []
+        for it in insts:
+            pp = Plan(it["n"], it["box"], precision="mixed", device=dev)
+            pp.set_instance(it)
+            s0 = torch.full(it["n"], float(it["mu"]), dtype=torch.float64, device=dev)
+            pl_newton_krylov_solve(pp.h, s0, make_opts(rtol=rtol, precision=prec))  # warm-up
+            s0.fill_(float(it["mu"]))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            infos.append(pl_newton_krylov_solve(pp.h, s0, make_opts(rtol=rtol, precision=prec)).as_dict())
+            torch.cuda.synchronize()
+            t += time.perf_counter() - t0
+            pp.close()
+        return t, infos
+
+    out = {"instances": len(insts)}
+    for name, prec, p in (("mixed", 1, 4), ("fp64", 0, 8)):
+        tb, binfos = run_batch(prec)
+        ts, sinfos = run_sequential(prec)
+        nconv = sum(1 for i in binfos if i["status"] == 0)
+        # algorithmic bytes of the CG steps each instance took, over the
+        # whole batched solve's wall time: a lower bound on the bandwidth
+        # of the batched passes (gradients, line searches and launch gaps
+        # are in the time, not in the bytes)
+        cg_bytes = sum(i["cg_its"] * cg_step_bytes(it["n"], p) for i, it in zip(binfos, insts))
+        out[name] = {"ms_batched": 1e3 * tb, "ms_sequential": 1e3 * ts, "speedup_batching": ts / tb,
+                     "instances_per_s_batched": len(insts) / tb, "instances_per_s_sequential": len(insts) / ts,
+                     "converged": nconv, "cg_its_total": sum(i["cg_its"] for i in binfos),
+                     "fp64_steps": sum(i["fp64_steps"] for i in binfos),
+                     "cg_algorithmic_bytes": cg_bytes, "cg_bytes_per_s_lower_bound_GBs": cg_bytes / tb / 1e9}
+        print(f"# batch {name}: {1e3 * tb:.0f} ms batched vs {1e3 * ts:.0f} ms sequential "
+              f"({ts / tb:.2f}x, {nconv}/64 converged, CG bytes {cg_bytes / tb / 1e9:.0f} GB/s over the solve)",
+              file=sys.stderr, flush=True)
+    out["speedup_mixed_batched_vs_fp64_sequential"] = out["fp64"]["ms_sequential"] / out["mixed"]["ms_batched"]
+    return out
 
 
 def main():

@@ -399,6 +399,20 @@ int pl_batch_create(pl_batch** out, int n_inst, const int32_t* n, const double* 
 int pl_batch_set_workspace(pl_batch* batch, void* dev_ptr);
 /* Set instance i's posterior (same contract as pl_set_problem). */
 int pl_batch_set_problem(pl_batch* batch, int i, const pl_problem* prob);
+/* Tile schedules of the batched passes, picked per grid length by timing
+   (the batch's counterpart of pl_plan_autotune).  For each distinct length
+   (the lengths holding the most cells first) the column passes and the row
+   pass of the instances of that length each take the default tile
+   (256 threads, <= 64 KB of LDS) or the narrow one (128 threads,
+   <= 32 KB; fewer idle lanes on short columns), whichever makes the
+   batched CG step (seven launches over every instance) fastest; FP64 and,
+   for a PL_MIXED batch, FP32.  Every launch then takes the largest block
+   and LDS of the instances it covers.  Needs every problem set; overwrites
+   the instances' Hessian diagonals and Krylov vectors.  cache_path
+   (nullable): a text file of earlier results keyed by arch, precision and
+   the set of lengths, read and extended as for pl_plan_autotune.  Every
+   choice gives the same result up to rounding.  Synchronises. */
+int pl_batch_autotune(pl_batch* batch, const char* cache_path);
 /* s_inout: host array of n_inst device pointers (start on input, MAP on
    output); infos: host array of n_inst (nullable).  Returns PL_OK if every
    instance converged, else the first failing instance's status; per-instance

@@ -37,7 +37,7 @@ EXPORTED = ("pl_default_opts", "pl_plan_create", "pl_plan_set_workspace", "pl_pl
             "pl_gaussian_map_solve",
             "pl_inverse_weight", "pl_compare_fields", "pl_linear_bias_grad", "pl_linear_bias_hessvec",
             "pl_linear_bias_solve", "pl_newton_krylov_solve_hat", "pl_linear_bias_solve_hat",
-            "pl_compare_fields_noalloc")
+            "pl_compare_fields_noalloc", "pl_batch_autotune")
 
 # priors of the linear-bias calls (PL_MODEL_* in pl.h)
 MODEL_LOGNORMAL = 0
@@ -114,6 +114,7 @@ def load(path=LIB_PATH):
     lib.pl_batch_set_problem.argtypes = [vp, i32, ctypes.POINTER(pl_problem)]
     lib.pl_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(pl_solve_opts),
                                    ctypes.POINTER(pl_solve_info)]
+    lib.pl_batch_autotune.argtypes = [vp, ctypes.c_char_p]
     lib.pl_batch_destroy.argtypes = [vp]
     lib.pl_plan_autotune.argtypes = [vp, ctypes.c_char_p]
     lib.pl_plan_get_variants.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
@@ -397,6 +398,10 @@ def pl_batch_solve(h, s_list, opts=None):
     return [infos[i].as_dict() for i in range(k)]
 
 
+def pl_batch_autotune(h, cache_path=None):
+    return _bcheck(h, load().pl_batch_autotune(h, cache_path.encode() if cache_path else None))
+
+
 def pl_batch_destroy(h):
     return load().pl_batch_destroy(h)
 
@@ -631,6 +636,11 @@ class Batch:
             pl_batch_set_problem(self.h, i, w, c, pk, it["amp"], it["mu"], it["nbar"], it.get("beta", 1.0),
                                  it.get("inv_p0", 0.0))
             self.mus.append(float(it["mu"]))
+
+    def autotune(self, cache_path=None):
+        """Pick the batched passes' tile variants per grid length (by timing,
+        or from cache_path)."""
+        pl_batch_autotune(self.h, cache_path)
 
     def solve(self, s0_list=None, **kw):
         t = self.torch

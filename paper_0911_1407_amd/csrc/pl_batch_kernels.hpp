@@ -9,36 +9,45 @@
 namespace pl {
 
 #define PL_BATCH_LENGTHS(X) X(32) X(48) X(64) X(96) X(128)
-constexpr int BATCH_THREADS = 256;
+constexpr int BATCH_THREADS = 256;  // the largest block of any batched pass
 
 inline bool batch_length_supported(int n) {
   return n == 32 || n == 48 || n == 64 || n == 96 || n == 128;
 }
 
+// Tile shapes of the batched passes per length and tile variant (0 default,
+// 2 narrow): columns per tile, threads, LDS bytes; row pairs per block,
+// threads, LDS bytes.  A batched launch takes the largest block and LDS of
+// the instances it covers.
 template <typename T>
-constexpr int batch_col_lds() {
-  int m = 1;
-#define PL_M(NN) m = ColShape<T, NN>::LDS > m ? ColShape<T, NN>::LDS : m;
-  PL_BATCH_LENGTHS(PL_M)
-#undef PL_M
-  return m;
+struct BatchShape {
+  int B, col_threads, col_lds, G, row_threads, row_lds;
+};
+template <typename T, int N, int V>
+constexpr BatchShape<T> batch_shape_nv() {
+  return {ColShape<T, N, V>::B, ColShape<T, N, V>::THREADS, (int)(ColShape<T, N, V>::LDS * sizeof(cx<T>)),
+          RowShape<N, V>::G, RowShape<N, V>::THREADS,
+          (int)(RowShape<N, V>::G * RowShape<N, V>::LEN * sizeof(cx<T>))};
+}
+template <typename T>
+inline BatchShape<T> batch_shape(int n, int v) {
+  switch (n) {
+#define PL_C(NN) \
+  case NN: return v == 2 ? batch_shape_nv<T, NN, 2>() : batch_shape_nv<T, NN, 0>();
+    PL_BATCH_LENGTHS(PL_C)
+#undef PL_C
+    default: return {0, 0, 0, 0, 0, 0};
+  }
 }
 
-template <typename T>
-constexpr int batch_row_lds() {
-  int m = 1;
-#define PL_M(NN) m = RowShape<NN>::G * RowShape<NN>::LEN > m ? RowShape<NN>::G * RowShape<NN>::LEN : m;
-  PL_BATCH_LENGTHS(PL_M)
-#undef PL_M
-  return m;
-}
-
-// work item: (instance, tile or row-pair block, slab, block index in the instance)
+// work item: (instance, tile or row-pair block, slab, block index in the
+// instance); threads / lds_bytes: the launch's block size and dynamic LDS
 template <typename T>
 hipError_t launch_col_batch(bool inverse, int op, const ColArgs<T>* args, const int4* work, int nblocks,
-                            hipStream_t st);
+                            int threads, int lds_bytes, hipStream_t st);
 template <typename T>
-hipError_t launch_row_batch(int op, const RowArgs<T>* args, const int4* work, int nblocks, hipStream_t st);
+hipError_t launch_row_batch(int op, const RowArgs<T>* args, const int4* work, int nblocks, int threads,
+                            int lds_bytes, hipStream_t st);
 
 // Per-instance operands of the batched elementwise kernels (grid.y = instance)
 template <typename T>

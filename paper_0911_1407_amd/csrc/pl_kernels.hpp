@@ -200,6 +200,7 @@ struct ColArgs {
   int cg_first;
   const cx<double>* cg_rhs;
   double cg_rhs_sign;
+  int variant;  // batched launches: this instance's tile variant (0 or 2)
 };
 
 // Column tile width B: 256 threads per block where possible, at most 64 KB
@@ -216,10 +217,14 @@ constexpr int col_tile(int P, int N, int elem_bytes, int threads, int lds_cap) {
   return b;
 }
 
+// V = 2 ("narrow", batched launches only): 128 threads and at most 32 KB,
+// for the small grids of a batch, whose short columns leave most lanes of a
+// default tile idle (a y pass of a 32^3 grid has 17 columns).
 template <typename T, int N, int V = 0>
 struct ColShape {
   static constexpr int P = Plan<N>::P;
-  static constexpr int B = col_tile(P, N, (int)sizeof(cx<T>), V ? 512 : 256, V ? 131072 : 65536);
+  static constexpr int B = col_tile(P, N, (int)sizeof(cx<T>), V == 1 ? 512 : (V == 2 ? 128 : 256),
+                                    V == 1 ? 131072 : (V == 2 ? 32768 : 65536));
   static constexpr int THREADS = B * P;
   static constexpr int LDS = P > 1 ? N * B : 1;  // complex elements
 };
@@ -535,12 +540,13 @@ struct RowArgs {
   int model;           // ROW_GRAD likelihood: MODEL_LOGNORMAL or MODEL_GAUSSIAN
   const double* lb_d1;  // ROW_LB_OUT: the curvature diagonal and the kept field q
   const double* lb_q;
+  int variant;  // batched launches: this instance's tile variant (0 or 2)
 };
 
 template <int N, int V = 0>
 struct RowShape {
   static constexpr int P = Plan<N>::P;
-  static constexpr int TH = V ? 512 : 256;
+  static constexpr int TH = V == 1 ? 512 : (V == 2 ? 128 : 256);
   static constexpr int G = (TH / P) > 32 ? 32 : (TH / P < 1 ? 1 : TH / P);  // row pairs per block
   static constexpr int THREADS = G * P;
   static constexpr int LEN = PaddedLen<N + 2, true>::value;  // LDS slots per pair

@@ -1798,68 +1798,70 @@ namespace {
 
 constexpr int NBB = 64;  // blocks per instance of the batched elementwise kernels
 
-template <typename T>
-int col_B(int n) {
-  switch (n) {
-#define PL_C(NN) \
-  case NN: return ColShape<T, NN>::B;
-    PL_BATCH_LENGTHS(PL_C)
-#undef PL_C
-    default: return 0;
-  }
-}
-
-int row_G(int n) {
-  switch (n) {
-#define PL_C(NN) \
-  case NN: return RowShape<NN>::G;
-    PL_BATCH_LENGTHS(PL_C)
-#undef PL_C
-    default: return 0;
-  }
-}
-
 int xcd_remap(int hw, int total) {
   const int xcd = hw & 7, k = hw >> 3, per = total >> 3, rem = total & 7;
   return xcd * per + (xcd < rem ? xcd : rem) + k;
 }
 
-// Work list of a column pass over all instances (axis 0: x, 1: y); blocks
-// ordered so that each XCD receives a contiguous range of work items.
+// Work list of one batched pass with its launch configuration: blocks
+// ordered so that each XCD receives a contiguous range of work items, the
+// block size and dynamic LDS the largest of the instances' tile shapes.
+struct BWork {
+  std::vector<int4> items;
+  std::vector<int> nb;  // blocks per instance (= partial-sum records)
+  int threads = 0, lds = 0;
+  size_t off = 0, cap = 0;  // region in the blob and its capacity (items)
+};
+enum BWorkId { W_X64 = 0, W_Y64, W_R64, W_X32, W_Y32, W_R32, W_COUNT };
+
+void order_for_xcds(std::vector<int4>& nat) {
+  std::vector<int4> w(nat.size());
+  for (int hw = 0; hw < (int)nat.size(); ++hw) w[hw] = nat[xcd_remap(hw, (int)nat.size())];
+  nat.swap(w);
+}
+
+// Column pass over all instances (axis 0: x, 1: y), instance i in tile
+// variant var[i].
 template <typename T>
-std::vector<int4> col_work(const std::vector<pl_plan*>& plans, int axis, std::vector<int>& nb) {
-  std::vector<int4> nat;
-  nb.assign(plans.size(), 0);
+void col_work(const std::vector<pl_plan*>& plans, int axis, const std::vector<int>& var, BWork& w) {
+  w.items.clear();
+  w.nb.assign(plans.size(), 0);
+  w.threads = 0;
+  w.lds = 0;
   for (size_t i = 0; i < plans.size(); ++i) {
     const pl_plan* p = plans[i];
+    const BatchShape<T> sh = batch_shape<T>(p->n[axis], var[i]);
     const int h = p->g.h;
     const int ncols = axis == 0 ? p->n[1] * h : h;
     const int nslabs = axis == 0 ? 1 : p->n[0];
-    const int B = col_B<T>(p->n[axis]);
-    const int nbx = (ncols + B - 1) / B;
+    const int nbx = (ncols + sh.B - 1) / sh.B;
     for (int sl = 0; sl < nslabs; ++sl)
-      for (int t = 0; t < nbx; ++t) nat.push_back(make_int4((int)i, t, sl, t + nbx * sl));
-    nb[i] = nbx * nslabs;
+      for (int t = 0; t < nbx; ++t) w.items.push_back(make_int4((int)i, t, sl, t + nbx * sl));
+    w.nb[i] = nbx * nslabs;
+    w.threads = std::max(w.threads, sh.col_threads);
+    w.lds = std::max(w.lds, sh.col_lds);
   }
-  std::vector<int4> w(nat.size());
-  for (int hw = 0; hw < (int)nat.size(); ++hw) w[hw] = nat[xcd_remap(hw, (int)nat.size())];
-  return w;
+  order_for_xcds(w.items);
 }
 
-std::vector<int4> row_work(const std::vector<pl_plan*>& plans, std::vector<int>& nb) {
-  std::vector<int4> nat;
-  nb.assign(plans.size(), 0);
+// Row (z) pass over all instances, instance i in tile variant var[i].
+template <typename T>
+void row_work(const std::vector<pl_plan*>& plans, const std::vector<int>& var, BWork& w) {
+  w.items.clear();
+  w.nb.assign(plans.size(), 0);
+  w.threads = 0;
+  w.lds = 0;
   for (size_t i = 0; i < plans.size(); ++i) {
     const pl_plan* p = plans[i];
+    const BatchShape<T> sh = batch_shape<T>(p->n[2], var[i]);
     const int nunits = p->n[0] * p->n[1] / 2;
-    const int G = row_G(p->n[2]);
-    const int nbu = (nunits + G - 1) / G;
-    for (int b = 0; b < nbu; ++b) nat.push_back(make_int4((int)i, b, 0, b));
-    nb[i] = nbu;
+    const int nbu = (nunits + sh.G - 1) / sh.G;
+    for (int b = 0; b < nbu; ++b) w.items.push_back(make_int4((int)i, b, 0, b));
+    w.nb[i] = nbu;
+    w.threads = std::max(w.threads, sh.row_threads);
+    w.lds = std::max(w.lds, sh.row_lds);
   }
-  std::vector<int4> w(nat.size());
-  for (int hw = 0; hw < (int)nat.size(); ++hw) w[hw] = nat[xcd_remap(hw, (int)nat.size())];
-  return w;
+  order_for_xcds(w.items);
 }
 
 // Column / row pass kinds of a batched solve
@@ -1880,13 +1882,14 @@ struct pl_batch {
   std::vector<size_t> plan_off;
   size_t ws_bytes = 0, plans_bytes = 0, blob_bytes = 0;
   char* ws = nullptr;
-  // work lists
-  std::vector<int4> w_x64, w_y64, w_x32, w_y32, w_row;
-  std::vector<int> nb_x64, nb_y64, nb_x32, nb_y32, nb_row;
+  // work lists of the passes (BWorkId) and the tile variant of every
+  // instance's column and row passes per precision ([0] FP64, [1] FP32),
+  // chosen per grid length (pl_batch_autotune)
+  BWork work[W_COUNT];
+  std::vector<int> vcol[2], vrow[2];
   // device blob and its host mirror
   char* d_blob = nullptr;
   char* h_blob = nullptr;
-  size_t off_w[5] = {0, 0, 0, 0, 0};
   size_t off_c64 = 0, off_ct64 = 0, off_ct32 = 0, off_r64 = 0, off_rt64 = 0, off_rt32 = 0, off_fin = 0,
          off_e64 = 0, off_e32 = 0, off_ctl = 0, off_scal = 0;
   double* scal_all = nullptr;
@@ -1923,8 +1926,7 @@ size_t batch_layout(pl_batch* b) {
     off += align_up(bytes);
     return r;
   };
-  const std::vector<int4>* wl[5] = {&b->w_x64, &b->w_y64, &b->w_x32, &b->w_y32, &b->w_row};
-  for (int i = 0; i < 5; ++i) b->off_w[i] = take(sizeof(int4) * std::max<size_t>(1, wl[i]->size()));
+  for (int i = 0; i < W_COUNT; ++i) b->work[i].off = take(sizeof(int4) * std::max<size_t>(1, b->work[i].cap));
   const size_t K = b->K;
   b->off_c64 = take(sizeof(ColArgs<double>) * K * BC_COUNT64);
   b->off_ct64 = take(sizeof(ColArgs<double>) * K * BT_COUNT);
@@ -1961,7 +1963,41 @@ template <typename T>
 BatchElem<T>* elems(pl_batch* b, bool host) {
   return blob_ptr<BatchElem<T>>(b, sizeof(T) == 8 ? b->off_e64 : b->off_e32, host);
 }
-const int4* work_dev(pl_batch* b, int which) { return blob_ptr<int4>(b, b->off_w[which], false); }
+const int4* work_dev(pl_batch* b, int which) { return blob_ptr<int4>(b, b->work[which].off, false); }
+
+// Work lists and launch shapes for the current tile variants, copied into
+// the host blob (uploaded with the pass arguments before each solve).
+void build_work(pl_batch* b) {
+  col_work<double>(b->plans, 0, b->vcol[0], b->work[W_X64]);
+  col_work<double>(b->plans, 1, b->vcol[0], b->work[W_Y64]);
+  row_work<double>(b->plans, b->vrow[0], b->work[W_R64]);
+  col_work<float>(b->plans, 0, b->vcol[1], b->work[W_X32]);
+  col_work<float>(b->plans, 1, b->vcol[1], b->work[W_Y32]);
+  row_work<float>(b->plans, b->vrow[1], b->work[W_R32]);
+  if (b->h_blob)
+    for (int i = 0; i < W_COUNT; ++i)
+      if (!b->work[i].items.empty())
+        std::memcpy(b->h_blob + b->work[i].off, b->work[i].items.data(), sizeof(int4) * b->work[i].items.size());
+}
+
+template <typename T>
+int wid_x() { return sizeof(T) == 8 ? W_X64 : W_X32; }
+template <typename T>
+int wid_y() { return sizeof(T) == 8 ? W_Y64 : W_Y32; }
+template <typename T>
+int wid_r() { return sizeof(T) == 8 ? W_R64 : W_R32; }
+
+// One batched column / row pass over work list `wid`.
+template <typename T>
+hipError_t bcol(pl_batch* b, bool inverse, int op, const ColArgs<T>* args, int wid) {
+  const BWork& w = b->work[wid];
+  return launch_col_batch<T>(inverse, op, args, work_dev(b, wid), (int)w.items.size(), w.threads, w.lds, b->stream);
+}
+template <typename T>
+hipError_t brow(pl_batch* b, int op, const RowArgs<T>* args, int wid) {
+  const BWork& w = b->work[wid];
+  return launch_row_batch<T>(op, args, work_dev(b, wid), (int)w.items.size(), w.threads, w.lds, b->stream);
+}
 
 // Fill the per-instance pass arguments (depends on the caller's s pointers).
 template <typename T>
@@ -1971,44 +2007,56 @@ void fill_args(pl_batch* b, double* const* s_io) {
     const double* inactive = p->scal + SC_INACTIVE;
     const double* done = p->scal + SC_DONE;
     // FP64 gradient and transforms of s
+    const int v64 = b->vcol[0][i], r64 = b->vrow[0][i];
+    const int vT = b->vcol[sizeof(T) == 4 ? 1 : 0][i], rT = b->vrow[sizeof(T) == 4 ? 1 : 0][i];
     ColArgs<double>* c;
     c = &cargs64(b, BC_SHAT_Y, true)[i]; *c = col_args<double>(p, 1, p->s_hat, p->s_hat); c->skip = inactive;
+    c->variant = v64;
     c = &cargs64(b, BC_SHAT_X, true)[i]; *c = col_args<double>(p, 0, p->s_hat, p->s_hat); c->skip = inactive;
+    c->variant = v64;
     c = &cargs64(b, BC_G_XINV, true)[i]; *c = col_args<double>(p, 0, p->s_hat, p->t64); c->skip = inactive;
+    c->variant = v64;
     c = &cargs64(b, BC_G_YINV, true)[i]; *c = col_args<double>(p, 1, p->t64, p->t64); c->skip = inactive;
+    c->variant = v64;
     c = &cargs64(b, BC_G_YFWD, true)[i]; *c = col_args<double>(p, 1, p->t64, p->t64); c->skip = inactive;
+    c->variant = v64;
     c = &cargs64(b, BC_G_XADD, true)[i]; *c = col_args<double>(p, 0, p->t64, p->g_hat); c->skip = inactive;
+    c->variant = v64;
     c->base = p->s_hat;
     c->k0_shift = (double)p->N * p->prob.mu;
     RowArgs<double>* r;
     r = &rargs64(b, BR_R2C, true)[i]; *r = row_args<double>(p); r->in_r = s_io[i]; r->out_c = p->s_hat; r->skip = inactive;
+    r->variant = r64;
     r = &rargs64(b, BR_GRAD, true)[i]; *r = row_args<double>(p); r->in_c = p->t64; r->out_c = p->t64;
     r->s_out = s_io[i]; r->e_out = p->e; r->d_out = p->d; r->skip = inactive;
+    r->variant = r64;
     // Krylov passes in T
     cx<T>*x = View<T>::x(p), *rr = View<T>::r(p), *pp = View<T>::pv(p), *t = View<T>::t(p);
     double* part_a = p->partials;
     double* part_b = p->partials + p->partials_len;
     ColArgs<T>* ct;
     ct = &cargs_t<T>(b, BT_CG1, true)[i]; *ct = col_args<T>(p, 0, pp, t);
-    ct->cg_r = rr; ct->scal = p->scal; ct->partials = part_a; ct->skip = done;
-    ct = &cargs_t<T>(b, BT_CGYI, true)[i]; *ct = col_args<T>(p, 1, t, t); ct->skip = done;
-    ct = &cargs_t<T>(b, BT_CGYF, true)[i]; *ct = col_args<T>(p, 1, t, t); ct->skip = done;
+    ct->cg_r = rr; ct->scal = p->scal; ct->partials = part_a; ct->skip = done; ct->variant = vT;
+    ct = &cargs_t<T>(b, BT_CGYI, true)[i]; *ct = col_args<T>(p, 1, t, t); ct->skip = done; ct->variant = vT;
+    ct = &cargs_t<T>(b, BT_CGYF, true)[i]; *ct = col_args<T>(p, 1, t, t); ct->skip = done; ct->variant = vT;
     ct = &cargs_t<T>(b, BT_CG5, true)[i]; *ct = col_args<T>(p, 0, t, t);
     ct->base = pp; ct->cg_r = rr; ct->cg_x = x; ct->scal = p->scal; ct->partials = part_a; ct->skip = done;
-    ct = &cargs_t<T>(b, BT_XCINV, true)[i]; *ct = col_args<T>(p, 0, x, t); ct->skip = inactive;
-    ct = &cargs_t<T>(b, BT_YCINV, true)[i]; *ct = col_args<T>(p, 1, t, t); ct->skip = inactive;
+    ct->variant = vT;
+    ct = &cargs_t<T>(b, BT_XCINV, true)[i]; *ct = col_args<T>(p, 0, x, t); ct->skip = inactive; ct->variant = vT;
+    ct = &cargs_t<T>(b, BT_YCINV, true)[i]; *ct = col_args<T>(p, 1, t, t); ct->skip = inactive; ct->variant = vT;
     RowArgs<T>* rt;
     rt = &rargs_t<T>(b, BRT_HVP, true)[i]; *rt = row_args<T>(p); rt->in_c = t; rt->out_c = t;
-    rt->partials = part_b; rt->skip = done;
+    rt->partials = part_b; rt->skip = done; rt->variant = rT;
     rt = &rargs_t<T>(b, BRT_C2R, true)[i]; *rt = row_args<T>(p); rt->in_c = t; rt->out_r = View<T>::preal(p);
-    rt->skip = inactive;
+    rt->skip = inactive; rt->variant = rT;
     // finalize records
-    const std::vector<int>& nbx = sizeof(T) == 8 ? b->nb_x64 : b->nb_x32;
+    const std::vector<int>& nbx = b->work[wid_x<T>()].nb;
+    const std::vector<int>& nbr = b->work[wid_r<T>()].nb;
     const double invN = 1.0 / (double)p->N;
-    fins(b, BF_GRAD_ROW, true)[i] = BatchFin{part_a, b->nb_row[i], nullptr, 0, p->scal, invN};
-    fins(b, BF_GRAD_X, true)[i] = BatchFin{part_a, b->nb_x64[i], nullptr, 0, p->scal, invN};
+    fins(b, BF_GRAD_ROW, true)[i] = BatchFin{part_a, b->work[W_R64].nb[i], nullptr, 0, p->scal, invN};
+    fins(b, BF_GRAD_X, true)[i] = BatchFin{part_a, b->work[W_X64].nb[i], nullptr, 0, p->scal, invN};
     fins(b, BF_INIT, true)[i] = BatchFin{part_a, NBB, nullptr, 0, p->scal, invN};
-    fins(b, BF_ALPHA, true)[i] = BatchFin{part_b, b->nb_row[i], part_a, nbx[i], p->scal, invN};
+    fins(b, BF_ALPHA, true)[i] = BatchFin{part_b, nbr[i], part_a, nbx[i], p->scal, invN};
     fins(b, BF_BETA, true)[i] = BatchFin{part_a, nbx[i], nullptr, 0, p->scal, invN};
     fins(b, BF_LS, true)[i] = BatchFin{part_a, NBB, nullptr, 0, p->scal, invN};
   }
@@ -2051,32 +2099,28 @@ int belem_upload(pl_batch* b) {
 }
 
 int bgrad(pl_batch* b) {
-  const int nx = (int)b->w_x64.size(), ny = (int)b->w_y64.size(), nr = (int)b->w_row.size();
-  BHIP(b, launch_col_batch<double>(true, COL_PLAIN, cargs64(b, BC_G_XINV, false), work_dev(b, 0), nx, b->stream));
-  BHIP(b, launch_col_batch<double>(true, COL_PLAIN, cargs64(b, BC_G_YINV, false), work_dev(b, 1), ny, b->stream));
-  BHIP(b, launch_row_batch<double>(ROW_GRAD, rargs64(b, BR_GRAD, false), work_dev(b, 4), nr, b->stream));
+  BHIP(b, bcol<double>(b, true, COL_PLAIN, cargs64(b, BC_G_XINV, false), W_X64));
+  BHIP(b, bcol<double>(b, true, COL_PLAIN, cargs64(b, BC_G_YINV, false), W_Y64));
+  BHIP(b, brow<double>(b, ROW_GRAD, rargs64(b, BR_GRAD, false), W_R64));
   int rc = bfin(b, BF_GRAD_ROW, 2, FIN_STORE, SC_LIK, 1.0, 0);
   if (rc) return rc;
-  BHIP(b, launch_col_batch<double>(false, COL_PLAIN, cargs64(b, BC_G_YFWD, false), work_dev(b, 1), ny, b->stream));
-  BHIP(b, launch_col_batch<double>(false, COL_ADDPRIOR, cargs64(b, BC_G_XADD, false), work_dev(b, 0), nx, b->stream));
+  BHIP(b, bcol<double>(b, false, COL_PLAIN, cargs64(b, BC_G_YFWD, false), W_Y64));
+  BHIP(b, bcol<double>(b, false, COL_ADDPRIOR, cargs64(b, BC_G_XADD, false), W_X64));
   return bfin(b, BF_GRAD_X, 3, FIN_STORE, SC_GG - 1, 0.0, 1);
 }
 
 // Enqueue `chunk` fused CG steps for all instances (captured in a graph)
 template <typename T>
 int bcg_chunk(pl_batch* b, int chunk, int max_cg) {
-  const int wx = sizeof(T) == 8 ? 0 : 2, wy = sizeof(T) == 8 ? 1 : 3;
-  const int nx = (int)(sizeof(T) == 8 ? b->w_x64.size() : b->w_x32.size());
-  const int ny = (int)(sizeof(T) == 8 ? b->w_y64.size() : b->w_y32.size());
-  const int nr = (int)b->w_row.size();
+  const int wx = wid_x<T>(), wy = wid_y<T>(), wr = wid_r<T>();
   for (int k = 0; k < chunk; ++k) {
-    BHIP(b, launch_col_batch<T>(true, COL_CG_FIRST, cargs_t<T>(b, BT_CG1, false), work_dev(b, wx), nx, b->stream));
-    BHIP(b, launch_col_batch<T>(true, COL_PLAIN, cargs_t<T>(b, BT_CGYI, false), work_dev(b, wy), ny, b->stream));
-    BHIP(b, launch_row_batch<T>(ROW_HVP, rargs_t<T>(b, BRT_HVP, false), work_dev(b, 4), nr, b->stream));
+    BHIP(b, bcol<T>(b, true, COL_CG_FIRST, cargs_t<T>(b, BT_CG1, false), wx));
+    BHIP(b, bcol<T>(b, true, COL_PLAIN, cargs_t<T>(b, BT_CGYI, false), wy));
+    BHIP(b, brow<T>(b, ROW_HVP, rargs_t<T>(b, BRT_HVP, false), wr));
     int rc = bfin(b, BF_ALPHA, 2, FIN_CG_ALPHA, 0, 1.0, 0, 0.0, 0.0, 1);
     if (rc) return rc;
-    BHIP(b, launch_col_batch<T>(false, COL_PLAIN, cargs_t<T>(b, BT_CGYF, false), work_dev(b, wy), ny, b->stream));
-    BHIP(b, launch_col_batch<T>(false, COL_CG_LAST, cargs_t<T>(b, BT_CG5, false), work_dev(b, wx), nx, b->stream));
+    BHIP(b, bcol<T>(b, false, COL_PLAIN, cargs_t<T>(b, BT_CGYF, false), wy));
+    BHIP(b, bcol<T>(b, false, COL_CG_LAST, cargs_t<T>(b, BT_CG5, false), wx));
     rc = bfin(b, BF_BETA, 2, FIN_CG_BETA, 0, 0.0, 1, (double)max_cg);
     if (rc) return rc;
   }
@@ -2100,12 +2144,9 @@ int batch_newton(pl_batch* b, double* const* s_io, const pl_solve_opts& o, pl_so
   int rc = bctl(b);
   if (rc) return rc;
   // s_hat = F s0, then the gradient
-  BHIP(b, launch_row_batch<double>(ROW_R2C, rargs64(b, BR_R2C, false), work_dev(b, 4), (int)b->w_row.size(),
-                                   b->stream));
-  BHIP(b, launch_col_batch<double>(false, COL_PLAIN, cargs64(b, BC_SHAT_Y, false), work_dev(b, 1),
-                                   (int)b->w_y64.size(), b->stream));
-  BHIP(b, launch_col_batch<double>(false, COL_PLAIN, cargs64(b, BC_SHAT_X, false), work_dev(b, 0),
-                                   (int)b->w_x64.size(), b->stream));
+  BHIP(b, brow<double>(b, ROW_R2C, rargs64(b, BR_R2C, false), W_R64));
+  BHIP(b, bcol<double>(b, false, COL_PLAIN, cargs64(b, BC_SHAT_Y, false), W_Y64));
+  BHIP(b, bcol<double>(b, false, COL_PLAIN, cargs64(b, BC_SHAT_X, false), W_X64));
   rc = bgrad(b);
   if (rc) return rc;
   rc = bread(b);
@@ -2230,13 +2271,9 @@ int batch_newton(pl_batch* b, double* const* s_io, const pl_solve_opts& o, pl_so
         inf[i].hvps += its + (hs(b, i, SC_DONE) == 2.0 ? 1 : 0);
       }
     // line search: real-space direction, spectral dots
-    const int wx = sizeof(T) == 8 ? 0 : 2, wy = sizeof(T) == 8 ? 1 : 3;
-    BHIP(b, launch_col_batch<T>(true, COL_PLAIN, cargs_t<T>(b, BT_XCINV, false), work_dev(b, wx),
-                                (int)(sizeof(T) == 8 ? b->w_x64.size() : b->w_x32.size()), b->stream));
-    BHIP(b, launch_col_batch<T>(true, COL_PLAIN, cargs_t<T>(b, BT_YCINV, false), work_dev(b, wy),
-                                (int)(sizeof(T) == 8 ? b->w_y64.size() : b->w_y32.size()), b->stream));
-    BHIP(b, launch_row_batch<T>(ROW_C2R, rargs_t<T>(b, BRT_C2R, false), work_dev(b, 4), (int)b->w_row.size(),
-                                b->stream));
+    BHIP(b, bcol<T>(b, true, COL_PLAIN, cargs_t<T>(b, BT_XCINV, false), wid_x<T>()));
+    BHIP(b, bcol<T>(b, true, COL_PLAIN, cargs_t<T>(b, BT_YCINV, false), wid_y<T>()));
+    BHIP(b, brow<T>(b, ROW_C2R, rargs_t<T>(b, BRT_C2R, false), wid_r<T>()));
     hipLaunchKernelGGL((ls_dots_batch_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream, elems<T>(b, false));
     BHIP(b, hipGetLastError());
     rc = bfin(b, BF_LS, 3, FIN_STORE, SC_LS_B, 0.0, 1);
@@ -2345,6 +2382,146 @@ int batch_newton(pl_batch* b, double* const* s_io, const pl_solve_opts& o, pl_so
   return first_bad;
 }
 
+// Time one batched CG step (the seven launches of bcg_chunk over every
+// instance) with the current tile variants, average of `reps`; on hashed
+// Krylov vectors and Hessian diagonals, so nothing is left in a meaningful
+// state.
+template <typename T>
+int time_batch_cg(pl_batch* b, int reps, float* ms) {
+  build_work(b);
+  std::vector<double*> dummy(b->K);
+  for (int i = 0; i < b->K; ++i) dummy[i] = b->plans[i]->s_ws;
+  fill_args<T>(b, dummy.data());
+  BHIP(b, hipMemcpyAsync(b->d_blob, b->h_blob, b->off_e64, hipMemcpyHostToDevice, b->stream));
+  for (int i = 0; i < b->K; ++i) {
+    pl_plan* p = b->plans[i];
+    int rc = fill_hash<T>(p, (T*)View<T>::x(p), 2 * p->Nh, 1);
+    if (!rc) rc = fill_hash<T>(p, (T*)View<T>::r(p), 2 * p->Nh, 2);
+    if (!rc) rc = fill_hash<T>(p, (T*)View<T>::pv(p), 2 * p->Nh, 3);
+    if (rc) return bfail(b, rc, pl_last_error(p));
+  }
+  BHIP(b, hipMemsetAsync(b->scal_all, 0, sizeof(double) * SC_COUNT * b->K, b->stream));
+  const int big = 1 << 30;
+  int rc = bcg_chunk<T>(b, 2, big);
+  if (rc) return rc;
+  hipEvent_t e0, e1;
+  BHIP(b, hipEventCreate(&e0));
+  BHIP(b, hipEventCreate(&e1));
+  (void)hipEventRecord(e0, b->stream);
+  rc = bcg_chunk<T>(b, reps, big);
+  (void)hipEventRecord(e1, b->stream);
+  (void)hipEventSynchronize(e1);
+  (void)hipEventElapsedTime(ms, e0, e1);
+  *ms /= (float)reps;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
+// Distinct grid lengths of a batch (each instance's three axes must be
+// equal to share a column/row variant per length), the ones holding the
+// most cells first.
+std::vector<int> batch_lengths(const pl_batch* b) {
+  std::vector<std::pair<long, int>> tot;
+  for (const pl_plan* p : b->plans)
+    for (int a = 0; a < 3; ++a) {
+      const int n = p->n[a];
+      auto it = std::find_if(tot.begin(), tot.end(), [n](const std::pair<long, int>& q) { return q.second == n; });
+      if (it == tot.end())
+        tot.push_back({p->N, n});
+      else
+        it->first += p->N;
+    }
+  std::sort(tot.begin(), tot.end(), [](const std::pair<long, int>& a, const std::pair<long, int>& c) {
+    return a.first != c.first ? a.first > c.first : a.second < c.second;
+  });
+  std::vector<int> out;
+  for (auto& q : tot) out.push_back(q.second);
+  return out;
+}
+
+// Per length L: the tile variant of the column passes and of the row pass
+// of every instance whose axes have length L (an instance with uneven axes
+// takes the variant of its x length).
+void set_length_variant(pl_batch* b, int ti, int L, int vc, int vr) {
+  for (int i = 0; i < b->K; ++i)
+    if (b->plans[i]->n[0] == L) {
+      b->vcol[ti][i] = vc;
+      b->vrow[ti][i] = vr;
+    }
+}
+
+template <typename T>
+int tune_batch_precision(pl_batch* b, const std::string& key, const std::vector<int>& lens,
+                         std::vector<std::string>& lines, bool* added) {
+  const int ti = sizeof(T) == 4 ? 1 : 0;
+  const size_t nl = lens.size();
+  for (const std::string& line : lines) {
+    if (line.compare(0, key.size() + 1, key + " ") != 0) continue;
+    // "<key> c0,c1,... r0,r1,... ms"
+    std::vector<int> vc, vr;
+    const char* q = line.c_str() + key.size();
+    for (int part = 0; part < 2; ++part) {
+      std::vector<int>& dst = part == 0 ? vc : vr;
+      while (*q == ' ') ++q;
+      while (*q && *q != ' ') {
+        char* end = nullptr;
+        long v = std::strtol(q, &end, 10);
+        if (end == q) break;
+        dst.push_back((int)v);
+        q = end;
+        if (*q == ',') ++q;
+      }
+    }
+    if (vc.size() != nl || vr.size() != nl) continue;
+    bool ok = true;
+    for (size_t j = 0; j < nl; ++j) ok = ok && (vc[j] == 0 || vc[j] == 2) && (vr[j] == 0 || vr[j] == 2);
+    if (!ok) continue;
+    for (size_t j = 0; j < nl; ++j) set_length_variant(b, ti, lens[j], vc[j], vr[j]);
+    return PL_OK;
+  }
+  // a positive Hessian diagonal for the timing runs
+  for (pl_plan* p : b->plans) {
+    int rc = fill_hash<double>(p, p->d, p->N, 5, 0.0, 1.0);
+    if (!rc && sizeof(T) == 4) rc = fill_hash<float>(p, p->d32, p->N, 5, 0.0, 1.0);
+    if (rc) return bfail(b, rc, pl_last_error(p));
+    p->d_valid = false;
+    p->d32_valid = false;
+  }
+  const int reps = 10;
+  float best = 0.f;
+  for (size_t j = 0; j < nl; ++j) set_length_variant(b, ti, lens[j], 0, 0);
+  int rc = time_batch_cg<T>(b, reps, &best);
+  if (rc) return rc;
+  std::vector<int> kc(nl, 0), kr(nl, 0);
+  // one length at a time, the lengths holding the most cells first
+  for (size_t j = 0; j < nl; ++j) {
+    for (int c = 0; c < 4; ++c) {
+      const int vc = (c & 1) ? 2 : 0, vr = (c & 2) ? 2 : 0;
+      if (vc == kc[j] && vr == kr[j]) continue;
+      set_length_variant(b, ti, lens[j], vc, vr);
+      float ms = 0.f;
+      rc = time_batch_cg<T>(b, reps, &ms);
+      if (rc) return rc;
+      if (ms < best) {
+        best = ms;
+        kc[j] = vc;
+        kr[j] = vr;
+      }
+    }
+    set_length_variant(b, ti, lens[j], kc[j], kr[j]);
+  }
+  std::string line = key + " ";
+  for (size_t j = 0; j < nl; ++j) line += (j ? "," : "") + std::to_string(kc[j]);
+  line += " ";
+  for (size_t j = 0; j < nl; ++j) line += (j ? "," : "") + std::to_string(kr[j]);
+  char buf[32];
+  std::snprintf(buf, sizeof(buf), " %.4f", (double)best);
+  lines.push_back(line + buf);
+  *added = true;
+  return PL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2379,11 +2556,19 @@ int pl_batch_create(pl_batch** out, int n_inst, const int32_t* n, const double* 
     off += align_up(ws);
   }
   b->plans_bytes = off;
-  b->w_x64 = col_work<double>(b->plans, 0, b->nb_x64);
-  b->w_y64 = col_work<double>(b->plans, 1, b->nb_y64);
-  b->w_x32 = col_work<float>(b->plans, 0, b->nb_x32);
-  b->w_y32 = col_work<float>(b->plans, 1, b->nb_y32);
-  b->w_row = row_work(b->plans, b->nb_row);
+  // work-list capacities: every instance in the narrow variant (the most
+  // blocks per pass); then the default variants
+  for (int t = 0; t < 2; ++t) {
+    b->vcol[t].assign(n_inst, 2);
+    b->vrow[t].assign(n_inst, 2);
+  }
+  build_work(b);
+  for (int i = 0; i < W_COUNT; ++i) b->work[i].cap = b->work[i].items.size();
+  for (int t = 0; t < 2; ++t) {
+    b->vcol[t].assign(n_inst, 0);
+    b->vrow[t].assign(n_inst, 0);
+  }
+  build_work(b);
   b->blob_bytes = batch_layout(b);
   b->ws_bytes = b->plans_bytes + b->blob_bytes;
   if (hipHostMalloc((void**)&b->h_blob, b->blob_bytes, hipHostMallocDefault) != hipSuccess) {
@@ -2391,12 +2576,7 @@ int pl_batch_create(pl_batch** out, int n_inst, const int32_t* n, const double* 
     return PL_ERR_HIP;
   }
   std::memset(b->h_blob, 0, b->blob_bytes);
-  {
-    // the host blob mirrors the device blob, work lists included
-    const std::vector<int4>* wl[5] = {&b->w_x64, &b->w_y64, &b->w_x32, &b->w_y32, &b->w_row};
-    for (int i = 0; i < 5; ++i)
-      if (!wl[i]->empty()) std::memcpy(b->h_blob + b->off_w[i], wl[i]->data(), sizeof(int4) * wl[i]->size());
-  }
+  build_work(b);  // the host blob mirrors the device blob, work lists included
   b->h_scal = blob_ptr<double>(b, b->off_scal, true);
   *workspace_bytes = b->ws_bytes;
   *out = b;
@@ -2443,6 +2623,52 @@ int pl_batch_set_problem(pl_batch* b, int i, const pl_problem* prob) {
   if (rc) return rc;
   rc = pl_set_problem(b->plans[i], prob);
   if (rc) return bfail(b, rc, "instance " + std::to_string(i) + ": " + pl_last_error(b->plans[i]));
+  return PL_OK;
+}
+
+int pl_batch_autotune(pl_batch* b, const char* cache_path) {
+  if (!b) return PL_ERR_INVALID_ARG;
+  if (!b->ws) return bfail(b, PL_ERR_INVALID_ARG, "workspace not set");
+  for (int i = 0; i < b->K; ++i)
+    if (!b->plans[i]->has_problem)
+      return bfail(b, PL_ERR_NO_PROBLEM, "instance " + std::to_string(i) + " has no problem");
+  std::vector<std::string> lines;
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "r")) {
+      char buf[512];
+      while (std::fgets(buf, sizeof(buf), f)) {
+        std::string l(buf);
+        while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+        if (!l.empty() && l[0] != '#') lines.push_back(l);
+      }
+      std::fclose(f);
+    }
+  }
+  int rc = join_user_stream(b);
+  if (rc) return rc;
+  const std::vector<int> lens = batch_lengths(b);
+  std::string base = arch_name() + " batch";
+  std::string ls;
+  for (size_t j = 0; j < lens.size(); ++j) ls += (j ? "," : "") + std::to_string(lens[j]);
+  bool added = false;
+  rc = tune_batch_precision<double>(b, base + " fp64 " + ls, lens, lines, &added);
+  if (!rc && b->precision == PL_MIXED) rc = tune_batch_precision<float>(b, base + " fp32 " + ls, lens, lines, &added);
+  build_work(b);
+  for (int t = 0; t < 2; ++t)
+    if (b->graph[t]) {
+      (void)hipGraphExecDestroy(b->graph[t]);
+      b->graph[t] = nullptr;
+    }
+  (void)hipStreamSynchronize(b->stream);
+  if (rc) return rc;
+  if (cache_path && added) {
+    if (FILE* f = std::fopen(cache_path, "w")) {
+      std::fprintf(f, "# pl_batch_autotune cache: arch batch precision lengths (most cells first) "
+                      "column-variants row-variants ms/CG-step\n");
+      for (const std::string& l : lines) std::fprintf(f, "%s\n", l.c_str());
+      std::fclose(f);
+    }
+  }
   return PL_OK;
 }
 

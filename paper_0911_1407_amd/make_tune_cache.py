@@ -1,6 +1,8 @@
 """Write the tile-variant cache that bench.py and users load with
-Plan.autotune(path): one line per (arch, grid, precision) holding the variant
-of each FFT pass and the timings that chose it.
+Plan.autotune(path) / Batch.autotune(path): one line per (arch, grid,
+precision) holding the variant of each FFT pass and the timings that chose
+it, and one per (arch, precision, set of lengths) of the batched workload
+holding the column and row tile variant per length.
 
     python -m paper_0911_1407_amd.make_tune_cache [path]
 
@@ -27,6 +29,10 @@ def main(argv):
         plan.set_instance(inst)
         print(name, inst["n"], plan.autotune(path), flush=True)
         plan.close()
+    # the batched workload's tile variants per grid length
+    batch = binding.Batch(synth.batch_instances(count=64), precision="mixed")
+    batch.autotune(path)
+    batch.close()
     print(open(path).read(), end="")
 
 
