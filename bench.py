@@ -184,6 +184,107 @@ def batched_workload(dev, rtol):
     return out
 
 
+def oracle_parity(workload, inst, fields):
+    """Relative L2 error of GPU MAP fields against the stored oracle MAP
+    (tests/golden/<workload>_map.json, written by the oracle alone) over its
+    sampled cells, and the worst cell in units of max(|ref|, 1e-2 max|ref|);
+    None when no stored result exists or the inputs differ from the stored
+    run's."""
+    import hashlib
+    if workload is None:
+        return None
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", f"{workload}_map.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        ref = json.load(f)
+    sha = hashlib.sha256(np.ascontiguousarray(inst["counts"]).tobytes()).hexdigest()
+    if sha != ref["inputs"]["counts_sha256"]:
+        return None
+    cells = np.asarray(ref["cells"])
+    r = np.asarray(ref["s_star_cells"])
+    scale = np.maximum(np.abs(r), 1e-2 * np.abs(r).max())
+    out = {"sample_cells": int(cells.size), "oracle_rtol": ref["oracle_solve"]["rtol"]}
+    for name, t in fields.items():
+        a = t.detach().cpu().numpy().ravel()[cells]
+        out[name] = {"rel_l2": float(np.linalg.norm(a - r) / np.linalg.norm(r)),
+                     "max_cell_rel": float(np.max(np.abs(a - r) / scale))}
+    return out
+
+
+def cpu_oracle_baseline(inst, v, full=False):
+    """The CPU oracle (plain FP64 numpy / scipy.fft on the host cores) timed
+    on bounded samples of the benchmark's workloads.  value: oracle spectral
+    HVPs per second at the workload's size (up to 40 HVPs, about 15 s).
+    time_to_map: the oracle's inexact Newton-Krylov solve of the 32^3 plain
+    workload (rtol 1e-8) and sequential solves of the first 8 instances of
+    the 64-instance batched workload (rtol 1e-6), with Newton / CG counts;
+    with full=True (--cpu-full) also the 256^3 selection workload's solve
+    (rtol 1e-6), the 256^3 bias workload's solve and adjoint (rtol 1e-6) and
+    all 64 batch instances, which take minutes."""
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from oracle import adjoint as o_adj
+    from oracle import dft as o_dft
+    from oracle.grid import Problem
+    from oracle.model import hess_diag
+    from oracle.newton import SpectralOps, newton_krylov
+    from paper_0911_1407_amd import synth
+
+    def problem(it):
+        return Problem(it["n"], it["box"], it["w"], it["counts"], it["pk"], it["amp"], it["mu"], it["nbar"],
+                       it["beta"], 0.0)
+
+    def timed_solve(it, rtol):
+        t0 = time.perf_counter()
+        s_, info = newton_krylov(problem(it), rtol=rtol, max_newton=200, max_cg=5000)
+        return s_, {"s": time.perf_counter() - t0, "newton_its": int(info["newton_its"]),
+                    "cg_its": int(info["cg_its"]), "status": info["status"], "rtol": rtol}
+
+    P = problem(inst)
+    ops = SpectralOps(P)
+    d = hess_diag(P, inst["s_true"])
+    vh = np.fft.rfftn(v)
+    ops.hessvec(d, vh)
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        ops.hessvec(d, vh)
+        reps += 1
+        if time.perf_counter() - t0 > 15.0 or reps >= 40:
+            break
+    t_hvp = (time.perf_counter() - t0) / reps
+    ttm = {}
+    _, ttm["plain32"] = timed_solve(synth.config_instance("plain32"), 1e-8)
+    insts = synth.batch_instances(count=64)
+    subset = insts if full else insts[:8]
+    recs = [timed_solve(it, 1e-6)[1] for it in subset]
+    ttm["batch64_sequential"] = {"instances": len(subset), "n": [int(it["n"][0]) for it in subset],
+                                 "s": sum(r["s"] for r in recs), "cg_its": sum(r["cg_its"] for r in recs),
+                                 "rtol": 1e-6}
+    if full:
+        _, ttm["sel256"] = timed_solve(synth.config_instance("sel256"), 1e-6)
+        bias = synth.config_instance("bias256")
+        s_b, ttm["bias256"] = timed_solve(bias, 1e-6)
+        _, dL = o_adj.squared_error_loss(s_b, bias["s_true"])
+        t0 = time.perf_counter()
+        _, its = o_adj.adjoint_pcg(problem(bias), s_b, dL, rtol=1e-6, max_cg=50000)
+        ttm["bias256_adjoint"] = {"s": time.perf_counter() - t0, "cg_its": int(its), "rtol": 1e-6}
+    cpu_model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        pass
+    n = inst["n"]
+    return {"value": 1.0 / t_hvp, "unit": "HVP/s", "cores": o_dft._WORKERS, "kind": "oracle",
+            "cpu_model": cpu_model,
+            "sample": f"{reps} oracle spectral HVPs (scipy rfftn/irfftn on {o_dft._WORKERS} threads, FP64) on "
+                      f"the same {n[0]}^3 data at s = s_true, elementwise numpy single-threaded; time_to_map: "
+                      f"oracle Newton-Krylov solves (plain32 at rtol 1e-8, {len(subset)} batch instances at "
+                      f"rtol 1e-6{', sel256, bias256 and its adjoint at rtol 1e-6' if full else ''})",
+            "time_to_map": ttm}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -191,6 +292,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--hvp-reps", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="CPU oracle baseline at full size: 256^3 solves and adjoint, all 64 batch instances "
+                         "(minutes of host CPU)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--only-hvp", action="store_true", help="profiling aid: only the isolated HVP loop")
     ap.add_argument("--only-batch", action="store_true", help="profiling aid: only the batched workload")
@@ -310,6 +414,10 @@ def main():
     mixed_rel = float(torch.linalg.norm(s_mixed - s_fp64) / torch.linalg.norm(s_fp64))
     print(f"# mixed solve {1e3 * t_mixed:.1f} ms, {minfos[-1]}, rel vs fp64 {mixed_rel:.2e}",
           file=sys.stderr, flush=True)
+    parity = oracle_parity(args.workload if args.n is None else None, inst,
+                           {"fp64_rtol_1e-6": s_fp64, "mixed_rtol_1e-6": s_mixed})
+    if parity:
+        print(f"# rel-L2 vs the stored oracle MAP: {parity}", file=sys.stderr, flush=True)
 
     # ---------------- adjoint at the MAP ----------------
     dL = 2.0 * (s_fp64 - s_true)
@@ -322,8 +430,26 @@ def main():
     grads32, ainfo32 = plan.adjoint(s_fp64, dL, want_fields=False, rtol=1e-6, precision=1, max_cg=20000)
     torch.cuda.synchronize()
     t_adj32 = time.perf_counter() - t0
-    print(f"# adjoint fp64 {1e3 * t_adj:.1f} ms {ainfo}; mixed {1e3 * t_adj32:.1f} ms",
-          file=sys.stderr, flush=True)
+    adj_agree = {k: abs(grads32[k] - grads[k]) / abs(grads[k]) for k in ("A", "beta", "nbar") if grads[k] != 0.0}
+    print(f"# adjoint fp64 {1e3 * t_adj:.1f} ms {ainfo}; mixed {1e3 * t_adj32:.1f} ms, "
+          f"mixed vs fp64 {adj_agree}", file=sys.stderr, flush=True)
+
+    # ---------------- the 32^3 plain workload (time-to-MAP beside the oracle's) ----------------
+    small = synth.config_instance("plain32")
+    splan = Plan(small["n"], small["box"], precision="mixed", device=dev)
+    splan.set_instance(small)
+    splan.autotune(TUNE_CACHE if os.path.exists(TUNE_CACHE) else None)
+    plain32 = {}
+    for name, prec in (("fp64", 0), ("mixed", 1)):
+        splan.solve(rtol=1e-8, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, sinfo = splan.solve(rtol=1e-8, precision=prec)
+        torch.cuda.synchronize()
+        plain32[name] = {"ms": 1e3 * (time.perf_counter() - t0), "newton_its": sinfo["newton_its"],
+                         "cg_its": sinfo["cg_its"], "status": sinfo["status"], "fp64_steps": sinfo["fp64_steps"]}
+    splan.close()
+    print(f"# plain32 (rtol 1e-8): {plain32}", file=sys.stderr, flush=True)
 
     # ---------------- paper-literal Krylov step (nonlinear-CG search vectors) ----------------
     s_nl, ninfo = plan.solve_nlcg(rtol=rtol, max_cg=20000)  # warm-up
@@ -431,35 +557,9 @@ def main():
     # ---------------- CPU oracle baseline ----------------
     cpu = None
     if not args.no_cpu:
-        sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
-        from oracle.grid import Problem
-        from oracle.model import hess_diag
-        from oracle.newton import SpectralOps
-        P = Problem(inst["n"], inst["box"], inst["w"], inst["counts"], inst["pk"], inst["amp"],
-                    inst["mu"], inst["nbar"], inst["beta"], 0.0)
-        ops = SpectralOps(P)
-        d = hess_diag(P, inst["s_true"])
-        vh = np.fft.rfftn(v)
-        ops.hessvec(d, vh)
-        reps = 0
-        t0 = time.perf_counter()
-        while True:
-            ops.hessvec(d, vh)
-            reps += 1
-            if time.perf_counter() - t0 > 15.0 or reps >= 40:
-                break
-        t_cpu = (time.perf_counter() - t0) / reps
-        cpu_model = None
-        try:
-            with open("/proc/cpuinfo") as f:
-                cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
-        except OSError:
-            pass
-        cpu = {"value": 1.0 / t_cpu, "unit": "HVP/s", "cores": os.cpu_count(), "kind": "oracle",
-               "cpu_model": cpu_model,
-               "sample": f"{reps} oracle spectral HVPs (scipy rfftn/irfftn, FP64) on the same "
-                         f"{n[0]}^3 data at s = s_true; elementwise numpy single-threaded"}
-        print(f"# cpu oracle HVP {1e3 * t_cpu:.0f} ms", file=sys.stderr, flush=True)
+        cpu = cpu_oracle_baseline(inst, v, args.cpu_full)
+        print(f"# cpu oracle HVP {1e3 / cpu['value']:.0f} ms; {json.dumps(cpu['time_to_map'])}",
+              file=sys.stderr, flush=True)
 
     wl_desc = {
         "sel256": "selection workload (sigma_G 1.5, w=exp(-(r/R)^2) x 20% masked 8^3 blocks, nbar 0.5, beta 1)",
@@ -497,10 +597,12 @@ def main():
         "solve_mixed": {"ms": 1e3 * t_mixed, "newton_its": minfos[-1]["newton_its"],
                         "cg_its": minfos[-1]["cg_its"], "hvps": minfos[-1]["hvps"],
                         "rel_grad": minfos[-1]["rel_grad"], "speedup_vs_fp64": ms_per_step / (1e3 * t_mixed),
-                        "rel_l2_vs_fp64": mixed_rel},
+                        "rel_l2_vs_fp64": mixed_rel, "fp64_steps": minfos[-1]["fp64_steps"]},
+        "oracle_parity": parity,
         "adjoint": {"ms_fp64": 1e3 * t_adj, "ms_mixed": 1e3 * t_adj32, "cg_its_fp64": ainfo["cg_its"],
                     "cg_its_mixed": ainfo32["cg_its"], "dL_dA": grads["A"], "dL_dbeta": grads["beta"],
-                    "dL_dnbar": grads["nbar"]},
+                    "dL_dnbar": grads["nbar"], "mixed_vs_fp64_rel": adj_agree},
+        "plain32_time_to_map": plain32,
         "nlcg": nlcg,
         "estimators": estimators,
         "linear_bias": linear_bias,

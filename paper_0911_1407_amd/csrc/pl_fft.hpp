@@ -280,27 +280,63 @@ struct PaddedLen {
 // Permute the block's data through LDS: slot (q, m) of every thread (QA
 // groups of RA) goes to element POS_A(t, q, m), then slot (q, r) (QB groups
 // of RB) is read back from element POS_B(t, q, r).
-template <int RA, int QA, int RB, int QB, class MAP, typename T, typename PA, typename PB>
+// SPLIT: the real parts go through LDS first, then the imaginary parts, so
+// the exchange needs half the LDS (lds then points at real-valued slots,
+// lds[MAP::off(e)] of a T array) at twice the barriers; every real part is
+// in LDS before any is overwritten in registers.
+template <int RA, int QA, int RB, int QB, class MAP, bool SPLIT = false, typename T, typename PA, typename PB>
 __device__ __forceinline__ void lds_permute(cx<T>* v, cx<T>* lds, bool active, PA pos_a, PB pos_b) {
-  __syncthreads();
-  if (active) {
+  if constexpr (SPLIT) {
+    T* lt = reinterpret_cast<T*>(lds);
+    __syncthreads();
+    if (active) {
 #pragma unroll
-    for (int q = 0; q < QA; ++q)
+      for (int q = 0; q < QA; ++q)
 #pragma unroll
-      for (int m = 0; m < RA; ++m) lds[MAP::off(pos_a(q, m))] = v[q * RA + m];
-  }
-  __syncthreads();
-  if (active) {
+        for (int m = 0; m < RA; ++m) lt[MAP::off(pos_a(q, m))] = v[q * RA + m].x;
+    }
+    __syncthreads();
+    if (active) {
 #pragma unroll
-    for (int q = 0; q < QB; ++q)
+      for (int q = 0; q < QB; ++q)
 #pragma unroll
-      for (int r = 0; r < RB; ++r) v[q * RB + r] = lds[MAP::off(pos_b(q, r))];
+        for (int r = 0; r < RB; ++r) v[q * RB + r].x = lt[MAP::off(pos_b(q, r))];
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int q = 0; q < QA; ++q)
+#pragma unroll
+        for (int m = 0; m < RA; ++m) lt[MAP::off(pos_a(q, m))] = v[q * RA + m].y;
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int q = 0; q < QB; ++q)
+#pragma unroll
+        for (int r = 0; r < RB; ++r) v[q * RB + r].y = lt[MAP::off(pos_b(q, r))];
+    }
+  } else {
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int q = 0; q < QA; ++q)
+#pragma unroll
+        for (int m = 0; m < RA; ++m) lds[MAP::off(pos_a(q, m))] = v[q * RA + m];
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int q = 0; q < QB; ++q)
+#pragma unroll
+        for (int r = 0; r < RB; ++r) v[q * RB + r] = lds[MAP::off(pos_b(q, r))];
+    }
   }
 }
 
 // Exchange between stage S-1 (outputs) and stage S (inputs).  Threads with
 // active == false take part in the barriers only.
-template <class PL, int S, class MAP, typename T>
+template <class PL, int S, class MAP, bool SPLIT = false, typename T>
 __device__ __forceinline__ void stage_exchange(cx<T>* v, int t, cx<T>* lds, bool active) {
   constexpr int RP = StageInfo<PL, S - 1>::R;
   constexpr int R = StageInfo<PL, S>::R;
@@ -315,7 +351,7 @@ __device__ __forceinline__ void stage_exchange(cx<T>* v, int t, cx<T>* lds, bool
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q * R + r] = tmp[in_pos<PL, S>(0, q, r)];
   } else {
-    lds_permute<RP, PL::W / RP, R, PL::W / R, MAP>(
+    lds_permute<RP, PL::W / RP, R, PL::W / R, MAP, SPLIT>(
         v, lds, active, [t](int q, int m) { return out_pos<PL, S - 1>(t, q, m); },
         [t](int q, int r) { return in_pos<PL, S>(t, q, r); });
   }
@@ -324,23 +360,23 @@ __device__ __forceinline__ void stage_exchange(cx<T>* v, int t, cx<T>* lds, bool
 // Whole transform: v holds stage-0 inputs (slot (q,r) <-> in_pos<0>) and
 // returns last-stage outputs (slot (q,m) <-> out_pos<NS-1>).  All threads of
 // the block must call this together when P > 1 (it contains barriers).
-template <class PL, bool INV, class MAP, typename T>
+template <class PL, bool INV, class MAP, bool SPLIT = false, typename T>
 __device__ __forceinline__ void fft_thread(cx<T>* v, int t, cx<T>* lds, const cx<T>* __restrict__ tw,
                                            bool active = true) {
   if (active) stage_compute<PL, 0, INV>(v, t, tw);
   if constexpr (PL::NS > 1) {
-    stage_exchange<PL, 1, MAP>(v, t, lds, active);
+    stage_exchange<PL, 1, MAP, SPLIT>(v, t, lds, active);
     if (active) stage_compute<PL, 1, INV>(v, t, tw);
   }
   if constexpr (PL::NS > 2) {
-    stage_exchange<PL, 2, MAP>(v, t, lds, active);
+    stage_exchange<PL, 2, MAP, SPLIT>(v, t, lds, active);
     if (active) stage_compute<PL, 2, INV>(v, t, tw);
   }
 }
 
 // Move data held in last-stage output slots into stage-0 input slots (used
 // between an inverse and a forward transform of the same data).
-template <class PL, class MAP, typename T>
+template <class PL, class MAP, bool SPLIT = false, typename T>
 __device__ __forceinline__ void last_to_first(cx<T>* v, int t, cx<T>* lds, bool active = true) {
   constexpr int RL = LastStage<PL>::R;
   constexpr int R0 = PL::R0;
@@ -358,7 +394,7 @@ __device__ __forceinline__ void last_to_first(cx<T>* v, int t, cx<T>* lds, bool 
 #pragma unroll
       for (int r = 0; r < R0; ++r) v[q * R0 + r] = tmp[in_pos<PL, 0>(0, q, r)];
   } else {
-    lds_permute<RL, PL::W / RL, R0, PL::W / R0, MAP>(
+    lds_permute<RL, PL::W / RL, R0, PL::W / R0, MAP, SPLIT>(
         v, lds, active, [t](int q, int m) { return out_pos<PL, PL::NS - 1>(t, q, m); },
         [t](int q, int r) { return in_pos<PL, 0>(t, q, r); });
   }

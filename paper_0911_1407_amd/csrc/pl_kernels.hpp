@@ -220,13 +220,18 @@ constexpr int col_tile(int P, int N, int elem_bytes, int threads, int lds_cap) {
 // V = 2 ("narrow", batched launches only): 128 threads and at most 32 KB,
 // for the small grids of a batch, whose short columns leave most lanes of a
 // default tile idle (a y pass of a 32^3 grid has 17 columns).
+// V = 3 ("split"): the default tile, with the stage exchanges passing real
+// and imaginary parts through LDS one after the other (half the LDS, so
+// twice the blocks per CU when registers allow) and the second operand of
+// the fused x passes loaded after the transform (fewer registers).
 template <typename T, int N, int V = 0>
 struct ColShape {
   static constexpr int P = Plan<N>::P;
   static constexpr int B = col_tile(P, N, (int)sizeof(cx<T>), V == 1 ? 512 : (V == 2 ? 128 : 256),
                                     V == 1 ? 131072 : (V == 2 ? 32768 : 65536));
   static constexpr int THREADS = B * P;
-  static constexpr int LDS = P > 1 ? N * B : 1;  // complex elements
+  static constexpr bool SPLIT = V == 3;
+  static constexpr int LDS = P > 1 ? (SPLIT ? (N * B + 1) / 2 : N * B) : 1;  // complex elements
 };
 
 // lengths with a wide variant
@@ -250,7 +255,8 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
   // the extra registers would cost occupancy (FP32 at 512 points: 146
   // instead of about 90 VGPRs, 3 instead of 4 waves per SIMD); FP64 passes
   // are held to 2 waves per SIMD by their LDS either way.
-  constexpr bool PRELOAD = !(sizeof(T) == 4 && N >= 512);
+  constexpr bool SPLIT = ColShape<T, N, V>::SPLIT;
+  constexpr bool PRELOAD = !(sizeof(T) == 4 && N >= 512) && !SPLIT;
 
   const bool active = (int)threadIdx.x < ColShape<T, N, V>::THREADS;
   const int cl = threadIdx.x % B;
@@ -258,7 +264,8 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
   const int c = tile * B + cl;
   const bool valid = active && c < a.ncols;
   const long base_off = (long)slab * a.slab_stride + (valid ? c : 0);
-  cx<T>* lds = lds_all + cl;
+  // column cl's slots: complex elements, or with SPLIT real ones
+  cx<T>* lds = SPLIT ? reinterpret_cast<cx<T>*>(reinterpret_cast<T*>(lds_all) + cl) : lds_all + cl;
 
   cx<T> v[W];
   if constexpr (OP == COL_CG_FIRST) {
@@ -317,7 +324,7 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
           v[q * R0 + r] = pn;
         }
     }
-    fft_thread<PL, true, MAP>(v, t, lds, a.tw, active);
+    fft_thread<PL, true, MAP, SPLIT>(v, t, lds, a.tw, active);
     if (first) {  // uniform over the launch
       block_reduce_store<3>(acc, a.partials, block_linear);
     } else {
@@ -337,12 +344,12 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
   if constexpr (OP == COL_CG_FIRST) {
     // done above
   } else if constexpr (OP == COL_PLAIN) {
-    fft_thread<PL, INV, MAP>(v, t, lds, a.tw, active);
+    fft_thread<PL, INV, MAP, SPLIT>(v, t, lds, a.tw, active);
   } else if constexpr (OP == COL_PRIOR) {
     // forward transform, multiply by 1/lambda (after removing the prior mean
     // from mode 0), inverse transform: S_L^-1 applied along the last axis of
     // a field already transformed along y and z.
-    fft_thread<PL, false, MAP>(v, t, lds, a.tw, active);
+    fft_thread<PL, false, MAP, SPLIT>(v, t, lds, a.tw, active);
     const int ky = c / a.g.h, kz = c % a.g.h;
     double acc[1] = {0.0};
 #pragma unroll
@@ -357,8 +364,8 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
         if (valid) acc[0] += herm_w(kz, a.g) * (double)il * ((double)x.x * x.x + (double)x.y * x.y);
         v[q * RL + m] = {x.x * il, x.y * il};
       }
-    last_to_first<PL, MAP>(v, t, lds, active);
-    fft_thread<PL, true, MAP>(v, t, lds, a.tw, active);
+    last_to_first<PL, MAP, SPLIT>(v, t, lds, active);
+    fft_thread<PL, true, MAP, SPLIT>(v, t, lds, a.tw, active);
     block_reduce_store<1>(acc, a.partials, block_linear);
   } else if constexpr (OP == COL_CG_LAST) {
     // forward transform; q = X + p/lambda (= H p); r -= alpha q and
@@ -379,7 +386,7 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
           pre_il[q * RL + m] = valid ? inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_TAB) : T(0);
         }
     }
-    fft_thread<PL, false, MAP>(v, t, lds, a.tw, active);
+    fft_thread<PL, false, MAP, SPLIT>(v, t, lds, a.tw, active);
     const double hw = herm_w(kz, a.g);
     const double alpha = a.scal[SC_ALPHA], dbar = a.scal[SC_DBAR];
     double acc[2] = {0.0, 0.0};
@@ -430,7 +437,7 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
           pre_il[q * RL + m] = valid ? inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_TAB) : T(0);
         }
     }
-    fft_thread<PL, false, MAP>(v, t, lds, a.tw, active);
+    fft_thread<PL, false, MAP, SPLIT>(v, t, lds, a.tw, active);
     double acc[3] = {0.0, 0.0, 0.0};
     const double hw = herm_w(kz, a.g);
 #pragma unroll

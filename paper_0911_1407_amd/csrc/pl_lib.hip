@@ -37,6 +37,17 @@ struct Status {
 enum VarSlot { V_XCG = 0, V_Y, V_Z, V_XOP, V_TAB_CG, V_TAB_OP, V_NT, V_COUNT };
 static_assert(V_COUNT == PL_NUM_VARIANTS, "schedule slots");
 
+// Values a schedule slot takes: column passes 0 (default tile), 1 (wide),
+// 3 (split LDS exchange); the row pass 0 or 1; tables 0 or 1; the
+// streaming policy 0..NT_ALL.  (2 is the batched passes' narrow tile.)
+bool variant_allowed(int slot, int v) {
+  switch (slot) {
+    case V_XCG: case V_Y: case V_XOP: return v == 0 || v == 1 || v == 3;
+    case V_NT: return v >= 0 && v <= 31;
+    default: return v == 0 || v == 1;
+  }
+}
+
 }  // namespace
 
 struct pl_plan {
@@ -1648,20 +1659,25 @@ int time_hvp(pl_plan* p, int reps, float* ms) {
   return rc;
 }
 
-// Try every combination of the choices in `slots` (each 0..max), timing
-// with `timer`; keep the fastest.  Returns its time in *best.
+// Try every combination of the choices in `slots` (each 0..max, skipping
+// values a slot does not allow), timing with `timer`; keep the fastest.
+// Returns its time in *best.
 template <typename Timer>
 int tune_slots(pl_plan* p, int pi, const int* slots, const int* maxv, int ns, Timer timer, float* best) {
   int cur[V_COUNT] = {}, keep[V_COUNT] = {};
   *best = 1e30f;
   for (;;) {
-    for (int i = 0; i < ns; ++i) p->var[pi][slots[i]] = cur[i];
-    float ms = 0.f;
-    int rc = timer(&ms);
-    if (rc) return rc;
-    if (ms < *best) {
-      *best = ms;
-      for (int i = 0; i < ns; ++i) keep[i] = cur[i];
+    bool ok = true;
+    for (int i = 0; i < ns; ++i) ok = ok && variant_allowed(slots[i], cur[i]);
+    if (ok) {
+      for (int i = 0; i < ns; ++i) p->var[pi][slots[i]] = cur[i];
+      float ms = 0.f;
+      int rc = timer(&ms);
+      if (rc) return rc;
+      if (ms < *best) {
+        *best = ms;
+        for (int i = 0; i < ns; ++i) keep[i] = cur[i];
+      }
     }
     int i = 0;
     while (i < ns && cur[i] == maxv[i]) cur[i++] = 0;
@@ -1679,15 +1695,18 @@ int tune_precision(pl_plan* p, const std::string& key, std::vector<std::string>&
     if (line.compare(0, key.size() + 1, key + " ") == 0) {
       int v[V_COUNT];
       float t_cg, t_hvp;
-      if (std::sscanf(line.c_str() + key.size(), "%d %d %d %d %d %d %d %f %f", &v[0], &v[1], &v[2], &v[3], &v[4],
-                      &v[5], &v[6], &t_cg, &t_hvp) == V_COUNT + 2 &&
-          ((v[0] | v[1] | v[2] | v[3] | v[4] | v[5]) & ~1) == 0 && (v[V_NT] & ~NT_ALL) == 0) {
+      bool ok = std::sscanf(line.c_str() + key.size(), "%d %d %d %d %d %d %d %f %f", &v[0], &v[1], &v[2], &v[3],
+                            &v[4], &v[5], &v[6], &t_cg, &t_hvp) == V_COUNT + 2;
+      for (int i = 0; ok && i < V_COUNT; ++i) ok = variant_allowed(i, v[i]);
+      if (ok) {
         for (int i = 0; i < V_COUNT; ++i) p->var[pi][i] = v[i];
         return PL_OK;
       }
     }
   }
-  const int mx = has_wide_variant(p->n[0]) ? 1 : 0, my = has_wide_variant(p->n[1]) ? 1 : 0,
+  // column passes: default, wide and split tiles (lengths 128-512); rows:
+  // default and wide
+  const int mx = has_wide_variant(p->n[0]) ? 3 : 0, my = has_wide_variant(p->n[1]) ? 3 : 0,
             mr = has_wide_variant(p->n[2]) ? 1 : 0, mt = p->radial ? 1 : 0;
   const int reps = p->N >= (1L << 24) ? 5 : 20;
   // the solver's CG step: first the tile variants of the x passes carrying
@@ -1767,10 +1786,8 @@ extern "C" int pl_plan_autotune(pl_plan* p, const char* cache_path) {
 
 extern "C" int pl_plan_set_variants(pl_plan* p, const int32_t v[2 * PL_NUM_VARIANTS]) {
   if (!p || !v) return PL_ERR_INVALID_ARG;
-  for (int i = 0; i < 2 * V_COUNT; ++i) {
-    const int hi = (i % V_COUNT == V_NT) ? NT_ALL : 1;
-    if (v[i] < 0 || v[i] > hi) return fail(p, PL_ERR_INVALID_ARG, "schedule choice out of range");
-  }
+  for (int i = 0; i < 2 * V_COUNT; ++i)
+    if (!variant_allowed(i % V_COUNT, v[i])) return fail(p, PL_ERR_INVALID_ARG, "schedule choice out of range");
   for (int pi = 0; pi < 2; ++pi)
     for (int i = 0; i < V_COUNT; ++i) p->var[pi][i] = v[V_COUNT * pi + i];
   return PL_OK;

@@ -61,6 +61,15 @@ static hipError_t row_launch_n(int op, const RowArgs<T>& a, hipStream_t st, int*
 template <>
 hipError_t launch_col<PL_T>(int N, bool inverse, int op, const ColArgs<PL_T>& a, int nslabs, hipStream_t st,
                             int* nblocks, int variant) {
+  if (variant == 3) {
+    switch (N) {
+#define PL_CASE(NN) \
+  case NN: return col_launch_n<PL_T, NN, 3>(inverse, op, a, nslabs, st, nblocks);
+      PL_WIDE_LENGTHS(PL_CASE)
+#undef PL_CASE
+      default: break;
+    }
+  }
   if (variant == 1) {
     switch (N) {
 #define PL_CASE(NN) \
