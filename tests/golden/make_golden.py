@@ -28,7 +28,7 @@ well below the 1e-6 tolerance of the parity tests):
   R = 200 Mpc/h, 20% masked 8^3 blocks, nbar 0.5, unit bias);
 * ``bias256`` -- the same selection with beta = 1.5, nbar = 2, plus the
   adjoint of L = sum (s* - s_true)^2: lambda = H(s*)^-1 dL/ds* by the oracle's
-  spectral PCG to 1e-12, dL/dA, dL/dbeta, dL/dnbar, and dL/dN along a seeded
+  spectral PCG to 1e-10, dL/dA, dL/dbeta, dL/dnbar, and dL/dN along a seeded
   direction u, +-1 in the cells with counts and 0 elsewhere
   (sum_i beta lambda_i u_i);
 * ``batch64`` -- the 64 uneven instances (n in {32, 48, 64, 96}) of the batched
@@ -95,13 +95,14 @@ def field_stats(x):
             "max": float(np.max(x))}
 
 
-def solve_map(inst, rtol=1e-10):
+def solve_map(inst, rtol=1e-10, precond="mean"):
     P = problem(inst)
     t = time.time()
-    s, s_hat, info = o_newton.newton_krylov(P, rtol=rtol, max_newton=200, max_cg=5000, return_hat=True)
+    s, s_hat, info = o_newton.newton_krylov(P, rtol=rtol, max_newton=200, max_cg=20000, return_hat=True,
+                                            precond=precond)
     dt = time.time() - t
     rec = {"rtol": rtol, "newton_its": int(info["newton_its"]), "cg_its": int(info["cg_its"]),
-           "rel_grad": float(info["rel_grad"]), "status": info["status"], "seconds": dt}
+           "rel_grad": float(info["rel_grad"]), "status": info["status"], "seconds": dt, "precond": precond}
     return P, s, rec
 
 
@@ -113,11 +114,11 @@ def write(name, obj):
     print(f"wrote {path}", flush=True)
 
 
-def golden_map(name, tag, with_adjoint=False, n_uniform=4096):
+def golden_map(name, tag, with_adjoint=False, n_uniform=4096, precond="mean", adjoint_rtol=1e-12):
     t = time.time()
     inst = synth.config_instance(name)
     print(f"{name}: inputs in {time.time() - t:.1f}s", flush=True)
-    P, s, rec = solve_map(inst)
+    P, s, rec = solve_map(inst, precond=precond)
     print(f"{name}: oracle MAP {rec}", flush=True)
     assert rec["status"] == "ok", rec
     idx = sample_cells(inst, s, n_uniform, tag)
@@ -131,14 +132,14 @@ def golden_map(name, tag, with_adjoint=False, n_uniform=4096):
         # L = sum (s* - s_true)^2 at the oracle MAP; adjoint by spectral PCG
         L, dL = o_adj.squared_error_loss(s, inst["s_true"])
         t = time.time()
-        lam, its = o_adj.adjoint_pcg(P, s, dL, rtol=1e-12, max_cg=50000)
+        lam, its = o_adj.adjoint_pcg(P, s, dL, rtol=adjoint_rtol, max_cg=100000, precond=precond)
         grads = o_adj.param_grads(P, s, lam)
         # direction of the counts derivative: +-1 in cells with counts (a
         # perturbation there keeps N >= 0), 0 elsewhere
         u = np.random.default_rng([SAMPLE_SEED, 100 + tag]).choice([-1.0, 1.0], size=inst["n"])
         u = np.where(inst["counts"] > 0, u, 0.0)
         out["adjoint"] = {
-            "loss": L, "cg_its": int(its), "rtol": 1e-12, "seconds": time.time() - t,
+            "loss": L, "cg_its": int(its), "rtol": adjoint_rtol, "precond": precond, "seconds": time.time() - t,
             "dL_dA": grads["A"], "dL_dbeta": grads["beta"], "dL_dnbar": grads["nbar"],
             "dL_dN_dot_u": float(np.sum(grads["N"] * u)),
             "u_seed": [SAMPLE_SEED, 100 + tag],
@@ -170,7 +171,12 @@ if __name__ == "__main__":
         if w == "sel256":
             golden_map("sel256", 1)
         elif w == "bias256":
-            golden_map("bias256", 2, with_adjoint=True)
+            # beta = 1.5, nbar = 2 under the radial selection: the Hessian
+            # diagonal spans decades and the mean-diagonal preconditioner
+            # needs ~10x the CG steps of the selection workload; the
+            # 25th-percentile constant reaches the same MAP (H is positive
+            # definite; tests/test_oracle_newton.py pins the equivalence)
+            golden_map("bias256", 2, with_adjoint=True, precond="p25", adjoint_rtol=1e-10)
         elif w == "batch64":
             golden_batch()
         elif w == "big512":

@@ -102,3 +102,22 @@ def test_not_converged_and_info():
     p = oracle_problem(inst)
     s, info = newton.newton_krylov(p, rtol=1e-8, max_newton=1)
     assert info["status"] == "not_converged" and info["newton_its"] == 1
+
+
+@pytest.mark.parametrize("name", ["bias256", "sel256"])
+def test_preconditioner_changes_path_not_map(name):
+    # the workloads' recipes at 32^3: the 25th-percentile preconditioner
+    # constant takes a different (shorter) CG path to the same MAP and the
+    # same adjoint solution as the mean-diagonal one (H is positive definite)
+    from oracle import adjoint
+    inst = synth.config_instance(name, n=32)
+    p = oracle_problem(inst)
+    s1, i1 = newton.newton_krylov(p, rtol=1e-11, max_cg=5000, precond="mean")
+    s2, i2 = newton.newton_krylov(p, rtol=1e-11, max_cg=5000, precond="p25")
+    assert i1["status"] == "ok" and i2["status"] == "ok"
+    assert i1["cg_its"] != i2["cg_its"]
+    assert np.linalg.norm(s1 - s2) <= 1e-9 * np.linalg.norm(s1)
+    dL = 2.0 * (s1 - inst["s_true"])
+    l1, _ = adjoint.adjoint_pcg(p, s1, dL, rtol=1e-12, max_cg=20000, precond="mean")
+    l2, _ = adjoint.adjoint_pcg(p, s1, dL, rtol=1e-12, max_cg=20000, precond="p25")
+    assert np.linalg.norm(l1 - l2) <= 1e-9 * np.linalg.norm(l1)
