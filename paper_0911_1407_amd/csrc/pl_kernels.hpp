@@ -167,7 +167,9 @@ enum ColOp {
   COL_PRIOR = 1,     // forward, times 1/lambda, inverse (partials K = 1)
   COL_ADDPRIOR = 2,  // forward; out = X + (1/lambda) base (partials K = 3)
   COL_CG_FIRST = 3,  // CG prologue on the input, then inverse transform (partials K = 1)
-  COL_CG_LAST = 4    // forward; q = X + p/lambda; r -= alpha q (partials K = 2)
+  COL_CG_LAST = 4,   // forward; q = X + p/lambda; r -= alpha q (partials K = 2)
+  COL_CG_INIT = 5    // COL_CG_FIRST of the first iteration: r0 = sign * rhs, x0 = 0,
+                     // p = M^-1 r0 (partials K = 3)
 };
 
 template <typename T>
@@ -193,11 +195,10 @@ struct ColArgs {
   const double* scal;  // device scalars (SC_*)
   const double* skip;  // if non-null and *skip != 0 the launch does nothing
   int nt;              // NT_* bits: operands loaded / stored non-temporally
-  // First CG iteration (cg_first != 0): COL_CG_FIRST forms the initial
+  // COL_CG_INIT (the first CG iteration's first pass) forms the initial
   // residual r = cg_rhs_sign * cg_rhs itself (stored to cg_r), x = 0 (stored
   // to cg_x) and p = M^-1 r, with partials (p^H Lambda^-1 p, r^H M^-1 r,
   // r^H r).
-  int cg_first;
   const cx<double>* cg_rhs;
   double cg_rhs_sign;
   int variant;  // batched launches: this instance's tile variant (0 or 2)
@@ -224,11 +225,14 @@ constexpr int col_tile(int P, int N, int elem_bytes, int threads, int lds_cap) {
 // and imaginary parts through LDS one after the other (half the LDS, so
 // twice the blocks per CU when registers allow) and the second operand of
 // the fused x passes loaded after the transform (fewer registers).
+// V = 4 ("extra wide"): 1024 threads and at most 160 KB, one block per CU
+// with the longest row segments (256 bytes of FP32 columns at 512 points).
 template <typename T, int N, int V = 0>
 struct ColShape {
   static constexpr int P = Plan<N>::P;
-  static constexpr int B = col_tile(P, N, (int)sizeof(cx<T>), V == 1 ? 512 : (V == 2 ? 128 : 256),
-                                    V == 1 ? 131072 : (V == 2 ? 32768 : 65536));
+  static constexpr int B = col_tile(P, N, (int)sizeof(cx<T>),
+                                    V == 1 ? 512 : (V == 2 ? 128 : (V == 4 ? 1024 : 256)),
+                                    V == 1 ? 131072 : (V == 2 ? 32768 : (V == 4 ? 163840 : 65536)));
   static constexpr int THREADS = B * P;
   static constexpr bool SPLIT = V == 3;
   static constexpr int LDS = P > 1 ? (SPLIT ? (N * B + 1) / 2 : N * B) : 1;  // complex elements
@@ -253,10 +257,11 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
   // The x passes that add (1/lambda) times a second operand load it and the
   // table before the transform, so that their latency overlaps it, unless
   // the extra registers would cost occupancy (FP32 at 512 points: 146
-  // instead of about 90 VGPRs, 3 instead of 4 waves per SIMD); FP64 passes
-  // are held to 2 waves per SIMD by their LDS either way.
+  // instead of about 90 VGPRs, 3 instead of 4 waves per SIMD; the split
+  // tile; 1024-thread blocks, held to 128 VGPRs); the other FP64 passes are
+  // held to 2 waves per SIMD by their LDS either way.
   constexpr bool SPLIT = ColShape<T, N, V>::SPLIT;
-  constexpr bool PRELOAD = !(sizeof(T) == 4 && N >= 512) && !SPLIT;
+  constexpr bool PRELOAD = !(sizeof(T) == 4 && N >= 512) && !SPLIT && ColShape<T, N, V>::THREADS <= 512;
 
   const bool active = (int)threadIdx.x < ColShape<T, N, V>::THREADS;
   const int cl = threadIdx.x % B;
@@ -268,17 +273,16 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
   cx<T>* lds = SPLIT ? reinterpret_cast<cx<T>*>(reinterpret_cast<T*>(lds_all) + cl) : lds_all + cl;
 
   cx<T> v[W];
-  if constexpr (OP == COL_CG_FIRST) {
+  if constexpr (OP == COL_CG_FIRST || OP == COL_CG_INIT) {
     // Krylov prologue on the x pass of a half spectrum (columns = (ky, kz)):
     //   p = M^-1 r + beta p_old (in place), partial sum of p^H Lambda^-1 p;
     // then the inverse transform of p.
     const double beta = a.scal[SC_BETA], dbar = a.scal[SC_DBAR];
     const int ky = c / a.g.h, kz = c % a.g.h;
     const double hw = herm_w(kz, a.g);
-    const bool first = a.cg_first != 0;
     double acc[3] = {0.0, 0.0, 0.0};
     cx<T>* pio = const_cast<cx<T>*>(a.in);
-    if (first) {  // uniform over the launch: one loop or the other
+    if constexpr (OP == COL_CG_INIT) {
 #pragma unroll
       for (int q = 0; q < W / R0; ++q)
 #pragma unroll
@@ -325,7 +329,7 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
         }
     }
     fft_thread<PL, true, MAP, SPLIT>(v, t, lds, a.tw, active);
-    if (first) {  // uniform over the launch
+    if constexpr (OP == COL_CG_INIT) {
       block_reduce_store<3>(acc, a.partials, block_linear);
     } else {
       double acc1[1] = {acc[0]};
@@ -341,7 +345,7 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
     }
   }
 
-  if constexpr (OP == COL_CG_FIRST) {
+  if constexpr (OP == COL_CG_FIRST || OP == COL_CG_INIT) {
     // done above
   } else if constexpr (OP == COL_PLAIN) {
     fft_thread<PL, INV, MAP, SPLIT>(v, t, lds, a.tw, active);
@@ -1188,7 +1192,7 @@ __global__ void set_scalar_kernel(double* scal, int idx, double value) {
 }
 
 // Start of a CG solve whose first iteration forms the initial residual
-// itself (cg_first): stopping threshold, iteration count and state.
+// itself (COL_CG_INIT): stopping threshold, iteration count and state.
 __global__ void cg_start_kernel(double* scal, double tol2) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     scal[SC_TOL2] = tol2;

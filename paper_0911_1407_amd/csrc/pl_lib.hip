@@ -38,11 +38,12 @@ enum VarSlot { V_XCG = 0, V_Y, V_Z, V_XOP, V_TAB_CG, V_TAB_OP, V_NT, V_COUNT };
 static_assert(V_COUNT == PL_NUM_VARIANTS, "schedule slots");
 
 // Values a schedule slot takes: column passes 0 (default tile), 1 (wide),
-// 3 (split LDS exchange); the row pass 0 or 1; tables 0 or 1; the
-// streaming policy 0..NT_ALL.  (2 is the batched passes' narrow tile.)
+// 3 (split LDS exchange), 4 (extra wide); the row pass 0 or 1; tables 0 or
+// 1; the streaming policy 0..NT_ALL.  (2 is the batched passes' narrow
+// tile.)
 bool variant_allowed(int slot, int v) {
   switch (slot) {
-    case V_XCG: case V_Y: case V_XOP: return v == 0 || v == 1 || v == 3;
+    case V_XCG: case V_Y: case V_XOP: return v == 0 || v == 1 || v == 3 || v == 4;
     case V_NT: return v >= 0 && v <= 31;
     default: return v == 0 || v == 1;
   }
@@ -249,7 +250,7 @@ template <typename T>
 hipError_t run_col(pl_plan* p, int axis, bool inverse, int op, const ColArgs<T>& a, int* nb) {
   int dummy;
   const int pi = sizeof(T) == 4 ? 1 : 0;
-  const bool krylov = op == COL_CG_FIRST || op == COL_CG_LAST;
+  const bool krylov = op == COL_CG_FIRST || op == COL_CG_LAST || op == COL_CG_INIT;
   const int v = axis == 1 ? p->var[pi][V_Y] : p->var[pi][krylov ? V_XCG : V_XOP];
   if (op == COL_PLAIN)
     return launch_col<T>(p->n[axis], inverse, op, a, axis == 0 ? 1 : p->n[0], p->stream, nb ? nb : &dummy, v);
@@ -411,7 +412,7 @@ int ensure_d32(pl_plan* p) {
 // ---------------------------------------------------------------------------
 // With tol_rel_of_rhs == 0 (an absolute tolerance known in advance) the
 // first iteration's first pass forms the initial residual itself
-// (COL_CG_FIRST with cg_first), so no separate initialisation pass runs;
+// (COL_CG_INIT), so no separate initialisation pass runs;
 // with a tolerance relative to ||rhs|| an initialisation pass and one
 // read-back of ||rhs|| come first.  first_chunk (> 0) sets how many
 // iterations are queued before the first host check (later checks come
@@ -455,11 +456,10 @@ int pcg(pl_plan* p, const cx<double>* rhs, double sign, double tol_abs, double t
       c1.scal = p->scal;
       c1.partials = part_a;
       c1.skip = skip;
-      c1.cg_first = first ? 1 : 0;
       c1.cg_rhs = rhs;
       c1.cg_rhs_sign = sign;
       c1.cg_x = x;
-      HIPCHK(p, run_col<T>(p, 0, true, COL_CG_FIRST, c1, &nb1));
+      HIPCHK(p, run_col<T>(p, 0, true, first ? COL_CG_INIT : COL_CG_FIRST, c1, &nb1));
       ColArgs<T> c2 = col_args<T>(p, 1, t, t);
       c2.skip = skip;
       HIPCHK(p, run_col<T>(p, 1, true, COL_PLAIN, c2, nullptr));
@@ -1704,9 +1704,9 @@ int tune_precision(pl_plan* p, const std::string& key, std::vector<std::string>&
       }
     }
   }
-  // column passes: default, wide and split tiles (lengths 128-512); rows:
-  // default and wide
-  const int mx = has_wide_variant(p->n[0]) ? 3 : 0, my = has_wide_variant(p->n[1]) ? 3 : 0,
+  // column passes: default, wide, split and extra-wide tiles (lengths
+  // 128-512); rows: default and wide
+  const int mx = has_wide_variant(p->n[0]) ? 4 : 0, my = has_wide_variant(p->n[1]) ? 4 : 0,
             mr = has_wide_variant(p->n[2]) ? 1 : 0, mt = p->radial ? 1 : 0;
   const int reps = p->N >= (1L << 24) ? 5 : 20;
   // the solver's CG step: first the tile variants of the x passes carrying

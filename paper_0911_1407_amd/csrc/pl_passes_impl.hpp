@@ -21,6 +21,8 @@ static hipError_t col_launch_n(bool inverse, int op, const ColArgs<T>& a, int ns
     hipLaunchKernelGGL((col_kernel<T, N, false, COL_ADDPRIOR, V>), grid, dim3(S::THREADS), 0, st, a);
   } else if (op == COL_CG_FIRST) {
     hipLaunchKernelGGL((col_kernel<T, N, true, COL_CG_FIRST, V>), grid, dim3(S::THREADS), 0, st, a);
+  } else if (op == COL_CG_INIT) {
+    hipLaunchKernelGGL((col_kernel<T, N, true, COL_CG_INIT, V>), grid, dim3(S::THREADS), 0, st, a);
   } else if (op == COL_CG_LAST) {
     hipLaunchKernelGGL((col_kernel<T, N, false, COL_CG_LAST, V>), grid, dim3(S::THREADS), 0, st, a);
   } else {
@@ -65,6 +67,15 @@ hipError_t launch_col<PL_T>(int N, bool inverse, int op, const ColArgs<PL_T>& a,
     switch (N) {
 #define PL_CASE(NN) \
   case NN: return col_launch_n<PL_T, NN, 3>(inverse, op, a, nslabs, st, nblocks);
+      PL_WIDE_LENGTHS(PL_CASE)
+#undef PL_CASE
+      default: break;
+    }
+  }
+  if (variant == 4) {
+    switch (N) {
+#define PL_CASE(NN) \
+  case NN: return col_launch_n<PL_T, NN, 4>(inverse, op, a, nslabs, st, nblocks);
       PL_WIDE_LENGTHS(PL_CASE)
 #undef PL_CASE
       default: break;

@@ -34,7 +34,7 @@ def test_every_variant_matches_oracle(n):
     assert radial == (len(set(n)) == 1)
     # the operator's passes: x (operator), y, z variants (default, wide and,
     # for the column passes, the split LDS exchange) and its table
-    for xo, y, z, tab, nt in itertools.product((0, 1, 3), (0, 1, 3), (0, 1), (0, 1), (0, 31)):
+    for xo, y, z, tab, nt in itertools.product((0, 1, 3, 4), (0, 1, 3, 4), (0, 1), (0, 1), (0, 31)):
         combo = (0, y, z, xo, 0, tab, nt)
         binding.pl_plan_set_variants(plan.h, fp64=combo, fp32=combo)
         plan.grad(s)
@@ -48,7 +48,7 @@ def test_every_variant_matches_oracle(n):
         # the Krylov-carrying passes: every x variant and table choice
         # reaches the same MAP (FP64 and mixed)
         ref_s = None
-        for xk, tab, nt in itertools.product((0, 1, 3), (0, 1), (0, 1, 2, 4, 8, 16, 31)):
+        for xk, tab, nt in itertools.product((0, 1, 3, 4), (0, 1), (0, 1, 2, 4, 8, 16, 31)):
             combo = (xk, 0, 0, 0, tab, 0, nt)
             binding.pl_plan_set_variants(plan.h, fp64=combo, fp32=combo)
             for prec in (binding.PL_FP64, binding.PL_MIXED):
