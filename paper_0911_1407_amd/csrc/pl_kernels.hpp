@@ -132,6 +132,7 @@ enum Scal {
   SC_DONE = 6,    // 0 running, 1 converged / capped, 2 breakdown
   SC_ITS = 7,     // CG iterations that changed the iterate
   SC_DBAR = 8,    // mean of the Hessian diagonal (preconditioner)
+  SC_RR0 = 9,     // r^H r of the initial residual
   SC_JUNK = 10,   // sink for an unused partial
   SC_GG = 11, SC_PRIOR = 12, SC_LIK = 13, SC_DSUM = 14,
   SC_INACTIVE = 15,  // batched solves: instance finished, every pass skips it
@@ -969,6 +970,7 @@ __device__ __forceinline__ void finalize_body(const double* __restrict__ partial
     case FIN_CG_INIT:
       scal[SC_RZ] = v[0];
       scal[SC_RR] = v[1];
+      scal[SC_RR0] = v[1];
       scal[SC_DONE] = (v[1] <= scal[SC_TOL2]) ? 1.0 : 0.0;
       scal[SC_ITS] = 0.0;
       scal[SC_ALPHA] = 0.0;
@@ -991,6 +993,7 @@ __device__ __forceinline__ void finalize_body(const double* __restrict__ partial
       const double rz = e3[1] * scale2, rr = e3[2] * scale2;
       scal[SC_RZ] = rz;
       scal[SC_RR] = rr;
+      scal[SC_RR0] = rr;
       scal[SC_ITS] = 0.0;
       scal[SC_BETA] = 0.0;
       scal[SC_ALPHA] = 0.0;

@@ -410,13 +410,27 @@ int ensure_d32(pl_plan* p) {
 // at once on the device (the passes read the done flag).
 // *its receives iterations that changed x, *hvps the Hessian products run.
 // ---------------------------------------------------------------------------
+// CG iterations to queue after a host check found the solve still running:
+// the residual fell from rr0 to rr in its iterations, so at that rate it
+// needs its * ln(rr / tol2) / ln(rr0 / rr) more (PCG usually speeds up, so
+// this rarely falls short), with a small margin; at least check_every and at
+// most its (the residual norm is not monotone: a slow start must not queue
+// a long tail of iterations that will be skipped).
+int next_cg_chunk(const double* sc, int check_every) {
+  const double its = sc[SC_ITS], rr = sc[SC_RR], rr0 = sc[SC_RR0], tol2 = sc[SC_TOL2];
+  if (!(its > 0.0 && rr > tol2 && tol2 > 0.0 && rr0 > rr)) return check_every;
+  const double est = its * std::log(rr / tol2) / std::log(rr0 / rr);
+  const int want = (int)std::ceil(1.0625 * est) + 2;
+  return std::max(check_every, std::min(want, (int)its));
+}
+
 // With tol_rel_of_rhs == 0 (an absolute tolerance known in advance) the
 // first iteration's first pass forms the initial residual itself
 // (COL_CG_INIT), so no separate initialisation pass runs;
 // with a tolerance relative to ||rhs|| an initialisation pass and one
 // read-back of ||rhs|| come first.  first_chunk (> 0) sets how many
-// iterations are queued before the first host check (later checks come
-// every check_every iterations).
+// iterations are queued before the first host check; later chunks are
+// sized from the residual decrease so far (next_cg_chunk).
 template <typename T>
 int pcg(pl_plan* p, const cx<double>* rhs, double sign, double tol_abs, double tol_rel_of_rhs, int max_cg,
         int check_every, int* its, int* hvps, double* rel_res, double* rhs_norm, int first_chunk = 0) {
@@ -445,7 +459,8 @@ int pcg(pl_plan* p, const cx<double>* rhs, double sign, double tol_abs, double t
   }
   int launched = 0;
   while (launched < max_cg) {
-    const int want = (launched == 0 && first_chunk > 0) ? first_chunk : check_every;
+    const int want = launched == 0 ? (first_chunk > 0 ? first_chunk : check_every)
+                                   : next_cg_chunk(p->h_scal, check_every);
     int chunk = std::min(want, max_cg - launched);
     for (int k = 0; k < chunk; ++k) {
       int nb1 = 0, nb3 = 0, nb5 = 0;
@@ -685,11 +700,24 @@ int newton_step_finish(pl_plan* p, double* s_io, const pl_solve_opts& o, double*
   return PL_OK;
 }
 
-// CG iterations queued before the first host check of a Newton step: most
-// of the previous step's count (the counts grow slowly as the forcing term
-// tightens), at least 4.  Each check costs a host round trip; each
-// iteration queued past convergence costs its launches, which exit at once.
-int first_cg_chunk(int prev_its) { return std::max(4, prev_its - prev_its / 8); }
+// CG iterations queued before the first host check of a Newton step.  PCG
+// on an SPD system needs about sqrt(kappa)/2 * ln(2/eta) iterations to cut
+// the residual by eta, and kappa moves little between late Newton steps, so
+// the previous step's count scaled by ln(2/eta)/ln(2/eta_prev) predicts
+// this one; a small margin on top makes one check the usual case.  While
+// the forcing term sits at its cap (the first, far-from-MAP steps) the
+// counts jump between 1 and tens of iterations from step to step, so there
+// at most 8 are queued before the first check.  Each check costs a host
+// round trip (the copy, then the first launches of the next batch run as
+// fast as the host issues them); each iteration queued past convergence
+// costs its launches, which exit at once: two or three of those cost about
+// one check.
+int first_cg_chunk(int prev_its, double prev_eta, double eta, double eta_max) {
+  if (prev_its <= 0 || !(prev_eta > 0.0 && prev_eta < 1.0) || !(eta > 0.0 && eta < 1.0)) return 8;
+  const double pred = prev_its * std::log(2.0 / eta) / std::log(2.0 / prev_eta);
+  const int want = std::max(4, (int)std::ceil(1.0625 * pred) + 2);
+  return prev_eta >= eta_max ? std::min(want, 8) : want;
+}
 
 // Inexact Newton-Krylov from the current s_io.  Each Newton step is queued
 // whole (CG, line search, the accepted update and the next gradient) and
@@ -717,6 +745,7 @@ int newton_solve(pl_plan* p, double* s_io, const pl_solve_opts& o, pl_solve_info
   }
   int status = PL_OK;
   int prev_its = 0;
+  double prev_eta = 0.0;
   if (g0 > 0.0) {
     for (int it = 0;; ++it) {
       if (gn <= o.rtol * g0) break;
@@ -731,7 +760,7 @@ int newton_solve(pl_plan* p, double* s_io, const pl_solve_opts& o, pl_solve_info
       rc = set_precond_constant(p);
       if (rc) return rc;
       int its = 0;
-      rc = newton_step_queue<T>(p, eta * gn, o, inf, first_cg_chunk(prev_its), &its);
+      rc = newton_step_queue<T>(p, eta * gn, o, inf, first_cg_chunk(prev_its, prev_eta, eta, o.eta_max), &its);
       if (rc) return rc;
       rc = grad_hat(p, s_io);
       if (rc) return rc;
@@ -743,9 +772,10 @@ int newton_solve(pl_plan* p, double* s_io, const pl_solve_opts& o, pl_solve_info
       if (rc) return rc;
       if constexpr (sizeof(T) == 4) {
         if (alpha < 0.0) {
-          // the iterate, its gradient and Hessian diagonal are unchanged
+          // the iterate, its gradient and Hessian diagonal are unchanged;
+          // the FP32 count at the same forcing term predicts the FP64 one
           int its64 = 0;
-          rc = newton_step_queue<double>(p, eta * gn, o, inf, first_cg_chunk(prev_its), &its64);
+          rc = newton_step_queue<double>(p, eta * gn, o, inf, first_cg_chunk(its, eta, eta, o.eta_max), &its64);
           if (rc) return rc;
           rc = grad_hat(p, s_io);
           if (rc) return rc;
@@ -757,6 +787,7 @@ int newton_solve(pl_plan* p, double* s_io, const pl_solve_opts& o, pl_solve_info
         }
       }
       prev_its = its;
+      prev_eta = eta;
       if (alpha < 0.0) {
         status = PL_ERR_LINESEARCH;
         p->err = descent ? "no step satisfies the Armijo condition" : "Newton direction is not a descent direction";

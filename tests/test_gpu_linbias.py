@@ -240,8 +240,10 @@ def test_no_data_returns_prior_mean(kind):
 def test_map_selection_workload_64_matches_oracle(kind):
     # the selection workload's recipe at 64^3 (radial selection, masked 8^3
     # blocks, nbar 0.5) with the benchmark's 1.5-cell smoothing multiplier;
-    # two oracle Newton paths with different preconditioners reach the same
-    # minimiser here (to 3e-10), so the comparison is of the MAP itself
+    # oracle Newton paths with different preconditioners reach the same
+    # minimiser on this recipe (asserted on the CPU by
+    # test_oracle_linbias.test_preconditioner_changes_path_not_minimiser),
+    # so the comparison is of the MAP itself
     inst = synth.config_instance("sel256", n=64)
     P = oracle_problem(inst)
     bk = _bk(inst, 1.0, 1.5)
