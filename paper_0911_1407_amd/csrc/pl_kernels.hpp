@@ -178,9 +178,13 @@ struct ColArgs {
   int n;             // transform length
   const cx<T>* in;
   cx<T>* out;
-  int ncols;         // columns per slab
+  int ncols;         // columns (of all slabs when cps > 0)
   long row_stride;   // distance (complex elements) between consecutive transform entries
-  long slab_stride;  // distance between slabs (blockIdx.y)
+  long slab_stride;  // distance between slabs
+  // y passes: columns per slab (kz values); column c is kz = c % cps of
+  // slab kx = c / cps, so tiles run across slab ends and none is ragged.
+  // 0 for x passes, whose columns are flattened (ky, kz) pairs of one slab.
+  int cps;
   const cx<T>* tw;   // twiddles of this length
   // fused x-pass operations (columns are flattened (ky, kz) pairs)
   Grid g;
@@ -269,7 +273,15 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
   const int t = active ? (int)threadIdx.x / B : 0;
   const int c = tile * B + cl;
   const bool valid = active && c < a.ncols;
-  const long base_off = (long)slab * a.slab_stride + (valid ? c : 0);
+  int sl = slab, cc = c;
+  if (a.cps > 0 && valid) {
+    sl = c / a.cps;
+    cc = c - sl * a.cps;
+  }
+  const long base_off = (long)sl * a.slab_stride + (valid ? cc : 0);
+  // the fused operations run on x passes: the column fixes (ky, kz), the
+  // transform position is kx, and an element's mode index is its offset
+  const int col_ky = c / a.g.h, col_kz = c % a.g.h;
   // column cl's slots: complex elements, or with SPLIT real ones
   cx<T>* lds = SPLIT ? reinterpret_cast<cx<T>*>(reinterpret_cast<T*>(lds_all) + cl) : lds_all + cl;
 
@@ -279,7 +291,7 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
     //   p = M^-1 r + beta p_old (in place), partial sum of p^H Lambda^-1 p;
     // then the inverse transform of p.
     const double beta = a.scal[SC_BETA], dbar = a.scal[SC_DBAR];
-    const int ky = c / a.g.h, kz = c % a.g.h;
+    const int kz = col_kz;
     const double hw = herm_w(kz, a.g);
     double acc[3] = {0.0, 0.0, 0.0};
     cx<T>* pio = const_cast<cx<T>*>(a.in);
@@ -288,12 +300,12 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
       for (int q = 0; q < W / R0; ++q)
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
-          int kx = in_pos<PL, 0>(t, q, r);
-          long idx = base_off + (long)kx * a.row_stride;
+          const int e = in_pos<PL, 0>(t, q, r), kx = e, ky = col_ky;
+          long idx = base_off + (long)e * a.row_stride;
           cx<T> pn = {T(0), T(0)};
           if (valid) {
             // r0 = sign * rhs; p = M^-1 r0 (no previous direction)
-            long mode = (long)kx * a.g.nyh + c;
+            long mode = base_off + (long)e * a.row_stride;
             const T il = inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_TAB);
             const T mi = precond_inv<T>(il, dbar);
             const cx<double> b = a.cg_rhs[idx];
@@ -314,12 +326,12 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
       for (int q = 0; q < W / R0; ++q)
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
-          int kx = in_pos<PL, 0>(t, q, r);
-          long idx = base_off + (long)kx * a.row_stride;
+          const int e = in_pos<PL, 0>(t, q, r), kx = e, ky = col_ky;
+          long idx = base_off + (long)e * a.row_stride;
           cx<T> pn = {T(0), T(0)};
           if (valid) {
             cx<T> po = ld_stream(pio + idx, a.nt & NT_P), rv = ld_stream(a.cg_r + idx, a.nt & NT_R);
-            long mode = (long)kx * a.g.nyh + c;
+            long mode = base_off + (long)e * a.row_stride;
             const T il = inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_TAB);
             const T mi = precond_inv<T>(il, dbar), bt = (T)beta;
             pn = {mi * rv.x + bt * po.x, mi * rv.y + bt * po.y};
@@ -355,14 +367,14 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
     // from mode 0), inverse transform: S_L^-1 applied along the last axis of
     // a field already transformed along y and z.
     fft_thread<PL, false, MAP, SPLIT>(v, t, lds, a.tw, active);
-    const int ky = c / a.g.h, kz = c % a.g.h;
+    const int kz = col_kz;
     double acc[1] = {0.0};
 #pragma unroll
     for (int q = 0; q < W / RL; ++q)
 #pragma unroll
       for (int m = 0; m < RL; ++m) {
-        int kx = out_pos<PL, PL::NS - 1>(t, q, m);
-        long mode = (long)kx * a.g.nyh + c;
+        const int e = out_pos<PL, PL::NS - 1>(t, q, m), kx = e, ky = col_ky;
+        long mode = base_off + (long)e * a.row_stride;
         cx<T> x = v[q * RL + m];
         if (mode == 0) x.x -= (T)a.k0_shift;
         T il = valid ? inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_TAB) : T(0);
@@ -377,7 +389,7 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
     // x += alpha p in place; partials (r^H r, r^H M^-1 r).  q is not stored.
     // p and 1/lambda at the output positions are loaded before the
     // transform so that their latency overlaps it.
-    const int ky = c / a.g.h, kz = c % a.g.h;
+    const int kz = col_kz;
     cx<T> pre_p[PRELOAD ? W : 1];
     T pre_il[PRELOAD ? W : 1];
     if constexpr (PRELOAD) {
@@ -385,8 +397,8 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
       for (int q = 0; q < W / RL; ++q)
 #pragma unroll
         for (int m = 0; m < RL; ++m) {
-          int kx = out_pos<PL, PL::NS - 1>(t, q, m);
-          long mode = (long)kx * a.g.nyh + c;
+          const int e = out_pos<PL, PL::NS - 1>(t, q, m), kx = e, ky = col_ky;
+          long mode = base_off + (long)e * a.row_stride;
           pre_p[q * RL + m] = valid ? ld_stream(a.base + mode, a.nt & NT_P) : cx<T>{T(0), T(0)};
           pre_il[q * RL + m] = valid ? inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_TAB) : T(0);
         }
@@ -399,8 +411,8 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
     for (int q = 0; q < W / RL; ++q)
 #pragma unroll
       for (int m = 0; m < RL; ++m) {
-        int kx = out_pos<PL, PL::NS - 1>(t, q, m);
-        long mode = (long)kx * a.g.nyh + c;
+        const int e = out_pos<PL, PL::NS - 1>(t, q, m), kx = e, ky = col_ky;
+        long mode = base_off + (long)e * a.row_stride;
         if (valid) {
           // vector arithmetic in the Krylov vectors' precision, sums in FP64
           cx<T> pv;
@@ -428,7 +440,7 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
   } else {
     // forward transform; out = scale * X + (1/lambda) (base - shift at mode 0);
     // base and 1/lambda are loaded before the transform (latency overlap)
-    const int ky = c / a.g.h, kz = c % a.g.h;
+    const int kz = col_kz;
     cx<T> pre_b[PRELOAD ? W : 1];
     T pre_il[PRELOAD ? W : 1];
     if constexpr (PRELOAD) {
@@ -436,8 +448,8 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
       for (int q = 0; q < W / RL; ++q)
 #pragma unroll
         for (int m = 0; m < RL; ++m) {
-          int kx = out_pos<PL, PL::NS - 1>(t, q, m);
-          long mode = (long)kx * a.g.nyh + c;
+          const int e = out_pos<PL, PL::NS - 1>(t, q, m), kx = e, ky = col_ky;
+          long mode = base_off + (long)e * a.row_stride;
           pre_b[q * RL + m] = valid ? ld_stream(a.base + mode, a.nt & NT_P) : cx<T>{T(0), T(0)};
           pre_il[q * RL + m] = valid ? inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_TAB) : T(0);
         }
@@ -449,8 +461,8 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
     for (int q = 0; q < W / RL; ++q)
 #pragma unroll
       for (int m = 0; m < RL; ++m) {
-        int kx = out_pos<PL, PL::NS - 1>(t, q, m);
-        long mode = (long)kx * a.g.nyh + c;
+        const int e = out_pos<PL, PL::NS - 1>(t, q, m), kx = e, ky = col_ky;
+        long mode = base_off + (long)e * a.row_stride;
         if (valid) {
           cx<T> b;
           T il;

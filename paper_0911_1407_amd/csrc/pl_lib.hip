@@ -238,10 +238,12 @@ ColArgs<T> col_args(pl_plan* p, int axis, const cx<T>* in, cx<T>* out) {
     a.ncols = (int)(p->n[1] * h);
     a.row_stride = (long)p->n[1] * h;
     a.slab_stride = 0;
-  } else {  // y: slabs = kx, columns = kz
-    a.ncols = (int)h;
+    a.cps = 0;
+  } else {  // y: columns = (kx, kz) pairs, kz fastest
+    a.ncols = (int)(p->n[0] * h);
     a.row_stride = h;
     a.slab_stride = (long)p->n[1] * h;
+    a.cps = (int)h;
   }
   return a;
 }
@@ -252,12 +254,11 @@ hipError_t run_col(pl_plan* p, int axis, bool inverse, int op, const ColArgs<T>&
   const int pi = sizeof(T) == 4 ? 1 : 0;
   const bool krylov = op == COL_CG_FIRST || op == COL_CG_LAST || op == COL_CG_INIT;
   const int v = axis == 1 ? p->var[pi][V_Y] : p->var[pi][krylov ? V_XCG : V_XOP];
-  if (op == COL_PLAIN)
-    return launch_col<T>(p->n[axis], inverse, op, a, axis == 0 ? 1 : p->n[0], p->stream, nb ? nb : &dummy, v);
+  if (op == COL_PLAIN) return launch_col<T>(p->n[axis], inverse, op, a, 1, p->stream, nb ? nb : &dummy, v);
   ColArgs<T> b = a;  // the 1/lambda table this pass reads
   b.radial = p->radial && p->var[pi][krylov ? V_TAB_CG : V_TAB_OP];
   b.inv_lam = View<T>::tab(p, b.radial);
-  return launch_col<T>(p->n[axis], inverse, op, b, axis == 0 ? 1 : p->n[0], p->stream, nb ? nb : &dummy, v);
+  return launch_col<T>(p->n[axis], inverse, op, b, 1, p->stream, nb ? nb : &dummy, v);
 }
 
 template <typename T>
@@ -466,7 +467,7 @@ int pcg(pl_plan* p, const cx<double>* rhs, double sign, double tol_abs, double t
       int nb1 = 0, nb3 = 0, nb5 = 0;
       const bool first = fused && launched == 0 && k == 0;
       const double* skip = p->scal + SC_DONE;
-      ColArgs<T> c1 = col_args<T>(p, 0, pp, t);
+          ColArgs<T> c1 = col_args<T>(p, 0, pp, t);
       c1.cg_r = r;
       c1.scal = p->scal;
       c1.partials = part_a;
@@ -1880,12 +1881,11 @@ void col_work(const std::vector<pl_plan*>& plans, int axis, const std::vector<in
     const pl_plan* p = plans[i];
     const BatchShape<T> sh = batch_shape<T>(p->n[axis], var[i]);
     const int h = p->g.h;
-    const int ncols = axis == 0 ? p->n[1] * h : h;
-    const int nslabs = axis == 0 ? 1 : p->n[0];
+    // y columns run across the kx slabs (ColArgs::cps), as x columns across ky
+    const int ncols = (axis == 0 ? p->n[1] : p->n[0]) * h;
     const int nbx = (ncols + sh.B - 1) / sh.B;
-    for (int sl = 0; sl < nslabs; ++sl)
-      for (int t = 0; t < nbx; ++t) w.items.push_back(make_int4((int)i, t, sl, t + nbx * sl));
-    w.nb[i] = nbx * nslabs;
+    for (int t = 0; t < nbx; ++t) w.items.push_back(make_int4((int)i, t, 0, t));
+    w.nb[i] = nbx;
     w.threads = std::max(w.threads, sh.col_threads);
     w.lds = std::max(w.lds, sh.col_lds);
   }
