@@ -173,6 +173,24 @@ enum ColOp {
                      // p = M^-1 r0 (partials K = 3)
 };
 
+// Arguments of one finalize (finalize_body): sums of per-block partials and
+// the scalar bookkeeping of kind FIN_*.
+struct FinArgs {
+  const double* partials;
+  int nb, K, kind, dst;
+  double scale;
+  double* scal;
+  double aux;
+  const double* partials2;
+  int nb2;
+  double scale2;
+};
+
+template <int NT>
+__device__ __forceinline__ void finalize_body(const double* __restrict__ partials, int nb, int K, int kind, int dst,
+                                              double scale, double* __restrict__ scal, double aux,
+                                              const double* __restrict__ partials2, int nb2, double scale2);
+
 template <typename T>
 struct ColArgs {
   int n;             // transform length
@@ -207,6 +225,11 @@ struct ColArgs {
   const cx<double>* cg_rhs;
   double cg_rhs_sign;
   int variant;  // batched launches: this instance's tile variant (0 or 2)
+  // COL_PLAIN launches with fin_on = 1 carry one extra workgroup that runs
+  // the finalize `fin` (saving a launch of its own); the host adds it to the
+  // grid
+  int fin_on;
+  FinArgs fin;
 };
 
 // Column tile width B: 256 threads per block where possible, at most 64 KB
@@ -502,6 +525,23 @@ template <typename T, int N, bool INV, int OP, int V>
 __global__ void __launch_bounds__((ColShape<T, N, V>::THREADS)) col_kernel(ColArgs<T> a) {
   __shared__ cx<T> lds_all[ColShape<T, N, V>::LDS];
   if (a.skip && *a.skip != 0.0) return;  // Krylov iteration after convergence
+  int gx = gridDim.x;
+  int hw = blockIdx.x + gridDim.x * blockIdx.y;
+  if constexpr (OP == COL_PLAIN) {
+    if (a.fin_on) {  // (launched with one row of tiles: gridDim.y == 1)
+      // the last workgroup runs the finalize riding on this launch (it only
+      // reads partials of earlier launches); the tiles keep their hardware
+      // ids, so the XCD mapping below holds
+      --gx;
+      if (hw == gx) {
+        const FinArgs& f = a.fin;
+        finalize_body<ColShape<T, N, V>::THREADS>(f.partials, f.nb, f.K, f.kind, f.dst, f.scale, f.scal, f.aux,
+                                                  f.partials2, f.nb2, f.scale2);
+        return;
+      }
+    }
+  }
+  const int total = gx * gridDim.y;
   // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
   // L2).  Give every XCD a contiguous range of (tile, slab) work items so
   // that neighbouring column tiles, whose row segments share cache lines
@@ -510,15 +550,13 @@ __global__ void __launch_bounds__((ColShape<T, N, V>::THREADS)) col_kernel(ColAr
   // (similar ky) are reused from that L2.
   int tile = blockIdx.x, slab = blockIdx.y;
   {
-    const int total = gridDim.x * gridDim.y;
-    const int hw = blockIdx.x + gridDim.x * blockIdx.y;
     const int xcd = hw & 7, k = hw >> 3;
     const int per = total >> 3, rem = total & 7;
     const int logical = xcd * per + (xcd < rem ? xcd : rem) + k;
-    tile = logical % gridDim.x;
-    slab = logical / gridDim.x;
+    tile = logical % gx;
+    slab = logical / gx;
   }
-  col_body<T, N, INV, OP, V>(a, tile, slab, lds_all, blockIdx.x + gridDim.x * blockIdx.y);
+  col_body<T, N, INV, OP, V>(a, tile, slab, lds_all, hw);
 }
 
 // ---------------------------------------------------------------------------
@@ -905,7 +943,6 @@ __global__ void __launch_bounds__(RED_THREADS) cg_init_kernel(const cx<double>* 
   cg_init_body<T>(rhs, rhs_sign, x, r, p, tab, radial, g, nh, scal, partials, blockIdx.x, gridDim.x);
 }
 
-#ifdef PL_OPS_KERNELS
 enum FinKind { FIN_STORE = 0, FIN_CG_INIT = 1, FIN_CG_ALPHA = 2, FIN_CG_BETA = 3, FIN_DBAR = 4, FIN_CG_ALPHA_ADD = 5,
                FIN_CG_ALPHA_FIRST = 6 };
 
@@ -1037,6 +1074,7 @@ __device__ __forceinline__ void finalize_body(const double* __restrict__ partial
   }
 }
 
+#ifdef PL_OPS_KERNELS
 constexpr int FIN_THREADS = 1024;
 __global__ void __launch_bounds__(FIN_THREADS) finalize_kernel(const double* __restrict__ partials, int nb, int K,
                                                                int kind, int dst, double scale,

@@ -485,10 +485,13 @@ int pcg(pl_plan* p, const cx<double>* rhs, double sign, double tol_abs, double t
       ra.partials = part_b;
       ra.skip = skip;
       HIPCHK(p, run_row<T>(p, ROW_HVP, ra, &nb3));
-      HIPCHK(p, finalize(p, nb3, 2, first ? FIN_CG_ALPHA_FIRST : FIN_CG_ALPHA, 0, 1.0, 0.0, part_b, part_a, nb1,
-                         invN));
+      // alpha = r^H z / p^H H p, finalized by an extra workgroup of the y
+      // pass that follows (which does not need it; the last x pass does)
       ColArgs<T> c4 = col_args<T>(p, 1, t, t);
       c4.skip = skip;
+      c4.fin_on = 1;
+      c4.fin = FinArgs{part_b, nb3, 2, first ? FIN_CG_ALPHA_FIRST : FIN_CG_ALPHA, 0, 1.0, p->scal, 0.0,
+                       part_a, nb1, invN};
       HIPCHK(p, run_col<T>(p, 1, false, COL_PLAIN, c4, nullptr));
       ColArgs<T> c5 = col_args<T>(p, 0, t, t);
       c5.base = pp;

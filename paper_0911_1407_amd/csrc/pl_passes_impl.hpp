@@ -8,8 +8,10 @@ template <typename T, int N, int V>
 static hipError_t col_launch_n(bool inverse, int op, const ColArgs<T>& a, int nslabs, hipStream_t st,
                                int* nblocks) {
   using S = ColShape<T, N, V>;
+  if (a.fin_on && (op != COL_PLAIN || nslabs != 1)) return hipErrorInvalidValue;
   dim3 grid((a.ncols + S::B - 1) / S::B, nslabs);
   *nblocks = (int)(grid.x * grid.y);
+  grid.x += a.fin_on ? 1 : 0;  // the finalize's workgroup
   if (op == COL_PLAIN) {
     if (inverse)
       hipLaunchKernelGGL((col_kernel<T, N, true, COL_PLAIN, V>), grid, dim3(S::THREADS), 0, st, a);
