@@ -339,12 +339,13 @@ int pl_compare_fields_noalloc(const int32_t n[3], const double* rec, const doubl
 const char* pl_last_error(const pl_plan* plan);
 
 /* FFT schedule autotuner.  For lengths 128, 192, 256 and 512 each column
-   (x, y) pass has four tile variants (0 default: 256 threads, <= 64 KB LDS;
+   (x, y) pass has six tile variants (0 default: 256 threads, <= 64 KB LDS;
    1 wide: 512 threads, <= 128 KB LDS, longer contiguous row segments; 3
    split: the default tile with the stage exchanges passing real and
    imaginary parts through LDS in turn, half the LDS and so more blocks per
-   CU; 4 extra wide: 1024 threads, <= 160 KB LDS) and the row (z) pass two
-   (0, 1).
+   CU; 4 extra wide: 1024 threads, <= 160 KB LDS; 5 wide split: 512 threads,
+   split exchanges in <= 64 KB; 6 extra-wide split: 1024 threads, split
+   exchanges in <= 128 KB) and the row (z) pass two (0, 1).
    The x passes that apply 1/lambda can also read it from the radial shell
    table (when pl_plan_prior_is_radial) or from the per-mode table: the
    shell table saves a streaming read, the per-mode table avoids a
@@ -372,14 +373,14 @@ int pl_plan_autotune(pl_plan* plan, const char* cache_path);
    loads and stores: bit 0 residual r, bit 1 direction p and the operator's
    input, bit 2 iterate x, bit 3 per-mode table, bit 4 Hessian diagonal;
    0..31).
-   Variants: 0 default, 1 wide, 3 split, 4 extra wide for the column passes
-   (x, y), 0 or 1 for the row pass (a length without these variants runs the
+   Variants: 0 default, 1 wide, 3 split, 4 extra wide, 5 wide split, 6
+   extra-wide split for the column passes (x, y), 0 or 1 for the row pass (a length without these variants runs the
    default); a shell-table choice runs the per-mode table when the spectrum
    is not radial. */
 #define PL_NUM_VARIANTS 7
 /* Current choices: out = the PL_NUM_VARIANTS choices for FP64, then FP32. */
 int pl_plan_get_variants(const pl_plan* plan, int32_t out[2 * PL_NUM_VARIANTS]);
-/* Force the choices (same order): column variants 0, 1, 3 or 4, row variant
+/* Force the choices (same order): column variants 0, 1, 3, 4, 5 or 6, row variant
    and tables 0 or 1, streaming policy 0..31 (PL_ERR_INVALID_ARG otherwise). */
 int pl_plan_set_variants(pl_plan* plan, const int32_t v[2 * PL_NUM_VARIANTS]);
 

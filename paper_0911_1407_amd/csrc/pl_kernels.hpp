@@ -196,13 +196,9 @@ struct ColArgs {
   int n;             // transform length
   const cx<T>* in;
   cx<T>* out;
-  int ncols;         // columns (of all slabs when cps > 0)
+  int ncols;         // columns per slab
   long row_stride;   // distance (complex elements) between consecutive transform entries
-  long slab_stride;  // distance between slabs
-  // y passes: columns per slab (kz values); column c is kz = c % cps of
-  // slab kx = c / cps, so tiles run across slab ends and none is ragged.
-  // 0 for x passes, whose columns are flattened (ky, kz) pairs of one slab.
-  int cps;
+  long slab_stride;  // distance between slabs (blockIdx.y)
   const cx<T>* tw;   // twiddles of this length
   // fused x-pass operations (columns are flattened (ky, kz) pairs)
   Grid g;
@@ -255,14 +251,23 @@ constexpr int col_tile(int P, int N, int elem_bytes, int threads, int lds_cap) {
 // the fused x passes loaded after the transform (fewer registers).
 // V = 4 ("extra wide"): 1024 threads and at most 160 KB, one block per CU
 // with the longest row segments (256 bytes of FP32 columns at 512 points).
+// V = 5 ("wide split"): 512 threads, split exchanges in at most 64 KB:
+// the wide tile's row segments (512 bytes of FP64 columns at 256 points)
+// at two blocks per CU.  V = 6 ("extra wide split"): 1024 threads, split
+// exchanges in at most 128 KB (1 KB segments of FP64 at 256 points).
+constexpr int col_threads(int V) { return V == 1 || V == 5 ? 512 : (V == 2 ? 128 : (V == 4 || V == 6 ? 1024 : 256)); }
+constexpr int col_lds_cap(int V) {
+  return V == 1 || V == 6 ? 131072 : (V == 2 ? 32768 : (V == 4 ? 163840 : 65536));
+}
+constexpr bool col_split(int V) { return V == 3 || V == 5 || V == 6; }
+
 template <typename T, int N, int V = 0>
 struct ColShape {
   static constexpr int P = Plan<N>::P;
-  static constexpr int B = col_tile(P, N, (int)sizeof(cx<T>),
-                                    V == 1 ? 512 : (V == 2 ? 128 : (V == 4 ? 1024 : 256)),
-                                    V == 1 ? 131072 : (V == 2 ? 32768 : (V == 4 ? 163840 : 65536)));
+  static constexpr bool SPLIT = col_split(V);
+  // a split exchange holds one real part per element at a time
+  static constexpr int B = col_tile(P, N, (int)sizeof(cx<T>) / (SPLIT ? 2 : 1), col_threads(V), col_lds_cap(V));
   static constexpr int THREADS = B * P;
-  static constexpr bool SPLIT = V == 3;
   static constexpr int LDS = P > 1 ? (SPLIT ? (N * B + 1) / 2 : N * B) : 1;  // complex elements
 };
 
@@ -296,12 +301,7 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
   const int t = active ? (int)threadIdx.x / B : 0;
   const int c = tile * B + cl;
   const bool valid = active && c < a.ncols;
-  int sl = slab, cc = c;
-  if (a.cps > 0 && valid) {
-    sl = c / a.cps;
-    cc = c - sl * a.cps;
-  }
-  const long base_off = (long)sl * a.slab_stride + (valid ? cc : 0);
+  const long base_off = (long)slab * a.slab_stride + (valid ? c : 0);
   // the fused operations run on x passes: the column fixes (ky, kz), the
   // transform position is kx, and an element's mode index is its offset
   const int col_ky = c / a.g.h, col_kz = c % a.g.h;
@@ -525,23 +525,36 @@ template <typename T, int N, bool INV, int OP, int V>
 __global__ void __launch_bounds__((ColShape<T, N, V>::THREADS)) col_kernel(ColArgs<T> a) {
   __shared__ cx<T> lds_all[ColShape<T, N, V>::LDS];
   if (a.skip && *a.skip != 0.0) return;  // Krylov iteration after convergence
-  int gx = gridDim.x;
-  int hw = blockIdx.x + gridDim.x * blockIdx.y;
+  int gx = gridDim.x, gy = gridDim.y;
+  const int hw = blockIdx.x + gridDim.x * blockIdx.y;
   if constexpr (OP == COL_PLAIN) {
-    if (a.fin_on) {  // (launched with one row of tiles: gridDim.y == 1)
-      // the last workgroup runs the finalize riding on this launch (it only
-      // reads partials of earlier launches); the tiles keep their hardware
-      // ids, so the XCD mapping below holds
-      --gx;
-      if (hw == gx) {
-        const FinArgs& f = a.fin;
-        finalize_body<ColShape<T, N, V>::THREADS>(f.partials, f.nb, f.K, f.kind, f.dst, f.scale, f.scal, f.aux,
-                                                  f.partials2, f.nb2, f.scale2);
+    if (a.fin_on) {
+      // the workgroups past the tiles (one more column of the grid, or one
+      // more row when there are several slabs) hold the finalize riding on
+      // this launch (it only reads partials of earlier launches); its first
+      // one runs it.  The tiles keep their hardware ids, so the XCD mapping
+      // below holds.
+      bool rider, lead;
+      if (gy > 1) {
+        --gy;
+        rider = (int)blockIdx.y == gy;
+        lead = blockIdx.x == 0;
+      } else {
+        --gx;
+        rider = hw == gx;
+        lead = true;
+      }
+      if (rider) {
+        if (lead) {
+          const FinArgs& f = a.fin;
+          finalize_body<ColShape<T, N, V>::THREADS>(f.partials, f.nb, f.K, f.kind, f.dst, f.scale, f.scal, f.aux,
+                                                    f.partials2, f.nb2, f.scale2);
+        }
         return;
       }
     }
   }
-  const int total = gx * gridDim.y;
+  const int total = gx * gy;
   // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
   // L2).  Give every XCD a contiguous range of (tile, slab) work items so
   // that neighbouring column tiles, whose row segments share cache lines

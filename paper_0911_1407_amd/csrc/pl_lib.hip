@@ -43,7 +43,7 @@ static_assert(V_COUNT == PL_NUM_VARIANTS, "schedule slots");
 // tile.)
 bool variant_allowed(int slot, int v) {
   switch (slot) {
-    case V_XCG: case V_Y: case V_XOP: return v == 0 || v == 1 || v == 3 || v == 4;
+    case V_XCG: case V_Y: case V_XOP: return v >= 0 && v <= 6 && v != 2;
     case V_NT: return v >= 0 && v <= 31;
     default: return v == 0 || v == 1;
   }
@@ -238,12 +238,10 @@ ColArgs<T> col_args(pl_plan* p, int axis, const cx<T>* in, cx<T>* out) {
     a.ncols = (int)(p->n[1] * h);
     a.row_stride = (long)p->n[1] * h;
     a.slab_stride = 0;
-    a.cps = 0;
-  } else {  // y: columns = (kx, kz) pairs, kz fastest
-    a.ncols = (int)(p->n[0] * h);
+  } else {  // y: slabs = kx, columns = kz
+    a.ncols = (int)h;
     a.row_stride = h;
     a.slab_stride = (long)p->n[1] * h;
-    a.cps = (int)h;
   }
   return a;
 }
@@ -254,11 +252,12 @@ hipError_t run_col(pl_plan* p, int axis, bool inverse, int op, const ColArgs<T>&
   const int pi = sizeof(T) == 4 ? 1 : 0;
   const bool krylov = op == COL_CG_FIRST || op == COL_CG_LAST || op == COL_CG_INIT;
   const int v = axis == 1 ? p->var[pi][V_Y] : p->var[pi][krylov ? V_XCG : V_XOP];
-  if (op == COL_PLAIN) return launch_col<T>(p->n[axis], inverse, op, a, 1, p->stream, nb ? nb : &dummy, v);
+  const int nslabs = axis == 0 ? 1 : p->n[0];
+  if (op == COL_PLAIN) return launch_col<T>(p->n[axis], inverse, op, a, nslabs, p->stream, nb ? nb : &dummy, v);
   ColArgs<T> b = a;  // the 1/lambda table this pass reads
   b.radial = p->radial && p->var[pi][krylov ? V_TAB_CG : V_TAB_OP];
   b.inv_lam = View<T>::tab(p, b.radial);
-  return launch_col<T>(p->n[axis], inverse, op, b, 1, p->stream, nb ? nb : &dummy, v);
+  return launch_col<T>(p->n[axis], inverse, op, b, nslabs, p->stream, nb ? nb : &dummy, v);
 }
 
 template <typename T>
@@ -1739,9 +1738,9 @@ int tune_precision(pl_plan* p, const std::string& key, std::vector<std::string>&
       }
     }
   }
-  // column passes: default, wide, split and extra-wide tiles (lengths
-  // 128-512); rows: default and wide
-  const int mx = has_wide_variant(p->n[0]) ? 4 : 0, my = has_wide_variant(p->n[1]) ? 4 : 0,
+  // column passes: default, wide, split, extra-wide, wide split and
+  // extra-wide split tiles (lengths 128-512); rows: default and wide
+  const int mx = has_wide_variant(p->n[0]) ? 6 : 0, my = has_wide_variant(p->n[1]) ? 6 : 0,
             mr = has_wide_variant(p->n[2]) ? 1 : 0, mt = p->radial ? 1 : 0;
   const int reps = p->N >= (1L << 24) ? 5 : 20;
   // the solver's CG step: first the tile variants of the x passes carrying
@@ -1884,11 +1883,12 @@ void col_work(const std::vector<pl_plan*>& plans, int axis, const std::vector<in
     const pl_plan* p = plans[i];
     const BatchShape<T> sh = batch_shape<T>(p->n[axis], var[i]);
     const int h = p->g.h;
-    // y columns run across the kx slabs (ColArgs::cps), as x columns across ky
-    const int ncols = (axis == 0 ? p->n[1] : p->n[0]) * h;
+    const int ncols = axis == 0 ? p->n[1] * h : h;
+    const int nslabs = axis == 0 ? 1 : p->n[0];
     const int nbx = (ncols + sh.B - 1) / sh.B;
-    for (int t = 0; t < nbx; ++t) w.items.push_back(make_int4((int)i, t, 0, t));
-    w.nb[i] = nbx;
+    for (int sl = 0; sl < nslabs; ++sl)
+      for (int t = 0; t < nbx; ++t) w.items.push_back(make_int4((int)i, t, sl, t + nbx * sl));
+    w.nb[i] = nbx * nslabs;
     w.threads = std::max(w.threads, sh.col_threads);
     w.lds = std::max(w.lds, sh.col_lds);
   }

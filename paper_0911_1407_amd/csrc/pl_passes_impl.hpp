@@ -8,10 +8,15 @@ template <typename T, int N, int V>
 static hipError_t col_launch_n(bool inverse, int op, const ColArgs<T>& a, int nslabs, hipStream_t st,
                                int* nblocks) {
   using S = ColShape<T, N, V>;
-  if (a.fin_on && (op != COL_PLAIN || nslabs != 1)) return hipErrorInvalidValue;
+  if (a.fin_on && op != COL_PLAIN) return hipErrorInvalidValue;
   dim3 grid((a.ncols + S::B - 1) / S::B, nslabs);
   *nblocks = (int)(grid.x * grid.y);
-  grid.x += a.fin_on ? 1 : 0;  // the finalize's workgroup
+  if (a.fin_on) {  // the finalize's workgroup(s), after the tiles
+    if (nslabs > 1)
+      grid.y += 1;
+    else
+      grid.x += 1;
+  }
   if (op == COL_PLAIN) {
     if (inverse)
       hipLaunchKernelGGL((col_kernel<T, N, true, COL_PLAIN, V>), grid, dim3(S::THREADS), 0, st, a);
@@ -78,6 +83,24 @@ hipError_t launch_col<PL_T>(int N, bool inverse, int op, const ColArgs<PL_T>& a,
     switch (N) {
 #define PL_CASE(NN) \
   case NN: return col_launch_n<PL_T, NN, 4>(inverse, op, a, nslabs, st, nblocks);
+      PL_WIDE_LENGTHS(PL_CASE)
+#undef PL_CASE
+      default: break;
+    }
+  }
+  if (variant == 5) {
+    switch (N) {
+#define PL_CASE(NN) \
+  case NN: return col_launch_n<PL_T, NN, 5>(inverse, op, a, nslabs, st, nblocks);
+      PL_WIDE_LENGTHS(PL_CASE)
+#undef PL_CASE
+      default: break;
+    }
+  }
+  if (variant == 6) {
+    switch (N) {
+#define PL_CASE(NN) \
+  case NN: return col_launch_n<PL_T, NN, 6>(inverse, op, a, nslabs, st, nblocks);
       PL_WIDE_LENGTHS(PL_CASE)
 #undef PL_CASE
       default: break;

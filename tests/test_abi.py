@@ -54,13 +54,13 @@ def test_every_pass_variant_is_instantiated():
     from paper_0911_1407_amd import binding
     col_ops = [("true", 0), ("false", 0), ("false", 1), ("false", 2), ("true", 3), ("false", 4), ("true", 5)]
     for n in binding.SUPPORTED_LENGTHS:
-        variants = (0, 1, 3, 4) if n in (128, 192, 256, 512) else (0,)
+        variants = (0, 1, 3, 4, 5, 6) if n in (128, 192, 256, 512) else (0,)
         for T in ("double", "float"):
             for v in variants:
                 for inv, op in col_ops:
                     assert f"col_kernel<{T}, {n}, {inv}, {op}, {v}>" in syms, (T, n, inv, op, v)
-                if v in (3, 4):
-                    continue  # the split and extra-wide variants are column-pass tiles
+                if v >= 3:
+                    continue  # variants 3-6 are column-pass tiles only
                 for op in ((0, 1, 2, 3, 4, 5) if T == "double" else (0, 1, 2, 4)):
                     assert f"row_kernel<{T}, {n}, {op}, {v}>" in syms, (T, n, op, v)
     for T in ("double", "float"):
