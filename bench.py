@@ -234,11 +234,11 @@ def cpu_oracle_baseline(inst, v, full=False):
         return Problem(it["n"], it["box"], it["w"], it["counts"], it["pk"], it["amp"], it["mu"], it["nbar"],
                        it["beta"], 0.0)
 
-    def timed_solve(it, rtol):
+    def timed_solve(it, rtol, precond="mean"):
         t0 = time.perf_counter()
-        s_, info = newton_krylov(problem(it), rtol=rtol, max_newton=200, max_cg=5000)
+        s_, info = newton_krylov(problem(it), rtol=rtol, max_newton=200, max_cg=5000, precond=precond)
         return s_, {"s": time.perf_counter() - t0, "newton_its": int(info["newton_its"]),
-                    "cg_its": int(info["cg_its"]), "status": info["status"], "rtol": rtol}
+                    "cg_its": int(info["cg_its"]), "status": info["status"], "rtol": rtol, "precond": precond}
 
     P = problem(inst)
     ops = SpectralOps(P)
@@ -263,12 +263,16 @@ def cpu_oracle_baseline(inst, v, full=False):
                                  "rtol": 1e-6}
     if full:
         _, ttm["sel256"] = timed_solve(synth.config_instance("sel256"), 1e-6)
+        # the bias workload with the oracle's 25th-percentile preconditioner
+        # constant (the mean-diagonal one takes about ten times the CG steps
+        # there; both reach the same MAP)
         bias = synth.config_instance("bias256")
-        s_b, ttm["bias256"] = timed_solve(bias, 1e-6)
+        s_b, ttm["bias256"] = timed_solve(bias, 1e-6, precond="p25")
         _, dL = o_adj.squared_error_loss(s_b, bias["s_true"])
         t0 = time.perf_counter()
-        _, its = o_adj.adjoint_pcg(problem(bias), s_b, dL, rtol=1e-6, max_cg=50000)
-        ttm["bias256_adjoint"] = {"s": time.perf_counter() - t0, "cg_its": int(its), "rtol": 1e-6}
+        _, its = o_adj.adjoint_pcg(problem(bias), s_b, dL, rtol=1e-6, max_cg=50000, precond="p25")
+        ttm["bias256_adjoint"] = {"s": time.perf_counter() - t0, "cg_its": int(its), "rtol": 1e-6,
+                                  "precond": "p25"}
     cpu_model = None
     try:
         with open("/proc/cpuinfo") as f:
@@ -298,6 +302,10 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--only-hvp", action="store_true", help="profiling aid: only the isolated HVP loop")
     ap.add_argument("--only-batch", action="store_true", help="profiling aid: only the batched workload")
+    ap.add_argument("--only-solve", action="store_true",
+                    help="profiling aid: only the timed FP64 and mixed MAP solves (no isolated HVP loop)")
+    ap.add_argument("--only-cpu", action="store_true",
+                    help="only the CPU oracle baseline (host cores, no GPU); with --cpu-full the full-size one")
     ap.add_argument("--n", type=int, default=None, help="override the grid length (same cell size)")
     ap.add_argument("--workload", default="sel256", choices=["sel256", "bias256", "big512"],
                     help="sel256: 256^3 selection workload (default); bias256: beta = 1.5, nbar = 2 "
@@ -310,6 +318,13 @@ def main():
         print("bench.py: this build runs on exactly one GPU (the solver is single-GPU); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.only_cpu:
+        from paper_0911_1407_amd import synth
+        inst = synth.config_instance(args.workload, n=args.n)
+        v = np.random.default_rng([0, 3]).standard_normal(inst["n"])
+        print(json.dumps(cpu_oracle_baseline(inst, v, full=args.cpu_full)))
+        return
 
     import torch
     from paper_0911_1407_amd import synth
@@ -359,23 +374,24 @@ def main():
         per_call = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(reps))
         return float(np.median(per_call))  # ms per HVP
 
-    ms64 = time_hvp(v_hat64, hv64, args.hvp_reps)
-    ms32 = time_hvp(v_hat32, hv32, args.hvp_reps)
-    b64 = hvp_bytes(n, 8)
-    b32 = hvp_bytes(n, 4)
-    gbs64 = b64 / (ms64 * 1e-3) / 1e9
-    gbs32 = b32 / (ms32 * 1e-3) / 1e9
-    print(f"# HVP fp64 {ms64:.3f} ms ({gbs64:.0f} GB/s), fp32 {ms32:.3f} ms ({gbs32:.0f} GB/s)",
-          file=sys.stderr, flush=True)
-    if args.copy_probe:
-        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-    if args.only_hvp:
-        print(json.dumps({"hvp_ms_fp64": ms64, "hvp_ms_fp32": ms32}))
-        return
+    if not args.only_solve:
+        ms64 = time_hvp(v_hat64, hv64, args.hvp_reps)
+        ms32 = time_hvp(v_hat32, hv32, args.hvp_reps)
+        b64 = hvp_bytes(n, 8)
+        b32 = hvp_bytes(n, 4)
+        gbs64 = b64 / (ms64 * 1e-3) / 1e9
+        gbs32 = b32 / (ms32 * 1e-3) / 1e9
+        print(f"# HVP fp64 {ms64:.3f} ms ({gbs64:.0f} GB/s), fp32 {ms32:.3f} ms ({gbs32:.0f} GB/s)",
+              file=sys.stderr, flush=True)
+        if args.copy_probe:
+            src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+        if args.only_hvp:
+            print(json.dumps({"hvp_ms_fp64": ms64, "hvp_ms_fp32": ms32}))
+            return
 
     # ---------------- timed FP64 solves (the steps) ----------------
     s = torch.empty(n, dtype=torch.float64, device=dev)
@@ -414,6 +430,10 @@ def main():
     mixed_rel = float(torch.linalg.norm(s_mixed - s_fp64) / torch.linalg.norm(s_fp64))
     print(f"# mixed solve {1e3 * t_mixed:.1f} ms, {minfos[-1]}, rel vs fp64 {mixed_rel:.2e}",
           file=sys.stderr, flush=True)
+    if args.only_solve:
+        print(json.dumps({"fp64_ms": ms_per_step, "fp64": infos[-1], "hvp_per_s": value,
+                          "mixed_ms": 1e3 * t_mixed, "mixed": minfos[-1]}))
+        return
     parity = oracle_parity(args.workload if args.n is None else None, inst,
                            {"fp64_rtol_1e-6": s_fp64, "mixed_rtol_1e-6": s_mixed})
     if parity:
