@@ -346,10 +346,12 @@ const char* pl_last_error(const pl_plan* plan);
    CU; 4 extra wide: 1024 threads, <= 160 KB LDS; 5 wide split: 512 threads,
    split exchanges in <= 64 KB; 6 extra-wide split: 1024 threads, split
    exchanges in <= 128 KB) and the row (z) pass two (0, 1).
-   The x passes that apply 1/lambda can also read it from the radial shell
-   table (when pl_plan_prior_is_radial) or from the per-mode table: the
-   shell table saves a streaming read, the per-mode table avoids a
-   scattered lookup.  Operands that a pass reads once (Krylov vectors, the
+   The x passes that apply 1/lambda read it from the per-mode table (0),
+   or, when pl_plan_prior_is_radial, from the radial shell table (1) or
+   from the per-mode table at (min(kx, nx - kx), ky, kz) (2, "mirror"): the
+   shell table saves a streaming read at the cost of a scattered lookup; the
+   mirror reads each entry for the two modes kx and nx - kx of one column,
+   so half the per-mode table streams.  Operands that a pass reads once (Krylov vectors, the
    Hessian diagonal, the per-mode table) can be loaded, and the Krylov
    vectors stored, non-temporally so that the pass-to-pass intermediate
    stays in the memory-side cache, which pays when that intermediate fits
@@ -368,20 +370,21 @@ int pl_plan_autotune(pl_plan* plan, const char* cache_path);
 
 /* Number of schedule choices per precision.  In order: x variant of the
    Krylov-carrying passes, y variant, z variant, x variant of the operator's
-   passes, table of the Krylov passes (1 shell, 0 per mode), table of the
-   operator's passes, streaming policy (one bit per array, covering its
+   passes, table of the Krylov passes (0 per mode, 1 shell, 2 mirrored per
+   mode), table of the operator's passes, streaming policy (one bit per array, covering its
    loads and stores: bit 0 residual r, bit 1 direction p and the operator's
    input, bit 2 iterate x, bit 3 per-mode table, bit 4 Hessian diagonal;
    0..31).
    Variants: 0 default, 1 wide, 3 split, 4 extra wide, 5 wide split, 6
    extra-wide split for the column passes (x, y), 0 or 1 for the row pass (a length without these variants runs the
-   default); a shell-table choice runs the per-mode table when the spectrum
-   is not radial. */
+   default); a shell or mirror choice runs the per-mode table when the
+   spectrum is not radial. */
 #define PL_NUM_VARIANTS 7
 /* Current choices: out = the PL_NUM_VARIANTS choices for FP64, then FP32. */
 int pl_plan_get_variants(const pl_plan* plan, int32_t out[2 * PL_NUM_VARIANTS]);
-/* Force the choices (same order): column variants 0, 1, 3, 4, 5 or 6, row variant
-   and tables 0 or 1, streaming policy 0..31 (PL_ERR_INVALID_ARG otherwise). */
+/* Force the choices (same order): column variants 0, 1, 3, 4, 5 or 6, row
+   variant 0 or 1, tables 0, 1 or 2, streaming policy 0..31
+   (PL_ERR_INVALID_ARG otherwise). */
 int pl_plan_set_variants(pl_plan* plan, const int32_t v[2 * PL_NUM_VARIANTS]);
 
 /* ---------------------------------------------------------------------------

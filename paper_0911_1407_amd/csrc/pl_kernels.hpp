@@ -105,14 +105,27 @@ struct Grid {
 
 __device__ __forceinline__ int fold(int m, int n) { return m >= (n >> 1) ? m - n : m; }
 
-// 1/lambda_k (section 2.3: S_L^-1 is diagonal in Fourier space).  radial:
-// table indexed by mx^2 + my^2 + mz^2 (cubic box); else one entry per mode.
+// Ways to look up 1/lambda_k (inv_lam_at).
+enum TabKind {
+  TAB_MODE = 0,    // per-mode table [nx][ny][h], entry `mode`
+  TAB_SHELL = 1,   // radial shell table indexed by mx^2 + my^2 + mz^2 (cubic box)
+  TAB_MIRROR = 2,  // per-mode table read at (min(kx, nx - kx), ky, kz): for a
+                   // spectrum even in kx (a radial one), whose entries at kx
+                   // and nx - kx agree; an x pass then reads each table entry
+                   // for two modes of one column, and the upper half never
+};
+
+// 1/lambda_k (section 2.3: S_L^-1 is diagonal in Fourier space).
 template <typename TT>
-__device__ __forceinline__ TT inv_lam_at(const TT* __restrict__ tab, int radial, const Grid& g,
+__device__ __forceinline__ TT inv_lam_at(const TT* __restrict__ tab, int kind, const Grid& g,
                                          int kx, int ky, int kz, long mode, int nt = 0) {
-  if (radial) {
+  if (kind == TAB_SHELL) {
     int fx = fold(kx, g.nx), fy = fold(ky, g.ny);
     return tab[fx * fx + fy * fy + kz * kz];
+  }
+  if (kind == TAB_MIRROR) {
+    const int mx = 2 * kx > g.nx ? g.nx - kx : kx;
+    return ld_stream(tab + ((long)mx * g.nyh + mode - (long)kx * g.nyh), nt);
   }
   return ld_stream(tab + mode, nt);
 }
@@ -203,7 +216,7 @@ struct ColArgs {
   // fused x-pass operations (columns are flattened (ky, kz) pairs)
   Grid g;
   const T* inv_lam;  // 1/lambda table (see inv_lam_at)
-  int radial;
+  int radial;        // its TabKind
   const cx<T>* base;  // COL_ADDPRIOR: vector added through the prior
   double k0_shift;    // subtracted from mode 0 before the prior multiply
   T out_scale;        // COL_ADDPRIOR: scale of the transformed input

@@ -45,6 +45,7 @@ bool variant_allowed(int slot, int v) {
   switch (slot) {
     case V_XCG: case V_Y: case V_XOP: return v >= 0 && v <= 6 && v != 2;
     case V_NT: return v >= 0 && v <= 31;
+    case V_TAB_CG: case V_TAB_OP: return v >= 0 && v <= 2;
     default: return v == 0 || v == 1;
   }
 }
@@ -254,9 +255,9 @@ hipError_t run_col(pl_plan* p, int axis, bool inverse, int op, const ColArgs<T>&
   const int v = axis == 1 ? p->var[pi][V_Y] : p->var[pi][krylov ? V_XCG : V_XOP];
   const int nslabs = axis == 0 ? 1 : p->n[0];
   if (op == COL_PLAIN) return launch_col<T>(p->n[axis], inverse, op, a, nslabs, p->stream, nb ? nb : &dummy, v);
-  ColArgs<T> b = a;  // the 1/lambda table this pass reads
-  b.radial = p->radial && p->var[pi][krylov ? V_TAB_CG : V_TAB_OP];
-  b.inv_lam = View<T>::tab(p, b.radial);
+  ColArgs<T> b = a;  // the 1/lambda table this pass reads (TabKind)
+  b.radial = p->radial ? p->var[pi][krylov ? V_TAB_CG : V_TAB_OP] : TAB_MODE;
+  b.inv_lam = View<T>::tab(p, b.radial == TAB_SHELL);
   return launch_col<T>(p->n[axis], inverse, op, b, nslabs, p->stream, nb ? nb : &dummy, v);
 }
 
@@ -1741,7 +1742,7 @@ int tune_precision(pl_plan* p, const std::string& key, std::vector<std::string>&
   // column passes: default, wide, split, extra-wide, wide split and
   // extra-wide split tiles (lengths 128-512); rows: default and wide
   const int mx = has_wide_variant(p->n[0]) ? 6 : 0, my = has_wide_variant(p->n[1]) ? 6 : 0,
-            mr = has_wide_variant(p->n[2]) ? 1 : 0, mt = p->radial ? 1 : 0;
+            mr = has_wide_variant(p->n[2]) ? 1 : 0, mt = p->radial ? 2 : 0;
   const int reps = p->N >= (1L << 24) ? 5 : 20;
   // the solver's CG step: first the tile variants of the x passes carrying
   // the Krylov updates, y and z and the table those x passes read (default
@@ -2972,7 +2973,8 @@ int lb_precond(pl_plan* p, int model) {
 // Host-driven, two scalar read-backs per iteration.
 int lb_pcg(pl_plan* p, int model, const double* bk, double tol_abs, int max_cg, int* its_out, int* hv_out) {
   cx<double>*x = p->x64, *r = p->r64, *pp = p->p64, *q = p->t64;
-  const int radial = p->radial && p->var[0][V_TAB_CG];  // the table the fused pass reads
+  // the table the fused pass reads (its mirrored form reads the per-mode one)
+  const int radial = p->radial && p->var[0][V_TAB_CG] == TAB_SHELL;
   const double* tab = View<double>::tab(p, radial);
   const double invN = 1.0 / (double)p->N;
   const int nb = grid_blocks(p->Nh);
