@@ -150,12 +150,18 @@ enum Scal {
   SC_GG = 11, SC_PRIOR = 12, SC_LIK = 13, SC_DSUM = 14,
   SC_INACTIVE = 15,  // batched solves: instance finished, every pass skips it
   SC_LS_B = 16, SC_LS_C = 17, SC_LS_SLOPE = 18,
+  SC_RZ_ODD = 19,  // r^H M^-1 r after an odd number of CG iterations (cg_rz_slot)
   SC_DF = 20,     // 4 slots
   SC_LS_ALPHA = 24,  // step the device-side Armijo test accepted (-1: none)
   SC_ADJ = 26,    // adjoint sums (4 slots)
   SC_LB_DQ = 30,  // linear-bias Krylov step: sum of phi'' B u q^2 (the diagonal part of p^H H p)
   SC_COUNT = 32
 };
+
+// The single-plan CG keeps r^H M^-1 r after k completed iterations in
+// slot cg_rz_slot(k): the first pass of iteration k reads slot k - 1 to form
+// beta while one of its workgroups stores slot k.
+__host__ __device__ constexpr int cg_rz_slot(int k) { return (k & 1) ? SC_RZ_ODD : SC_RZ; }
 
 // Inverse of the preconditioner M_k = 1/lambda_k + dbar (dbar a constant
 // taken from the Hessian diagonal d), in the Krylov vectors' precision:
@@ -203,6 +209,8 @@ template <int NT>
 __device__ __forceinline__ void finalize_body(const double* __restrict__ partials, int nb, int K, int kind, int dst,
                                               double scale, double* __restrict__ scal, double aux,
                                               const double* __restrict__ partials2, int nb2, double scale2);
+template <int NT, int K>
+__device__ __forceinline__ void fin_sums(const double* __restrict__ src, int n, double* out);
 
 template <typename T>
 struct ColArgs {
@@ -234,6 +242,18 @@ struct ColArgs {
   const cx<double>* cg_rhs;
   double cg_rhs_sign;
   int variant;  // batched launches: this instance's tile variant (0 or 2)
+  // COL_CG_FIRST with beta_part set: the pass itself closes iteration
+  // cg_k - 1 from that iteration's last-pass partials (beta_nb blocks of
+  // (r^H r, r^H M^-1 r), times beta_scale): every workgroup sums them in the
+  // same order, so all take the same beta and the same convergence
+  // decision, and workgroup 0 stores the bookkeeping (SC_ITS = cg_k, SC_RR,
+  // cg_rz_slot(cg_k), SC_BETA, SC_DONE when r^H r <= SC_TOL2 or cg_k >=
+  // cg_max), in place of a finalize launch of its own
+  const double* beta_part;
+  int beta_nb;
+  double beta_scale;
+  int cg_k;
+  double cg_max;
   // COL_PLAIN launches with fin_on = 1 carry one extra workgroup that runs
   // the finalize `fin` (saving a launch of its own); the host adds it to the
   // grid
@@ -358,6 +378,24 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
           v[q * R0 + r] = pn;
         }
     } else {
+      double beta_k = beta;
+      if (a.beta_part) {
+        double v2[2];
+        fin_sums<ColShape<T, N, V>::THREADS, 2>(a.beta_part, a.beta_nb, v2);
+        const double rr = v2[0] * a.beta_scale, rz = v2[1] * a.beta_scale;
+        const double rzo = a.scal[cg_rz_slot(a.cg_k - 1)];
+        beta_k = rzo > 0.0 ? rz / rzo : 0.0;
+        const bool done = rr <= a.scal[SC_TOL2] || (double)a.cg_k >= a.cg_max;
+        if (block_linear == 0 && threadIdx.x == 0) {
+          double* sc = const_cast<double*>(a.scal);
+          sc[SC_ITS] = (double)a.cg_k;
+          sc[SC_RR] = rr;
+          sc[cg_rz_slot(a.cg_k)] = rz;
+          sc[SC_BETA] = beta_k;
+          if (done) sc[SC_DONE] = 1.0;
+        }
+        if (done) return;  // the whole workgroup (every one decides alike)
+      }
 #pragma unroll
       for (int q = 0; q < W / R0; ++q)
 #pragma unroll
@@ -369,7 +407,7 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
             cx<T> po = ld_stream(pio + idx, a.nt & NT_P), rv = ld_stream(a.cg_r + idx, a.nt & NT_R);
             long mode = base_off + (long)e * a.row_stride;
             const T il = inv_lam_at(a.inv_lam, a.radial, a.g, kx, ky, kz, mode, a.nt & NT_TAB);
-            const T mi = precond_inv<T>(il, dbar), bt = (T)beta;
+            const T mi = precond_inv<T>(il, dbar), bt = (T)beta_k;
             pn = {mi * rv.x + bt * po.x, mi * rv.y + bt * po.y};
             st_stream(pio + idx, pn, a.nt & NT_P);
             acc[0] += hw * (double)(il * (pn.x * pn.x + pn.y * pn.y));
@@ -599,7 +637,10 @@ enum RowOp {
   ROW_C2R_GRADLIK = 5,  // half -> real: scale * x + beta (nbar w e^{beta s} - N);
                         // writes d; partials sum(e - beta N s)
   ROW_LB_IN = 6,        // half -> real q (stored to out_r), times d, -> half
-  ROW_LB_OUT = 7        // half -> real g, d g + lb_d1 lb_q, -> half (double only)
+  ROW_LB_OUT = 7,       // half -> real g, d g + lb_d1 lb_q, -> half (double only)
+  ROW_GRAD_STEP = 8     // ROW_GRAD after a step: s = s_in + alpha v in real space
+                        // (alpha = scal[SC_LS_ALPHA], none if <= 0) instead of
+                        // the inverse transform of s_hat (double only)
 };
 
 template <typename T>
@@ -629,7 +670,37 @@ struct RowArgs {
   const double* lb_d1;  // ROW_LB_OUT: the curvature diagonal and the kept field q
   const double* lb_q;
   int variant;  // batched launches: this instance's tile variant (0 or 2)
+  const double* scal;  // ROW_GRAD_STEP: device scalars (the step length)
 };
+
+// The likelihood terms of the gradient at one cell (sections 2.1 and 2.4,
+// the power-law bias; the Gaussian-prior model of section 2.2.2): writes s,
+// e and the Hessian diagonal d, adds to the partial sums (the likelihood
+// part of f, sum d) and returns the likelihood gradient l.
+template <typename T>
+__device__ __forceinline__ double grad_cell(const RowArgs<T>& a, long i, double s, double* acc) {
+  const double cnt = a.counts[i];
+  a.s_out[i] = s;
+  if (a.model == MODEL_GAUSSIAN) {
+    // Gaussian prior on delta = s, unity bias:
+    // -ln L = sum nbar w (1 + delta) - N ln(1 + delta) + const
+    const double nw = a.nbar * a.w[i], op = 1.0 + s;
+    const double inv = cnt > 0.0 ? 1.0 / op : 0.0;
+    const double dd = cnt * inv * inv;
+    a.e_out[i] = op;
+    a.d_out[i] = dd;
+    acc[0] += nw * s - (cnt > 0.0 ? cnt * log1p(s) : 0.0);
+    acc[1] += dd;
+    return nw - cnt * inv;
+  }
+  const double ex = a.nbar * a.w[i] * exp(a.beta * s);
+  a.e_out[i] = ex;
+  const double dd = a.beta * a.beta * ex;
+  a.d_out[i] = dd;
+  acc[0] += ex - a.beta * cnt * s;
+  acc[1] += dd;
+  return a.beta * (ex - cnt);
+}
 
 template <int N, int V = 0>
 struct RowShape {
@@ -662,9 +733,29 @@ __device__ __forceinline__ void row_body(const RowArgs<T>& a, int ublock, cx<T>*
   const long rowA = 2L * uc, rowB = 2L * uc + 1;
 
   cx<T> v[W];
+  double acc[2] = {0.0, 0.0};
 
   // ---- gather the complex length-N input Z = A + i B (stage-0 slots) ----
-  if constexpr (OP == ROW_R2C) {
+  if constexpr (OP == ROW_GRAD_STEP) {
+    // real rows of the stepped iterate: the likelihood gradient l at each
+    // cell is this transform's input
+    const double al = a.scal[SC_LS_ALPHA] > 0.0 ? a.scal[SC_LS_ALPHA] : 0.0;
+#pragma unroll
+    for (int q = 0; q < W / R0; ++q)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        const int e = in_pos<PL, 0>(t, q, r);
+        double l[2] = {0.0, 0.0};
+        if (valid) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const long i = (h ? rowB : rowA) * N + e;
+            l[h] = grad_cell(a, i, a.s_in[i] + al * (double)a.v[i], acc);
+          }
+        }
+        v[q * R0 + r] = {(T)l[0], (T)l[1]};
+      }
+  } else if constexpr (OP == ROW_R2C) {
 #pragma unroll
     for (int q = 0; q < W / R0; ++q)
 #pragma unroll
@@ -698,8 +789,6 @@ __device__ __forceinline__ void row_body(const RowArgs<T>& a, int ublock, cx<T>*
       }
   }
 
-  double acc[2] = {0.0, 0.0};
-
   // ROW_HVP / ROW_LB_IN: the diagonal at the positions this thread
   // multiplies, loaded before the transforms so that its latency overlaps them
   constexpr bool PRE_D = OP == ROW_HVP || OP == ROW_LB_IN;
@@ -720,7 +809,7 @@ __device__ __forceinline__ void row_body(const RowArgs<T>& a, int ublock, cx<T>*
       }
   }
 
-  if constexpr (OP == ROW_R2C) {
+  if constexpr (OP == ROW_R2C || OP == ROW_GRAD_STEP) {
     fft_thread<PL, false, MAP>(v, t, lds, a.tw, active);
   } else {
     fft_thread<PL, true, MAP>(v, t, lds, a.tw, active);
@@ -838,29 +927,7 @@ __device__ __forceinline__ void row_body(const RowArgs<T>& a, int ublock, cx<T>*
 #pragma unroll
               for (int h = 0; h < 2; ++h) {
                 long i = (h ? rowB : rowA) * N + e;
-                double s = (double)(h ? z.y : z.x) * (double)a.scale;
-                double cnt = a.counts[i];
-                a.s_out[i] = s;
-                if (a.model == MODEL_GAUSSIAN) {
-                  // Gaussian prior on delta = s, unity bias (section 2.2.2):
-                  // -ln L = sum nbar w (1 + delta) - N ln(1 + delta) + const
-                  const double nw = a.nbar * a.w[i], op = 1.0 + s;
-                  const double inv = cnt > 0.0 ? 1.0 / op : 0.0;
-                  const double dd = cnt * inv * inv;
-                  a.e_out[i] = op;
-                  a.d_out[i] = dd;
-                  acc[0] += nw * s - (cnt > 0.0 ? cnt * log1p(s) : 0.0);
-                  acc[1] += dd;
-                  l[h] = nw - cnt * inv;
-                } else {
-                  double ex = a.nbar * a.w[i] * exp(a.beta * s);
-                  a.e_out[i] = ex;
-                  double dd = a.beta * a.beta * ex;
-                  a.d_out[i] = dd;
-                  acc[0] += ex - a.beta * cnt * s;
-                  acc[1] += dd;
-                  l[h] = a.beta * (ex - cnt);
-                }
+                l[h] = grad_cell(a, i, (double)(h ? z.y : z.x) * (double)a.scale, acc);
               }
             }
             v[q * RL + m] = {(T)l[0], (T)l[1]};
@@ -905,7 +972,7 @@ __device__ __forceinline__ void row_body(const RowArgs<T>& a, int ublock, cx<T>*
       }
     }
   }
-  if constexpr (OP == ROW_GRAD || OP == ROW_HVP || OP == ROW_LB_IN)
+  if constexpr (OP == ROW_GRAD || OP == ROW_GRAD_STEP || OP == ROW_HVP || OP == ROW_LB_IN)
     block_reduce_store<2>(acc, a.partials, block_linear);
 }
 
@@ -970,7 +1037,7 @@ __global__ void __launch_bounds__(RED_THREADS) cg_init_kernel(const cx<double>* 
 }
 
 enum FinKind { FIN_STORE = 0, FIN_CG_INIT = 1, FIN_CG_ALPHA = 2, FIN_CG_BETA = 3, FIN_DBAR = 4, FIN_CG_ALPHA_ADD = 5,
-               FIN_CG_ALPHA_FIRST = 6 };
+               FIN_CG_ALPHA_FIRST = 6, FIN_CG_BETA_K = 7 };
 
 // Sum partials[nb][K] in a fixed order; then scalar bookkeeping.
 // kind FIN_CG_ALPHA: p^H H p = scale2 * sum(partials2[nb2]) (prior part from
@@ -1056,8 +1123,9 @@ __device__ __forceinline__ void finalize_body(const double* __restrict__ partial
       if (scal[SC_DONE] != 0.0) break;  // iteration skipped
       const double pq = v[0] + extra + (kind == FIN_CG_ALPHA_ADD ? scal[dst] : 0.0);
       scal[SC_PQ] = pq;
+      // aux > 0: the slot holding r^H M^-1 r (cg_rz_slot), else SC_RZ
       double al = 0.0;
-      if (scal[SC_DONE] == 0.0 && pq > 0.0) al = scal[SC_RZ] / pq;
+      if (scal[SC_DONE] == 0.0 && pq > 0.0) al = scal[aux > 0.0 ? (int)aux : SC_RZ] / pq;
       if (scal[SC_DONE] == 0.0 && !(pq > 0.0)) scal[SC_DONE] = 2.0;  // breakdown
       scal[SC_ALPHA] = al;
       break;
@@ -1092,6 +1160,18 @@ __device__ __forceinline__ void finalize_body(const double* __restrict__ partial
       scal[SC_RZ] = v[1];
       scal[SC_BETA] = b;
       if (v[0] <= scal[SC_TOL2] || scal[SC_ITS] >= aux) scal[SC_DONE] = 1.0;
+      break;
+    }
+    case FIN_CG_BETA_K: {
+      // the bookkeeping a COL_CG_FIRST pass with beta_part does, for the
+      // host's check after a chunk: dst = iterations completed
+      if (scal[SC_DONE] != 0.0) break;  // iteration skipped
+      scal[SC_ITS] = (double)dst;
+      scal[SC_RR] = v[0];
+      const double rzo = scal[cg_rz_slot(dst - 1)];
+      scal[cg_rz_slot(dst)] = v[1];
+      scal[SC_BETA] = rzo > 0.0 ? v[1] / rzo : 0.0;
+      if (v[0] <= scal[SC_TOL2] || (double)dst >= aux) scal[SC_DONE] = 1.0;
       break;
     }
     case FIN_DBAR:

@@ -163,9 +163,9 @@ size_t carve(pl_plan* p, char* base) {
     maxb = std::max(maxb, (long)p->n[0] * p->n[1] / 2 + 1);  // row pass, >= 1 pair per block
   }
   p->partials_len = maxb * 4;
-  // two regions: the fused CG keeps the first pass's partials while the z
-  // pass writes its own
-  p->partials = (double*)take(sizeof(double) * p->partials_len * 2);
+  // three regions: the fused CG keeps the first pass's partials while the z
+  // pass writes its own, and the last pass's until the next first pass
+  p->partials = (double*)take(sizeof(double) * p->partials_len * 3);
   p->scal = (double*)take(sizeof(double) * SC_COUNT);
   p->flags = (int*)take(sizeof(int) * 4);
   p->hist = (int*)take(sizeof(int) * DQ_BINS);
@@ -351,18 +351,29 @@ int hvp_hat(pl_plan* p, const cx<T>* pin, cx<T>* q, int* nb) {
 
 // Gradient at the spectral iterate s_hat: g_hat, and s (real, written to
 // s_out), e, d; scalars GG, PRIOR (finalized), LIK, DSUM.
-int grad_hat(pl_plan* p, double* s_out) {
+// step_dir (nullable): s_out holds the real field of the previous iterate
+// and s_hat has just been advanced by alpha = SC_LS_ALPHA (<= 0: not at
+// all) times the direction whose real field is step_dir; then s = s_out +
+// alpha step_dir in real space (equal to F^-1 s_hat up to FFT rounding of
+// the direction) and the two inverse column passes are skipped.
+int grad_hat(pl_plan* p, double* s_out, const double* step_dir = nullptr) {
   cx<double>* t = p->t64;
-  HIPCHK(p, run_col<double>(p, 0, true, COL_PLAIN, col_args<double>(p, 0, p->s_hat, t), nullptr));
-  HIPCHK(p, run_col<double>(p, 1, true, COL_PLAIN, col_args<double>(p, 1, t, t), nullptr));
   RowArgs<double> ra = row_args<double>(p);
-  ra.in_c = t;
+  if (step_dir) {
+    ra.s_in = s_out;
+    ra.v = step_dir;
+    ra.scal = p->scal;
+  } else {
+    HIPCHK(p, run_col<double>(p, 0, true, COL_PLAIN, col_args<double>(p, 0, p->s_hat, t), nullptr));
+    HIPCHK(p, run_col<double>(p, 1, true, COL_PLAIN, col_args<double>(p, 1, t, t), nullptr));
+    ra.in_c = t;
+  }
   ra.out_c = t;
   ra.s_out = s_out;
   ra.e_out = p->e;
   ra.d_out = p->d;
   int nb = 0;
-  HIPCHK(p, run_row<double>(p, ROW_GRAD, ra, &nb));
+  HIPCHK(p, run_row<double>(p, step_dir ? ROW_GRAD_STEP : ROW_GRAD, ra, &nb));
   HIPCHK(p, finalize(p, nb, 2, FIN_STORE, SC_LIK, 1.0));
   HIPCHK(p, run_col<double>(p, 1, false, COL_PLAIN, col_args<double>(p, 1, t, t), nullptr));
   ColArgs<double> ca = col_args<double>(p, 0, t, p->g_hat);
@@ -458,16 +469,24 @@ int pcg(pl_plan* p, const cx<double>* rhs, double sign, double tol_abs, double t
     HIPCHK(p, set_scalar(p, SC_TOL2, tol2));
     HIPCHK(p, set_scalar(p, SC_DONE, rr0 <= tol2 ? 1.0 : 0.0));
   }
-  int launched = 0;
+  // Per iteration k: the first x pass (p = M^-1 r + beta p, which from k = 1
+  // on also closes iteration k - 1: beta, the convergence test and the
+  // bookkeeping, from the last pass's partials in part_c), y, z (with
+  // p^H H p), y (whose extra workgroup finalizes alpha), the last x pass
+  // (r, x and the partials of r^H r, r^H M^-1 r).  After each chunk one
+  // finalize closes its last iteration for the host's check.
+  double* part_c = p->partials + 2 * p->partials_len;
+  int launched = 0, nb5 = 0;
   while (launched < max_cg) {
     const int want = launched == 0 ? (first_chunk > 0 ? first_chunk : check_every)
                                    : next_cg_chunk(p->h_scal, check_every);
     int chunk = std::min(want, max_cg - launched);
     for (int k = 0; k < chunk; ++k) {
-      int nb1 = 0, nb3 = 0, nb5 = 0;
-      const bool first = fused && launched == 0 && k == 0;
+      const int kg = launched + k;  // iterations before this one
+      int nb1 = 0, nb3 = 0;
+      const bool first = fused && kg == 0;
       const double* skip = p->scal + SC_DONE;
-          ColArgs<T> c1 = col_args<T>(p, 0, pp, t);
+      ColArgs<T> c1 = col_args<T>(p, 0, pp, t);
       c1.cg_r = r;
       c1.scal = p->scal;
       c1.partials = part_a;
@@ -475,6 +494,13 @@ int pcg(pl_plan* p, const cx<double>* rhs, double sign, double tol_abs, double t
       c1.cg_rhs = rhs;
       c1.cg_rhs_sign = sign;
       c1.cg_x = x;
+      if (kg > 0) {
+        c1.beta_part = part_c;
+        c1.beta_nb = nb5;
+        c1.beta_scale = invN;
+        c1.cg_k = kg;
+        c1.cg_max = (double)max_cg;
+      }
       HIPCHK(p, run_col<T>(p, 0, true, first ? COL_CG_INIT : COL_CG_FIRST, c1, &nb1));
       ColArgs<T> c2 = col_args<T>(p, 1, t, t);
       c2.skip = skip;
@@ -490,20 +516,20 @@ int pcg(pl_plan* p, const cx<double>* rhs, double sign, double tol_abs, double t
       ColArgs<T> c4 = col_args<T>(p, 1, t, t);
       c4.skip = skip;
       c4.fin_on = 1;
-      c4.fin = FinArgs{part_b, nb3, 2, first ? FIN_CG_ALPHA_FIRST : FIN_CG_ALPHA, 0, 1.0, p->scal, 0.0,
-                       part_a, nb1, invN};
+      c4.fin = FinArgs{part_b, nb3, 2, first ? FIN_CG_ALPHA_FIRST : FIN_CG_ALPHA, 0, 1.0, p->scal,
+                       (double)cg_rz_slot(kg), part_a, nb1, invN};
       HIPCHK(p, run_col<T>(p, 1, false, COL_PLAIN, c4, nullptr));
       ColArgs<T> c5 = col_args<T>(p, 0, t, t);
       c5.base = pp;
       c5.cg_r = r;
       c5.cg_x = x;
       c5.scal = p->scal;
-      c5.partials = part_a;
+      c5.partials = part_c;
       c5.skip = skip;
       HIPCHK(p, run_col<T>(p, 0, false, COL_CG_LAST, c5, &nb5));
-      HIPCHK(p, finalize(p, nb5, 2, FIN_CG_BETA, 0, invN, (double)max_cg, part_a));
     }
     launched += chunk;
+    HIPCHK(p, finalize(p, nb5, 2, FIN_CG_BETA_K, launched, invN, (double)max_cg, part_c));
     int rc = read_scalars(p);
     if (rc) return rc;
     if (p->h_scal[SC_DONE] != 0.0) break;
@@ -766,7 +792,10 @@ int newton_solve(pl_plan* p, double* s_io, const pl_solve_opts& o, pl_solve_info
       int its = 0;
       rc = newton_step_queue<T>(p, eta * gn, o, inf, first_cg_chunk(prev_its, prev_eta, eta, o.eta_max), &its);
       if (rc) return rc;
-      rc = grad_hat(p, s_io);
+      // FP64 directions: the step is applied to the real field too (their
+      // real form from the line search is exact to FP64 rounding); FP32 ones
+      // (whose real form carries FP32 transform rounding) go through s_hat
+      rc = grad_hat(p, s_io, sizeof(T) == 8 ? p->preal : nullptr);
       if (rc) return rc;
       rc = read_scalars(p);
       if (rc) return rc;
@@ -781,7 +810,7 @@ int newton_solve(pl_plan* p, double* s_io, const pl_solve_opts& o, pl_solve_info
           int its64 = 0;
           rc = newton_step_queue<double>(p, eta * gn, o, inf, first_cg_chunk(its, eta, eta, o.eta_max), &its64);
           if (rc) return rc;
-          rc = grad_hat(p, s_io);
+          rc = grad_hat(p, s_io, p->preal);
           if (rc) return rc;
           rc = read_scalars(p);
           if (rc) return rc;

@@ -52,6 +52,9 @@ static hipError_t row_launch_n(int op, const RowArgs<T>& a, hipStream_t st, int*
       break;
 #if PL_T_IS_DOUBLE
     case ROW_GRAD: hipLaunchKernelGGL((row_kernel<T, N, ROW_GRAD, V>), grid, dim3(S::THREADS), 0, st, a); break;
+    case ROW_GRAD_STEP:
+      hipLaunchKernelGGL((row_kernel<T, N, ROW_GRAD_STEP, V>), grid, dim3(S::THREADS), 0, st, a);
+      break;
     case ROW_C2R_GRADLIK:
       hipLaunchKernelGGL((row_kernel<T, N, ROW_C2R_GRADLIK, V>), grid, dim3(S::THREADS), 0, st, a);
       break;
