@@ -991,11 +991,14 @@ __global__ void __launch_bounds__((RowShape<N, V>::THREADS)) row_kernel(RowArgs<
 
 struct ModeIter {
   Grid g;
+  // 32-bit unsigned divisions: half spectra hold at most 512 x 512 x 257
+  // modes, far below 2^32 (64-bit division is a long software sequence)
   __device__ __forceinline__ void decompose(long i, int& kx, int& ky, int& kz) const {
-    kx = (int)(i / g.nyh);
-    long r = i - (long)kx * g.nyh;
-    ky = (int)(r / g.h);
-    kz = (int)(r - (long)ky * g.h);
+    const unsigned ui = (unsigned)i, nyh = (unsigned)g.nyh, h = (unsigned)g.h;
+    const unsigned x = ui / nyh, r = ui - x * nyh, y = r / h;
+    kx = (int)x;
+    ky = (int)y;
+    kz = (int)(r - y * h);
   }
 };
 

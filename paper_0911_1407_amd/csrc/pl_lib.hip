@@ -197,7 +197,9 @@ struct View<double> {
   static cx<double>* pv(pl_plan* p) { return p->p64; }
   static cx<double>* t(pl_plan* p) { return p->t64; }
   static double* preal(pl_plan* p) { return p->preal; }
-  static const double* tab(pl_plan* p) { return p->radial ? p->tab_rad : p->tab_mode; }
+  // the table elementwise kernels read: the per-mode one streams, where
+  // the shell table would be a scattered lookup per element
+  static const double* tab(pl_plan* p) { return p->tab_mode; }
   static const double* tab(pl_plan* p, int radial) { return radial ? p->tab_rad : p->tab_mode; }
   static const cx<double>* tw(pl_plan* p, int a) { return p->tw64[a]; }
 };
@@ -208,7 +210,7 @@ struct View<float> {
   static cx<float>* pv(pl_plan* p) { return p->p32; }
   static cx<float>* t(pl_plan* p) { return p->t32; }
   static float* preal(pl_plan* p) { return p->preal32; }
-  static const float* tab(pl_plan* p) { return p->radial ? p->tab_rad32 : p->tab_mode32; }
+  static const float* tab(pl_plan* p) { return p->tab_mode32; }
   static const float* tab(pl_plan* p, int radial) { return radial ? p->tab_rad32 : p->tab_mode32; }
   static const cx<float>* tw(pl_plan* p, int a) { return p->tw32[a]; }
 };
@@ -230,7 +232,7 @@ ColArgs<T> col_args(pl_plan* p, int axis, const cx<T>* in, cx<T>* out) {
   a.tw = View<T>::tw(p, axis);
   a.g = p->g;
   a.inv_lam = View<T>::tab(p);
-  a.radial = p->radial;
+  a.radial = TAB_MODE;
   a.partials = p->partials;
   a.out_scale = T(1);
   a.nt = p->var[sizeof(T) == 4 ? 1 : 0][V_NT];
@@ -459,7 +461,7 @@ int pcg(pl_plan* p, const cx<double>* rhs, double sign, double tol_abs, double t
   } else {
     HIPCHK(p, set_scalar(p, SC_TOL2, tol_abs * tol_abs));
     hipLaunchKernelGGL((cg_init_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, rhs, sign, x, r, pp, tab,
-                       p->radial, p->g, p->Nh, p->scal, p->partials);
+                       TAB_MODE, p->g, p->Nh, p->scal, p->partials);
     HIPCHK(p, hipGetLastError());
     HIPCHK(p, finalize(p, NB_RED, 2, FIN_CG_INIT, 0, invN));
     int rc = read_scalars(p);
@@ -587,7 +589,7 @@ int line_search(pl_plan* p, cx<T>* x, double a_start, const pl_solve_opts& o, do
   int rc = inv_c2r<T>(p, x, View<T>::t(p), View<T>::preal(p));
   if (rc) return rc;
   hipLaunchKernelGGL((ls_dots_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, x, p->s_hat, p->g_hat,
-                     p->radial ? p->tab_rad : p->tab_mode, p->radial, p->g, p->Nh, (double)p->N * prior_mean(p),
+                     p->tab_mode, TAB_MODE, p->g, p->Nh, (double)p->N * prior_mean(p),
                      p->partials);
   HIPCHK(p, hipGetLastError());
   HIPCHK(p, finalize(p, NB_RED, 3, FIN_STORE, SC_LS_B, invN));
@@ -673,7 +675,7 @@ int newton_step_queue(pl_plan* p, double eta_gn, const pl_solve_opts& o, pl_solv
   rc = inv_c2r<T>(p, x, View<T>::t(p), View<T>::preal(p));
   if (rc) return rc;
   hipLaunchKernelGGL((ls_dots_kernel<T>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, x, p->s_hat, p->g_hat,
-                     p->radial ? p->tab_rad : p->tab_mode, p->radial, p->g, p->Nh, (double)p->N * prior_mean(p),
+                     p->tab_mode, TAB_MODE, p->g, p->Nh, (double)p->N * prior_mean(p),
                      p->partials);
   HIPCHK(p, hipGetLastError());
   HIPCHK(p, finalize(p, NB_RED, 3, FIN_STORE, SC_LS_B, invN));
@@ -938,7 +940,7 @@ int adjoint_solve(pl_plan* p, const double* s_star, const double* dL_ds, double*
   if (rc) return rc;
   // dL/dA from the spectral prior dot (k != 0)
   hipLaunchKernelGGL(adjoint_prior_dot_kernel, dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, p->x64, p->s_hat,
-                     p->radial ? p->tab_rad : p->tab_mode, p->radial, p->g, p->Nh, p->partials);
+                     p->tab_mode, TAB_MODE, p->g, p->Nh, p->partials);
   HIPCHK(p, hipGetLastError());
   HIPCHK(p, finalize(p, NB_RED, 1, FIN_STORE, SC_ADJ + 3, invN));
   hipLaunchKernelGGL(adjoint_cells_kernel, dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, lam, s_star, p->prob.w,
@@ -986,7 +988,7 @@ int nlcg_solve(pl_plan* p, double* s_io, const pl_solve_opts& o, pl_solve_info* 
   cx<double>* xi = p->x64;
   cx<double>* g_old = p->r64;
   cx<double>* q = p->p64;
-  const double* tab = p->radial ? p->tab_rad : p->tab_mode;
+  const double* tab = p->tab_mode;
   double gz_old = 0.0;
   bool restart = true;
   int status = PL_OK;
@@ -1003,7 +1005,7 @@ int nlcg_solve(pl_plan* p, double* s_io, const pl_solve_opts& o, pl_solve_info* 
     }
     // search vector
     hipLaunchKernelGGL(nlcg_dots_kernel, dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, p->g_hat, g_old, tab,
-                       p->radial, p->g, p->Nh, p->scal, p->partials);
+                       TAB_MODE, p->g, p->Nh, p->scal, p->partials);
     HIPCHK(p, hipGetLastError());
     HIPCHK(p, finalize(p, NB_RED, 2, FIN_STORE, SC_DF, invN));
     rc = read_scalars(p);
@@ -1013,7 +1015,7 @@ int nlcg_solve(pl_plan* p, double* s_io, const pl_solve_opts& o, pl_solve_info* 
     double slope = 0.0;
     for (int attempt = 0; attempt < 2; ++attempt) {
       hipLaunchKernelGGL(nlcg_update_kernel, dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, p->g_hat, g_old, xi,
-                         beta, tab, p->radial, p->g, p->Nh, p->scal, p->partials);
+                         beta, tab, TAB_MODE, p->g, p->Nh, p->scal, p->partials);
       HIPCHK(p, hipGetLastError());
       HIPCHK(p, finalize(p, NB_RED, 1, FIN_STORE, SC_DF + 2, invN));
       rc = read_scalars(p);
@@ -2296,7 +2298,7 @@ int batch_newton(pl_batch* b, double* const* s_io, const pl_solve_opts& o, pl_so
       e.n = p->N;
       e.g = p->g;
       e.radial = p->radial;
-      e.tab = View<T>::tab(p);
+      e.tab = View<T>::tab(p, p->radial);
       e.tab64 = p->radial ? p->tab_rad : p->tab_mode;
       e.rhs = p->g_hat;
       e.sign = -1.0;
@@ -3071,7 +3073,7 @@ int lb_pcg_fused(pl_plan* p, const double* bk, double tol_abs, int max_cg, int c
   double* part_x = part_a + p->partials_len / 2;
   HIPCHK(p, set_scalar(p, SC_TOL2, tol_abs * tol_abs));
   hipLaunchKernelGGL((cg_init_kernel<double>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, p->g_hat, -1.0, x, r,
-                     pp, View<double>::tab(p), p->radial, p->g, p->Nh, p->scal, p->partials);
+                     pp, View<double>::tab(p), TAB_MODE, p->g, p->Nh, p->scal, p->partials);
   HIPCHK(p, hipGetLastError());
   HIPCHK(p, finalize(p, NB_RED, 2, FIN_CG_INIT, 0, invN));
   const double* skip = p->scal + SC_DONE;
@@ -3161,7 +3163,7 @@ int lb_line_search(pl_plan* p, int model, const double* bk, const double* x_real
   int rc = inv_c2r<double>(p, x, p->t64, p->preal);
   if (rc) return rc;
   hipLaunchKernelGGL((ls_dots_kernel<double>), dim3(NB_RED), dim3(RED_THREADS), 0, p->stream, x, p->s_hat, p->g_hat,
-                     p->radial ? p->tab_rad : p->tab_mode, p->radial, p->g, p->Nh, (double)p->N * prior_mean(p),
+                     p->tab_mode, TAB_MODE, p->g, p->Nh, (double)p->N * prior_mean(p),
                      p->partials);
   HIPCHK(p, hipGetLastError());
   HIPCHK(p, finalize(p, NB_RED, 3, FIN_STORE, SC_LS_B, invN));
