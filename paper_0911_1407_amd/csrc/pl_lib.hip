@@ -2105,6 +2105,10 @@ void fill_args(pl_batch* b, double* const* s_io) {
     c->variant = v64;
     c = &cargs64(b, BC_G_XADD, true)[i]; *c = col_args<double>(p, 0, p->t64, p->g_hat); c->skip = inactive;
     c->variant = v64;
+    // the batch's x passes read the shell table of a radial spectrum (a few
+    // KB to 60 KB for these grids, cached), else the per-mode one
+    c->radial = p->radial ? TAB_SHELL : TAB_MODE;
+    c->inv_lam = View<double>::tab(p, p->radial);
     c->base = p->s_hat;
     c->k0_shift = (double)p->N * p->prob.mu;
     RowArgs<double>* r;
@@ -2120,11 +2124,15 @@ void fill_args(pl_batch* b, double* const* s_io) {
     ColArgs<T>* ct;
     ct = &cargs_t<T>(b, BT_CG1, true)[i]; *ct = col_args<T>(p, 0, pp, t);
     ct->cg_r = rr; ct->scal = p->scal; ct->partials = part_a; ct->skip = done; ct->variant = vT;
+    ct->radial = p->radial ? TAB_SHELL : TAB_MODE;
+    ct->inv_lam = View<T>::tab(p, p->radial);
     ct = &cargs_t<T>(b, BT_CGYI, true)[i]; *ct = col_args<T>(p, 1, t, t); ct->skip = done; ct->variant = vT;
     ct = &cargs_t<T>(b, BT_CGYF, true)[i]; *ct = col_args<T>(p, 1, t, t); ct->skip = done; ct->variant = vT;
     ct = &cargs_t<T>(b, BT_CG5, true)[i]; *ct = col_args<T>(p, 0, t, t);
     ct->base = pp; ct->cg_r = rr; ct->cg_x = x; ct->scal = p->scal; ct->partials = part_a; ct->skip = done;
     ct->variant = vT;
+    ct->radial = p->radial ? TAB_SHELL : TAB_MODE;
+    ct->inv_lam = View<T>::tab(p, p->radial);
     ct = &cargs_t<T>(b, BT_XCINV, true)[i]; *ct = col_args<T>(p, 0, x, t); ct->skip = inactive; ct->variant = vT;
     ct = &cargs_t<T>(b, BT_YCINV, true)[i]; *ct = col_args<T>(p, 1, t, t); ct->skip = inactive; ct->variant = vT;
     RowArgs<T>* rt;
