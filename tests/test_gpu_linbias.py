@@ -242,7 +242,7 @@ def test_map_selection_workload_64_matches_oracle(kind):
     # blocks, nbar 0.5) with the benchmark's 1.5-cell smoothing multiplier;
     # oracle Newton paths with different preconditioners reach the same
     # minimiser on this recipe (asserted on the CPU by
-    # test_oracle_linbias.test_preconditioner_changes_path_not_minimiser),
+    # test_oracle_spectral.test_linear_bias_minimiser_does_not_depend_on_preconditioner),
     # so the comparison is of the MAP itself
     inst = synth.config_instance("sel256", n=64)
     P = oracle_problem(inst)
