@@ -2272,38 +2272,38 @@ int batch_newton(pl_batch* b, double* const* s_io, const pl_solve_opts& o, pl_so
     b->graph_chunk[ti] = o.check_every;
     b->graph_maxcg[ti] = o.max_cg;
   }
-  for (int it = 0;; ++it) {
-    // retire converged / capped instances
-    int n_active = 0;
-    for (int i = 0; i < K; ++i) {
-      ctl[i] = BatchCtl{b->plans[i]->scal, 0, 0, 0.0, 0.0, 0, 0, 0, 0};
-      if (!active[i]) {
-        ctl[i].inactive = 1.0; ctl[i].done = 1.0; ctl[i].set_inactive = 1; ctl[i].set_done = 1;
-        continue;
-      }
-      if (gn[i] <= o.rtol * g0[i]) {
-        active[i] = 0;
-      } else if (it >= o.max_newton) {
-        active[i] = 0;
-        inf[i].status = PL_ERR_NOT_CONVERGED;
-      }
-      if (!active[i]) {
-        ctl[i].inactive = 1.0; ctl[i].done = 1.0; ctl[i].set_inactive = 1; ctl[i].set_done = 1;
-        continue;
-      }
-      ++n_active;
-      const double eta = std::min(o.eta_max, std::max(std::sqrt(gn[i] / g0[i]), 0.5 * o.rtol * g0[i] / gn[i]));
-      ctl[i].tol2 = eta * gn[i] * eta * gn[i];
-      ctl[i].set_tol2 = 1;
+  // Each instance advances on its own: a round runs (1) the line search,
+  // update and gradient of the instances whose CG ended in the previous
+  // round, (2) the CG start of those that go on, (3) one graph-replayed
+  // chunk of CG steps for every instance in its CG.  SC_INACTIVE masks the
+  // instances a phase does not concern (the transform passes and the
+  // finalizes skip them), SC_DONE the CG passes; so an instance whose CG
+  // ends early takes its next Newton step while the others' CG runs on.
+  enum { PH_OFF = 0, PH_START, PH_CG, PH_STEP };
+  std::vector<int> phase(K, PH_OFF), newton(K, 0);
+  for (int i = 0; i < K; ++i) {
+    if (!active[i]) continue;
+    if (gn[i] <= o.rtol * g0[i]) {
+      active[i] = 0;
+    } else if (o.max_newton <= 0) {
+      active[i] = 0;
+      inf[i].status = PL_ERR_NOT_CONVERGED;
+    } else {
+      phase[i] = PH_START;
     }
-    rc = bctl(b);
-    if (rc) return rc;
-    if (n_active == 0) break;
-    // elementwise operands for this Newton step
+  }
+  // mask: SC_INACTIVE = !in[i]; optionally SC_DONE and SC_TOL2 too
+  auto apply_mask = [&](const std::vector<int>& in) -> int {
+    for (int i = 0; i < K; ++i) {
+      ctl[i] = BatchCtl{b->plans[i]->scal, 0, 0, in[i] ? 0.0 : 1.0, 1.0, 0, 0, 1, phase[i] == PH_OFF ? 1 : 0};
+    }
+    return bctl(b);
+  };
+  auto fill_elems = [&](const std::vector<int>& in) {
     for (int i = 0; i < K; ++i) {
       pl_plan* p = b->plans[i];
       BatchElem<T> e{};
-      e.active = active[i];
+      e.active = in[i];
       e.nh = p->Nh;
       e.n = p->N;
       e.g = p->g;
@@ -2333,113 +2333,163 @@ int batch_newton(pl_batch* b, double* const* s_io, const pl_solve_opts& o, pl_so
       e.hist = p->hist;
       E[i] = e;
     }
-    rc = belem_upload<T>(b);
-    if (rc) return rc;
-    hipLaunchKernelGGL((dquant_hist_batch_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream,
-                       elems<T>(b, false));
-    BHIP(b, hipGetLastError());
-    hipLaunchKernelGGL((dquant_select_batch_kernel<T>), dim3(K), dim3(DQ_SELECT_THREADS), 0, b->stream, elems<T>(b, false));
-    BHIP(b, hipGetLastError());
-    if constexpr (sizeof(T) == 4) {
-      hipLaunchKernelGGL((d32_batch_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream, elems<T>(b, false));
-      BHIP(b, hipGetLastError());
+  };
+  auto retire = [&](int i, int status) {
+    phase[i] = PH_OFF;
+    active[i] = 0;
+    if (status != PL_OK) inf[i].status = status;
+  };
+  for (;;) {
+    std::vector<int> in(K, 0);
+    // (1) line search, update and gradient of the instances whose CG ended
+    bool any = false;
+    for (int i = 0; i < K; ++i) {
+      in[i] = phase[i] == PH_STEP;
+      any = any || in[i];
     }
-    hipLaunchKernelGGL((cg_init_batch_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream, elems<T>(b, false));
-    BHIP(b, hipGetLastError());
-    rc = bfin(b, BF_INIT, 2, FIN_CG_INIT, 0, 0.0, 1);
-    if (rc) return rc;
-    for (int launched = 0; launched < o.max_cg; launched += o.check_every) {
-      BHIP(b, hipGraphLaunch(b->graph[ti], b->stream));
-      rc = bread(b);
+    if (any) {
+      rc = apply_mask(in);
       if (rc) return rc;
-      bool all = true;
-      for (int i = 0; i < K; ++i)
-        if (active[i] && hs(b, i, SC_DONE) == 0.0) all = false;
-      if (all) break;
-    }
-    for (int i = 0; i < K; ++i)
-      if (active[i]) {
-        const int its = (int)hs(b, i, SC_ITS);
-        inf[i].cg_its += its;
-        inf[i].hvps += its + (hs(b, i, SC_DONE) == 2.0 ? 1 : 0);
-      }
-    // line search: real-space direction, spectral dots
-    BHIP(b, bcol<T>(b, true, COL_PLAIN, cargs_t<T>(b, BT_XCINV, false), wid_x<T>()));
-    BHIP(b, bcol<T>(b, true, COL_PLAIN, cargs_t<T>(b, BT_YCINV, false), wid_y<T>()));
-    BHIP(b, brow<T>(b, ROW_C2R, rargs_t<T>(b, BRT_C2R, false), wid_r<T>()));
-    hipLaunchKernelGGL((ls_dots_batch_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream, elems<T>(b, false));
-    BHIP(b, hipGetLastError());
-    rc = bfin(b, BF_LS, 3, FIN_STORE, SC_LS_B, 0.0, 1);
-    if (rc) return rc;
-    rc = bread(b);
-    if (rc) return rc;
-    std::vector<double> alpha(K, -1.0), a0(K, 1.0);
-    std::vector<int> pending(K, 0);
-    for (int i = 0; i < K; ++i)
-      if (active[i]) pending[i] = hs(b, i, SC_LS_SLOPE) < 0.0 ? 1 : 0;
-    for (int batch = 0; batch < 8; ++batch) {
-      bool any = false;
-      for (int i = 0; i < K; ++i) {
-        E[i].active = pending[i];
-        E[i].a0 = a0[i];
-        any = any || pending[i];
-      }
-      if (!any) break;
+      fill_elems(in);
       rc = belem_upload<T>(b);
       if (rc) return rc;
-      hipLaunchKernelGGL((ls_eval_batch_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream,
+      BHIP(b, bcol<T>(b, true, COL_PLAIN, cargs_t<T>(b, BT_XCINV, false), wid_x<T>()));
+      BHIP(b, bcol<T>(b, true, COL_PLAIN, cargs_t<T>(b, BT_YCINV, false), wid_y<T>()));
+      BHIP(b, brow<T>(b, ROW_C2R, rargs_t<T>(b, BRT_C2R, false), wid_r<T>()));
+      hipLaunchKernelGGL((ls_dots_batch_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream,
                          elems<T>(b, false));
       BHIP(b, hipGetLastError());
-      rc = bfin(b, BF_LS, 4, FIN_STORE, SC_DF, 1.0, 0);
+      rc = bfin(b, BF_LS, 3, FIN_STORE, SC_LS_B, 0.0, 1);
+      if (rc) return rc;
+      rc = bread(b);
+      if (rc) return rc;
+      std::vector<double> alpha(K, -1.0), a0(K, 1.0);
+      std::vector<int> pending(K, 0);
+      for (int i = 0; i < K; ++i)
+        if (in[i]) pending[i] = hs(b, i, SC_LS_SLOPE) < 0.0 ? 1 : 0;
+      for (int batch = 0; batch < 8; ++batch) {
+        bool anyp = false;
+        for (int i = 0; i < K; ++i) {
+          E[i].active = pending[i];
+          E[i].a0 = a0[i];
+          anyp = anyp || pending[i];
+        }
+        if (!anyp) break;
+        rc = belem_upload<T>(b);
+        if (rc) return rc;
+        hipLaunchKernelGGL((ls_eval_batch_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream,
+                           elems<T>(b, false));
+        BHIP(b, hipGetLastError());
+        rc = bfin(b, BF_LS, 4, FIN_STORE, SC_DF, 1.0, 0);
+        if (rc) return rc;
+        rc = bread(b);
+        if (rc) return rc;
+        for (int i = 0; i < K; ++i) {
+          if (!pending[i]) continue;
+          const double bb = hs(b, i, SC_LS_B), cc = hs(b, i, SC_LS_C), slope = hs(b, i, SC_LS_SLOPE);
+          double a = a0[i];
+          for (int j = 0; j < 4; ++j, a *= 0.5) {
+            const double df = a * bb + 0.5 * a * a * cc + hs(b, i, SC_DF + j);
+            if (df <= o.ls_c1 * a * slope) {
+              alpha[i] = a;
+              pending[i] = 0;
+              break;
+            }
+          }
+          a0[i] *= 1.0 / 16.0;
+        }
+      }
+      for (int i = 0; i < K; ++i) {
+        E[i].active = in[i] && alpha[i] > 0.0;
+        E[i].alpha = alpha[i];
+        if (in[i] && alpha[i] <= 0.0) {
+          retire(i, PL_ERR_LINESEARCH);
+          in[i] = 0;
+        }
+      }
+      rc = belem_upload<T>(b);
+      if (rc) return rc;
+      hipLaunchKernelGGL((axpy_batch_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream, elems<T>(b, false));
+      BHIP(b, hipGetLastError());
+      // line-search failures keep their s; mask them out of the gradient
+      rc = apply_mask(in);
+      if (rc) return rc;
+      rc = bgrad(b);
       if (rc) return rc;
       rc = bread(b);
       if (rc) return rc;
       for (int i = 0; i < K; ++i) {
-        if (!pending[i]) continue;
-        const double bb = hs(b, i, SC_LS_B), cc = hs(b, i, SC_LS_C), slope = hs(b, i, SC_LS_SLOPE);
-        double a = a0[i];
-        for (int j = 0; j < 4; ++j, a *= 0.5) {
-          const double df = a * bb + 0.5 * a * a * cc + hs(b, i, SC_DF + j);
-          if (df <= o.ls_c1 * a * slope) {
-            alpha[i] = a;
-            pending[i] = 0;
-            break;
-          }
+        if (!in[i]) continue;
+        gn[i] = std::sqrt(std::max(0.0, hs(b, i, SC_GG)));
+        inf[i].obj = 0.5 * hs(b, i, SC_PRIOR) + hs(b, i, SC_LIK);
+        inf[i].newton_its = ++newton[i];
+        if (!std::isfinite(gn[i]))
+          retire(i, PL_ERR_DOMAIN);
+        else if (gn[i] <= o.rtol * g0[i])
+          retire(i, PL_OK);
+        else if (newton[i] >= o.max_newton)
+          retire(i, PL_ERR_NOT_CONVERGED);
+        else
+          phase[i] = PH_START;
+      }
+    }
+    // (2) CG start: preconditioner constant, tolerance, initial residual
+    any = false;
+    for (int i = 0; i < K; ++i) {
+      in[i] = phase[i] == PH_START;
+      any = any || in[i];
+    }
+    if (any) {
+      for (int i = 0; i < K; ++i) {
+        ctl[i] = BatchCtl{b->plans[i]->scal, 0, 0, in[i] ? 0.0 : 1.0, 1.0, 0, 0, 1, phase[i] == PH_OFF ? 1 : 0};
+        if (in[i]) {
+          const double eta =
+              std::min(o.eta_max, std::max(std::sqrt(gn[i] / g0[i]), 0.5 * o.rtol * g0[i] / gn[i]));
+          ctl[i].tol2 = eta * gn[i] * eta * gn[i];
+          ctl[i].set_tol2 = 1;
         }
-        a0[i] *= 1.0 / 16.0;
       }
-    }
-    for (int i = 0; i < K; ++i) {
-      E[i].active = active[i] && alpha[i] > 0.0;
-      E[i].alpha = alpha[i];
-      if (active[i] && alpha[i] <= 0.0) {
-        active[i] = 0;
-        inf[i].status = PL_ERR_LINESEARCH;
+      rc = bctl(b);
+      if (rc) return rc;
+      fill_elems(in);
+      rc = belem_upload<T>(b);
+      if (rc) return rc;
+      hipLaunchKernelGGL((dquant_hist_batch_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream,
+                         elems<T>(b, false));
+      BHIP(b, hipGetLastError());
+      hipLaunchKernelGGL((dquant_select_batch_kernel<T>), dim3(K), dim3(DQ_SELECT_THREADS), 0, b->stream,
+                         elems<T>(b, false));
+      BHIP(b, hipGetLastError());
+      if constexpr (sizeof(T) == 4) {
+        hipLaunchKernelGGL((d32_batch_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream, elems<T>(b, false));
+        BHIP(b, hipGetLastError());
       }
+      hipLaunchKernelGGL((cg_init_batch_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream,
+                         elems<T>(b, false));
+      BHIP(b, hipGetLastError());
+      rc = bfin(b, BF_INIT, 2, FIN_CG_INIT, 0, 0.0, 1);
+      if (rc) return rc;
+      for (int i = 0; i < K; ++i)
+        if (in[i]) phase[i] = PH_CG;
     }
-    rc = belem_upload<T>(b);
-    if (rc) return rc;
-    hipLaunchKernelGGL((axpy_batch_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream, elems<T>(b, false));
-    BHIP(b, hipGetLastError());
-    // retire line-search failures before the gradient (their s stays put)
+    // (3) one chunk of CG steps for every instance in its CG
+    any = false;
     for (int i = 0; i < K; ++i) {
-      ctl[i] = BatchCtl{b->plans[i]->scal, 0, 0, active[i] ? 0.0 : 1.0, 1.0, 0, 0, 1, 0};
+      in[i] = phase[i] == PH_CG;
+      any = any || in[i];
     }
-    rc = bctl(b);
+    if (!any) break;  // every instance retired
+    rc = apply_mask(in);
     if (rc) return rc;
-    rc = bgrad(b);
-    if (rc) return rc;
+    BHIP(b, hipGraphLaunch(b->graph[ti], b->stream));
     rc = bread(b);
     if (rc) return rc;
     for (int i = 0; i < K; ++i) {
-      if (!active[i]) continue;
-      gn[i] = std::sqrt(std::max(0.0, hs(b, i, SC_GG)));
-      inf[i].obj = 0.5 * hs(b, i, SC_PRIOR) + hs(b, i, SC_LIK);
-      inf[i].newton_its = it + 1;
-      if (!std::isfinite(gn[i])) {
-        active[i] = 0;
-        inf[i].status = PL_ERR_DOMAIN;
-      }
+      if (!in[i] || hs(b, i, SC_DONE) == 0.0) continue;
+      const int its = (int)hs(b, i, SC_ITS);
+      inf[i].cg_its += its;
+      inf[i].hvps += its + (hs(b, i, SC_DONE) == 2.0 ? 1 : 0);
+      phase[i] = PH_STEP;
     }
   }
   if constexpr (sizeof(T) == 4) {
