@@ -1,5 +1,7 @@
 """Batched MAP solves (many uneven grids, one launch per pass) against the
 oracle and against single-plan solves."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -111,3 +113,38 @@ def test_batch_tile_variants_give_the_same_map(prec, tmp_path):
             assert info["status"] == 0 and info["rel_grad"] <= 1e-10, (vc, vr, i, info)
             assert _rel(s.cpu().numpy(), ref) <= tol, (vc, vr, i)
         b.close()
+
+
+def test_batch_waits_for_the_callers_stream():
+    # the caller's stream still writes w, counts and the spectrum (queued
+    # behind a spin of about 0.1 s) when set_problem is called: the batch
+    # joins that stream first, so it validates and solves the data that
+    # lands, not what the buffers held before; the result equals a solve of
+    # the same data written ahead of time, bit for bit
+    from paper_0911_1407_amd import binding
+    insts = synth.batch_instances(count=3, master_seed=7)
+    ref = binding.Batch(insts, precision="fp64")
+    s_ref, info_ref = ref.solve(rtol=1e-8, precision=0)
+    ref.close()
+    ns = [tuple(int(v) for v in it["n"]) for it in insts]
+    st = torch.cuda.current_stream()
+    h, ws_bytes = binding.pl_batch_create(ns, [tuple(it["box"]) for it in insts], binding.PL_FP64,
+                                          ctypes.c_void_p(st.cuda_stream))
+    ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device="cuda")
+    binding.pl_batch_set_workspace(h, ws[(-ws.data_ptr()) % 256:])
+    keep = []
+    for i, it in enumerate(insts):
+        dev = [torch.zeros(np.shape(it[k]), dtype=torch.float64, device="cuda") for k in ("w", "counts", "pk")]
+        host = [torch.from_numpy(np.ascontiguousarray(it[k])).pin_memory() for k in ("w", "counts", "pk")]
+        torch.cuda._sleep(200_000_000)
+        for d, hst in zip(dev, host):
+            d.copy_(hst, non_blocking=True)
+        binding.pl_batch_set_problem(h, i, *dev, it["amp"], it["mu"], it["nbar"], it.get("beta", 1.0),
+                                     it.get("inv_p0", 0.0))
+        keep.append((dev, host))
+    s = [torch.full(n, float(it["mu"]), dtype=torch.float64, device="cuda") for n, it in zip(ns, insts)]
+    infos = binding.pl_batch_solve(h, s, binding.make_opts(rtol=1e-8, precision=0))
+    binding.pl_batch_destroy(h)
+    for got, want, info, iref in zip(s, s_ref, infos, info_ref):
+        assert info["status"] == 0 and info["cg_its"] == iref["cg_its"], (info, iref)
+        assert torch.equal(got, want)
