@@ -8,6 +8,8 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <string>
 #include <vector>
 
@@ -20,6 +22,15 @@
 using namespace pl;
 
 namespace {
+
+// A named range for rocprofv3 --marker-trace (Newton steps, CG chunks,
+// HVPs, batch rounds); free when no tool is attached.
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 constexpr int NB_RED = 1024;  // blocks of the grid-stride reduction kernels
 // relative tolerance of each FP32 sweep of a mixed-precision linear solve
@@ -336,6 +347,7 @@ int inv_c2r(pl_plan* p, const cx<T>* in, cx<T>* tmp, T* out) {
 // with K = 3 over *nb blocks.
 template <typename T>
 int hvp_hat(pl_plan* p, const cx<T>* pin, cx<T>* q, int* nb) {
+  Range range("pl hvp");
   cx<T>* t = View<T>::t(p);
   HIPCHK(p, run_col<T>(p, 0, true, COL_PLAIN, col_args<T>(p, 0, pin, t), nullptr));
   HIPCHK(p, run_col<T>(p, 1, true, COL_PLAIN, col_args<T>(p, 1, t, t), nullptr));
@@ -485,6 +497,7 @@ int pcg(pl_plan* p, const cx<double>* rhs, double sign, double tol_abs, double t
     const int want = launched == 0 ? (first_chunk > 0 ? first_chunk : check_every)
                                    : next_cg_chunk(p->h_scal, check_every);
     int chunk = std::min(want, max_cg - launched);
+    Range range("pl cg chunk");
     for (int k = 0; k < chunk; ++k) {
       const int kg = launched + k;  // iterations before this one
       int nb1 = 0, nb3 = 0;
@@ -791,6 +804,7 @@ int newton_solve(pl_plan* p, double* s_io, const pl_solve_opts& o, pl_solve_info
       // forcing term: sqrt(||g||/||g0||), but no tighter than needed to
       // reach the stopping tolerance from here (half of it, for margin)
       const double eta = std::min(o.eta_max, std::max(std::sqrt(gn / g0), 0.5 * o.rtol * g0 / gn));
+      Range range("pl newton step");
       rc = set_precond_constant(p);
       if (rc) return rc;
       int its = 0;
@@ -2340,6 +2354,7 @@ int batch_newton(pl_batch* b, double* const* s_io, const pl_solve_opts& o, pl_so
     if (status != PL_OK) inf[i].status = status;
   };
   for (;;) {
+    Range range("pl batch round");
     std::vector<int> in(K, 0);
     // (1) line search, update and gradient of the instances whose CG ended
     bool any = false;
