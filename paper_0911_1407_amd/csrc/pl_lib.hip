@@ -1911,7 +1911,10 @@ struct BWork {
   int threads = 0, lds = 0;
   size_t off = 0, cap = 0;  // region in the blob and its capacity (items)
 };
-enum BWorkId { W_X64 = 0, W_Y64, W_R64, W_X32, W_Y32, W_R32, W_COUNT };
+// W_XC / W_YC / W_RC: the running solve's CG passes over the instances not
+// yet finished (rebuilt as they finish, so that the last CG steps do not
+// dispatch the blocks of finished grids)
+enum BWorkId { W_X64 = 0, W_Y64, W_R64, W_X32, W_Y32, W_R32, W_XC, W_YC, W_RC, W_COUNT };
 
 void order_for_xcds(std::vector<int4>& nat) {
   std::vector<int4> w(nat.size());
@@ -1922,12 +1925,14 @@ void order_for_xcds(std::vector<int4>& nat) {
 // Column pass over all instances (axis 0: x, 1: y), instance i in tile
 // variant var[i].
 template <typename T>
-void col_work(const std::vector<pl_plan*>& plans, int axis, const std::vector<int>& var, BWork& w) {
+void col_work(const std::vector<pl_plan*>& plans, int axis, const std::vector<int>& var, BWork& w,
+              const std::vector<int>* subset = nullptr) {
   w.items.clear();
   w.nb.assign(plans.size(), 0);
   w.threads = 0;
   w.lds = 0;
   for (size_t i = 0; i < plans.size(); ++i) {
+    if (subset && !(*subset)[i]) continue;
     const pl_plan* p = plans[i];
     const BatchShape<T> sh = batch_shape<T>(p->n[axis], var[i]);
     const int h = p->g.h;
@@ -1945,12 +1950,14 @@ void col_work(const std::vector<pl_plan*>& plans, int axis, const std::vector<in
 
 // Row (z) pass over all instances, instance i in tile variant var[i].
 template <typename T>
-void row_work(const std::vector<pl_plan*>& plans, const std::vector<int>& var, BWork& w) {
+void row_work(const std::vector<pl_plan*>& plans, const std::vector<int>& var, BWork& w,
+              const std::vector<int>* subset = nullptr) {
   w.items.clear();
   w.nb.assign(plans.size(), 0);
   w.threads = 0;
   w.lds = 0;
   for (size_t i = 0; i < plans.size(); ++i) {
+    if (subset && !(*subset)[i]) continue;
     const pl_plan* p = plans[i];
     const BatchShape<T> sh = batch_shape<T>(p->n[2], var[i]);
     const int nunits = p->n[0] * p->n[1] / 2;
@@ -1994,6 +2001,7 @@ struct pl_batch {
   double* scal_all = nullptr;
   double* h_scal = nullptr;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t graph_c = nullptr;  // the running solve's CG chunk over W_XC / W_YC / W_RC
   int graph_chunk[2] = {0, 0}, graph_maxcg[2] = {0, 0};
   std::string err;
 };
@@ -2077,6 +2085,24 @@ void build_work(pl_batch* b) {
     for (int i = 0; i < W_COUNT; ++i)
       if (!b->work[i].items.empty())
         std::memcpy(b->h_blob + b->work[i].off, b->work[i].items.data(), sizeof(int4) * b->work[i].items.size());
+}
+
+// The CG passes' work lists over the instances in `subset` (W_XC, W_YC,
+// W_RC), copied to the device on the batch's stream.
+template <typename T>
+int build_compact(pl_batch* b, const std::vector<int>& subset) {
+  const int ti = sizeof(T) == 8 ? 0 : 1;
+  col_work<T>(b->plans, 0, b->vcol[ti], b->work[W_XC], &subset);
+  col_work<T>(b->plans, 1, b->vcol[ti], b->work[W_YC], &subset);
+  row_work<T>(b->plans, b->vrow[ti], b->work[W_RC], &subset);
+  for (int i : {(int)W_XC, (int)W_YC, (int)W_RC}) {
+    BWork& w = b->work[i];
+    if (w.items.empty() || w.items.size() > w.cap) return PL_ERR_INVALID_ARG;
+    std::memcpy(b->h_blob + w.off, w.items.data(), sizeof(int4) * w.items.size());
+    BHIP(b, hipMemcpyAsync(b->d_blob + w.off, b->h_blob + w.off, sizeof(int4) * w.items.size(),
+                           hipMemcpyHostToDevice, b->stream));
+  }
+  return PL_OK;
 }
 
 template <typename T>
@@ -2218,8 +2244,7 @@ int bgrad(pl_batch* b) {
 
 // Enqueue `chunk` fused CG steps for all instances (captured in a graph)
 template <typename T>
-int bcg_chunk(pl_batch* b, int chunk, int max_cg) {
-  const int wx = wid_x<T>(), wy = wid_y<T>(), wr = wid_r<T>();
+int bcg_chunk(pl_batch* b, int chunk, int max_cg, int wx = wid_x<T>(), int wy = wid_y<T>(), int wr = wid_r<T>()) {
   for (int k = 0; k < chunk; ++k) {
     BHIP(b, bcol<T>(b, true, COL_CG_FIRST, cargs_t<T>(b, BT_CG1, false), wx));
     BHIP(b, bcol<T>(b, true, COL_PLAIN, cargs_t<T>(b, BT_CGYI, false), wy));
@@ -2295,6 +2320,12 @@ int batch_newton(pl_batch* b, double* const* s_io, const pl_solve_opts& o, pl_so
   // ends early takes its next Newton step while the others' CG runs on.
   enum { PH_OFF = 0, PH_START, PH_CG, PH_STEP };
   std::vector<int> phase(K, PH_OFF), newton(K, 0);
+  // the CG chunks run from the graph over every instance until the cells of
+  // the unfinished ones fall to half of those it covers; then from a graph
+  // over the unfinished instances only (rebuilt each time they halve again)
+  hipGraphExec_t cg_graph = b->graph[ti];
+  double graph_cells = 0.0;
+  for (int i = 0; i < K; ++i) graph_cells += (double)b->plans[i]->N;
   for (int i = 0; i < K; ++i) {
     if (!active[i]) continue;
     if (gn[i] <= o.rtol * g0[i]) {
@@ -2496,7 +2527,35 @@ int batch_newton(pl_batch* b, double* const* s_io, const pl_solve_opts& o, pl_so
     if (!any) break;  // every instance retired
     rc = apply_mask(in);
     if (rc) return rc;
-    BHIP(b, hipGraphLaunch(b->graph[ti], b->stream));
+    {
+      std::vector<int> unfinished(K, 0);
+      double cells = 0.0;
+      for (int i = 0; i < K; ++i)
+        if (phase[i] != PH_OFF) {
+          unfinished[i] = 1;
+          cells += (double)b->plans[i]->N;
+        }
+      if (cells <= 0.5 * graph_cells) {
+        rc = build_compact<T>(b, unfinished);
+        if (rc) return bfail(b, rc, "compacted work lists exceed their capacity");
+        if (b->graph_c) {
+          (void)hipGraphExecDestroy(b->graph_c);
+          b->graph_c = nullptr;
+        }
+        BHIP(b, hipStreamSynchronize(b->stream));
+        hipGraph_t g = nullptr;
+        BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        int crc = bcg_chunk<T>(b, o.check_every, o.max_cg, W_XC, W_YC, W_RC);
+        hipError_t e = hipStreamEndCapture(b->stream, &g);
+        if (crc) return crc;
+        BHIP(b, e);
+        BHIP(b, hipGraphInstantiate(&b->graph_c, g, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(g);
+        cg_graph = b->graph_c;
+        graph_cells = cells;
+      }
+    }
+    BHIP(b, hipGraphLaunch(cg_graph, b->stream));
     rc = bread(b);
     if (rc) return rc;
     for (int i = 0; i < K; ++i) {
@@ -2722,6 +2781,9 @@ int pl_batch_create(pl_batch** out, int n_inst, const int32_t* n, const double* 
   }
   build_work(b);
   for (int i = 0; i < W_COUNT; ++i) b->work[i].cap = b->work[i].items.size();
+  b->work[W_XC].cap = std::max(b->work[W_X64].cap, b->work[W_X32].cap);
+  b->work[W_YC].cap = std::max(b->work[W_Y64].cap, b->work[W_Y32].cap);
+  b->work[W_RC].cap = std::max(b->work[W_R64].cap, b->work[W_R32].cap);
   for (int t = 0; t < 2; ++t) {
     b->vcol[t].assign(n_inst, 0);
     b->vrow[t].assign(n_inst, 0);
@@ -2859,6 +2921,7 @@ int pl_batch_destroy(pl_batch* b) {
   if (!b) return PL_ERR_INVALID_ARG;
   for (int t = 0; t < 2; ++t)
     if (b->graph[t]) (void)hipGraphExecDestroy(b->graph[t]);
+  if (b->graph_c) (void)hipGraphExecDestroy(b->graph_c);
   for (pl_plan* p : b->plans) pl_plan_destroy(p);
   if (b->h_blob) (void)hipHostFree(b->h_blob);
   if (b->ev) (void)hipEventDestroy(b->ev);

@@ -148,3 +148,29 @@ def test_batch_waits_for_the_callers_stream():
     for got, want, info, iref in zip(s, s_ref, infos, info_ref):
         assert info["status"] == 0 and info["cg_its"] == iref["cg_its"], (info, iref)
         assert torch.equal(got, want)
+
+
+def test_batch_newton_cap_and_mixed_outcomes():
+    # a Newton cap of 2 stops every instance that needs more, each with its
+    # own status, while an instance with nothing to fit (w = 0) stays at mu;
+    # the same batch then solves to convergence
+    from paper_0911_1407_amd.binding import Batch, PL_ERR_NOT_CONVERGED
+    insts = synth.batch_instances(count=4, master_seed=13)
+    empty = synth.make_instance((32, 32, 32), (100.0,) * 3, 1.0, 1.0, 1.0, seed=4)
+    empty["w"] = np.zeros((32, 32, 32))
+    empty["counts"] = np.zeros((32, 32, 32))
+    insts.append(empty)
+    b = Batch(insts, precision="mixed")
+    s_list, infos = b.solve(rtol=1e-10, max_newton=2, precision=0)
+    for i, info in enumerate(infos[:-1]):
+        # (the Armijo test is on f, so ||g|| may still exceed ||g0|| here)
+        assert info["status"] == PL_ERR_NOT_CONVERGED and info["newton_its"] == 2, (i, info)
+        assert np.isfinite(info["rel_grad"]) and info["rel_grad"] > 1e-10
+    assert infos[-1]["status"] == 0 and infos[-1]["newton_its"] == 0
+    assert torch.all(s_list[-1] == insts[-1]["mu"])
+    s_list, infos = b.solve(rtol=1e-10, max_newton=100, precision=1)
+    for i, (inst, s, info) in enumerate(zip(insts[:-1], s_list, infos)):
+        assert info["status"] == 0 and info["rel_grad"] <= 1e-10, (i, info)
+        ref, _ = o_newton.newton_krylov(oracle_problem(inst), rtol=1e-11)
+        assert _rel(s.cpu().numpy(), ref) <= 1e-4, i
+    b.close()
