@@ -220,8 +220,9 @@ def cpu_oracle_baseline(inst, v, full=False):
     workload (rtol 1e-8) and sequential solves of the first 8 instances of
     the 64-instance batched workload (rtol 1e-6), with Newton / CG counts;
     with full=True (--cpu-full) also the 256^3 selection workload's solve
-    (rtol 1e-6), the 256^3 bias workload's solve and adjoint (rtol 1e-6) and
-    all 64 batch instances, which take minutes."""
+    and adjoint (rtol 1e-6) and all 64 batch instances, which take minutes
+    (the 256^3 bias workload's oracle MAP takes hours; its time at rtol
+    1e-10 is recorded by tests/golden/make_golden.py)."""
     sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
     from oracle import adjoint as o_adj
     from oracle import dft as o_dft
@@ -234,9 +235,16 @@ def cpu_oracle_baseline(inst, v, full=False):
         return Problem(it["n"], it["box"], it["w"], it["counts"], it["pk"], it["amp"], it["mu"], it["nbar"],
                        it["beta"], 0.0)
 
-    def timed_solve(it, rtol, precond="mean"):
+    def timed_solve(it, rtol, precond="mean", name=None):
+        # progress lines (one per Newton step) only for the long full-size
+        # solves; printing is outside the oracle's arithmetic
+        prog = None
+        if name:
+            def prog(k, rg, cg):
+                print(f"# cpu oracle {name}: newton {k} rel_grad {rg:.2e} cg {cg}", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
-        s_, info = newton_krylov(problem(it), rtol=rtol, max_newton=200, max_cg=5000, precond=precond)
+        s_, info = newton_krylov(problem(it), rtol=rtol, max_newton=200, max_cg=5000, precond=precond,
+                                 progress=prog)
         return s_, {"s": time.perf_counter() - t0, "newton_its": int(info["newton_its"]),
                     "cg_its": int(info["cg_its"]), "status": info["status"], "rtol": rtol, "precond": precond}
 
@@ -257,22 +265,29 @@ def cpu_oracle_baseline(inst, v, full=False):
     _, ttm["plain32"] = timed_solve(synth.config_instance("plain32"), 1e-8)
     insts = synth.batch_instances(count=64)
     subset = insts if full else insts[:8]
-    recs = [timed_solve(it, 1e-6)[1] for it in subset]
+    recs = []
+    for k, it in enumerate(subset):
+        recs.append(timed_solve(it, 1e-6)[1])
+        if full:
+            print(f"# cpu oracle batch instance {k + 1}/{len(subset)} n={it['n'][0]}: {recs[-1]['s']:.1f} s",
+                  file=sys.stderr, flush=True)
     ttm["batch64_sequential"] = {"instances": len(subset), "n": [int(it["n"][0]) for it in subset],
                                  "s": sum(r["s"] for r in recs), "cg_its": sum(r["cg_its"] for r in recs),
                                  "rtol": 1e-6}
     if full:
-        _, ttm["sel256"] = timed_solve(synth.config_instance("sel256"), 1e-6)
-        # the bias workload with the oracle's 25th-percentile preconditioner
-        # constant (the mean-diagonal one takes about ten times the CG steps
-        # there; both reach the same MAP)
-        bias = synth.config_instance("bias256")
-        s_b, ttm["bias256"] = timed_solve(bias, 1e-6, precond="p25")
-        _, dL = o_adj.squared_error_loss(s_b, bias["s_true"])
+        sel = synth.config_instance("sel256")
+        s_sel, ttm["sel256"] = timed_solve(sel, 1e-6, name="sel256")
+        print(f"# cpu oracle sel256 solve: {ttm['sel256']}", file=sys.stderr, flush=True)
+        # the adjoint of L = sum (s* - s_true)^2 at that MAP
+        _, dL = o_adj.squared_error_loss(s_sel, sel["s_true"])
         t0 = time.perf_counter()
-        _, its = o_adj.adjoint_pcg(problem(bias), s_b, dL, rtol=1e-6, max_cg=50000, precond="p25")
-        ttm["bias256_adjoint"] = {"s": time.perf_counter() - t0, "cg_its": int(its), "rtol": 1e-6,
-                                  "precond": "p25"}
+
+        def aprog(k, rn):
+            print(f"# cpu oracle sel256 adjoint: cg {k} residual {rn:.3e}", file=sys.stderr, flush=True)
+
+        _, its = o_adj.adjoint_pcg(problem(sel), s_sel, dL, rtol=1e-6, max_cg=50000, progress=aprog)
+        ttm["sel256_adjoint"] = {"s": time.perf_counter() - t0, "cg_its": int(its), "rtol": 1e-6}
+        print(f"# cpu oracle sel256 adjoint: {ttm['sel256_adjoint']}", file=sys.stderr, flush=True)
     cpu_model = None
     try:
         with open("/proc/cpuinfo") as f:
@@ -285,7 +300,7 @@ def cpu_oracle_baseline(inst, v, full=False):
             "sample": f"{reps} oracle spectral HVPs (scipy rfftn/irfftn on {o_dft._WORKERS} threads, FP64) on "
                       f"the same {n[0]}^3 data at s = s_true, elementwise numpy single-threaded; time_to_map: "
                       f"oracle Newton-Krylov solves (plain32 at rtol 1e-8, {len(subset)} batch instances at "
-                      f"rtol 1e-6{', sel256, bias256 and its adjoint at rtol 1e-6' if full else ''})",
+                      f"rtol 1e-6{', the 256^3 selection workload and its adjoint at rtol 1e-6' if full else ''})",
             "time_to_map": ttm}
 
 

@@ -34,13 +34,13 @@ def adjoint_dense(prob, s_star, dL_ds):
     return np.linalg.solve(H, np.asarray(dL_ds, dtype=np.float64).ravel()).reshape(prob.n)
 
 
-def adjoint_pcg(prob, s_star, dL_ds, rtol=1e-12, max_cg=20000, precond="mean"):
+def adjoint_pcg(prob, s_star, dL_ds, rtol=1e-12, max_cg=20000, precond="mean", progress=None):
     """lambda from spectral preconditioned CG on H(s*) lambda = dL/ds*
-    (preconditioner as ``newton.precond_constant``)."""
+    (preconditioner as ``newton.precond_constant``; progress as ``pcg``'s)."""
     ops = SpectralOps(prob)
     d = hess_diag(prob, s_star)
     b_hat = ops.fwd(np.asarray(dL_ds, dtype=np.float64))
-    x_hat, its, rn = pcg(ops, d, b_hat, rtol * ops.norm(b_hat), max_cg, precond)
+    x_hat, its, rn = pcg(ops, d, b_hat, rtol * ops.norm(b_hat), max_cg, precond, progress)
     return ops.inv(x_hat), its
 
 

@@ -160,10 +160,11 @@ def precond_constant(d, kind="mean"):
     return m
 
 
-def pcg(ops, d, rhs_hat, tol_abs, max_cg, precond="mean"):
+def pcg(ops, d, rhs_hat, tol_abs, max_cg, precond="mean", progress=None):
     """Preconditioned CG on H x = rhs in spectral coordinates, preconditioned by
     the Fourier-diagonal 1/lambda_k + c (c from ``precond_constant``).  Stops
-    when ||r|| <= tol_abs."""
+    when ||r|| <= tol_abs.  progress (optional): called with (iteration,
+    ||r||) every 100 iterations (reporting only)."""
     M = ops.inv_lam + precond_constant(d, precond)
     Minv = np.where(M > 0, 1.0 / np.where(M > 0, M, 1.0), 0.0)
     x = np.zeros_like(rhs_hat)
@@ -185,6 +186,8 @@ def pcg(ops, d, rhs_hat, tol_abs, max_cg, precond="mean"):
         its = k + 1
         if ops.norm(r) <= tol_abs:
             break
+        if progress is not None and its % 100 == 0:
+            progress(its, ops.norm(r))
         z = Minv * r
         rz_new = ops.dot(r, z)
         p = z + (rz_new / rz) * p
@@ -193,9 +196,11 @@ def pcg(ops, d, rhs_hat, tol_abs, max_cg, precond="mean"):
 
 
 def newton_krylov(prob, s0=None, rtol=1e-8, max_newton=100, max_cg=500,
-                  eta_max=0.5, return_hat=False, precond="mean"):
+                  eta_max=0.5, return_hat=False, precond="mean", progress=None):
     """Inexact Newton-Krylov MAP solver with the spectral iterate (inner PCG
-    preconditioned as ``precond_constant`` says)."""
+    preconditioned as ``precond_constant`` says).  progress (optional): called
+    with (Newton step, ||g|| / ||g0||, CG iterations so far) after each step
+    (reporting only)."""
     ops = SpectralOps(prob)
     n = prob.n
     s0 = np.full(n, prob.mu) if s0 is None else np.array(s0, dtype=np.float64).reshape(n)
@@ -237,6 +242,8 @@ def newton_krylov(prob, s0=None, rtol=1e-8, max_newton=100, max_cg=500,
         gnorm = ops.norm(g_hat)
         info["newton_its"] = it + 1
         info["history"].append(gnorm / g0)
+        if progress is not None:
+            progress(it + 1, gnorm / g0, info["cg_its"])
     else:
         if gnorm > rtol * g0:
             info["status"] = "not_converged"
