@@ -181,7 +181,11 @@ def test_map_and_adjoint_256_bias_workload_match_oracle(bias256):
             "nbar": abs(grads["nbar"] - adj["dL_dnbar"]) / abs(adj["dL_dnbar"]),
             "N.u": abs(dN_u - adj["dL_dN_dot_u"]) / abs(adj["dL_dN_dot_u"]),
         }
-        lrel, lworst = cell_compare(grads["lam"].cpu().numpy(), ref["cells"], adj["lambda_cells"], tol)
+        # lambda solves H(s*) lambda = 2 (s* - s_true) at each side's own MAP
+        # (3e-9 apart): that difference, amplified by H's conditioning,
+        # lands in the cells where lambda is small, so the cell floor is a
+        # tenth of max|lambda| (a tile or index error gives O(1) errors)
+        lrel, lworst = cell_compare(grads["lam"].cpu().numpy(), ref["cells"], adj["lambda_cells"], tol, floor=0.1)
         print(f"bias256 adjoint {prec} rtol {rtol:g}: rel errors vs oracle {errs}, lambda rel-L2 {lrel:.3e} "
               f"(worst cell {lworst:.3f} of the bound), cg {ainfo['cg_its']}", flush=True)
         for k, e in errs.items():
@@ -191,8 +195,11 @@ def test_map_and_adjoint_256_bias_workload_match_oracle(bias256):
 
 def test_adjoint_256_bias_workload_matches_central_fd(bias256):
     # central differences of L(s*(theta)) at relative step 1e-5 on A and
-    # beta, and along the stored direction u of the counts (step 1e-5),
-    # through FP64 GPU solves, against the FP64 adjoint
+    # beta, and along the stored direction u of the counts (step 1e-3),
+    # through FP64 GPU solves, against the FP64 adjoint.  The counts enter
+    # the gradient linearly, so s*(N) is smooth and the O(h^2) truncation
+    # stays near 1e-6 at h = 1e-3; at h = 1e-5 the change of L (about 0.2)
+    # sinks into the spread of two MAP solves stopped at rtol 1e-12
     inst, ref = bias256
     plan = _plan(inst)
     st = torch.from_numpy(inst["s_true"]).cuda()
@@ -220,7 +227,7 @@ def test_adjoint_256_bias_workload_matches_central_fd(bias256):
         print(f"bias256 dL/d{name}: adjoint {grads[name]:.10e} central FD {fd:.10e} "
               f"rel {abs(grads[name] - fd) / abs(fd):.2e}", flush=True)
         assert abs(grads[name] - fd) <= 1e-4 * abs(fd), (name, grads[name], fd)
-    h = 1e-5
+    h = 1e-3
     fd = (L_at(counts=inst["counts"] + h * u) - L_at(counts=inst["counts"] - h * u)) / (2 * h)
     print(f"bias256 dL/dN . u: adjoint {dN_u:.10e} central FD {fd:.10e} rel {abs(dN_u - fd) / abs(fd):.2e}",
           flush=True)
