@@ -18,9 +18,9 @@ __global__ void __launch_bounds__(BATCH_THREADS) col_batch_kernel(const ColArgs<
 #define PL_C(NN)                                                      \
   case NN:                                                            \
     if (a.variant == 2)                                               \
-      col_body<T, NN, INV, OP, 2>(a, w.y, w.z, lds_all, w.w);         \
+      col_body<T, NN, INV, OP, 2, true>(a, w.y, w.z, lds_all, w.w);   \
     else                                                              \
-      col_body<T, NN, INV, OP, 0>(a, w.y, w.z, lds_all, w.w);         \
+      col_body<T, NN, INV, OP, 0, true>(a, w.y, w.z, lds_all, w.w);   \
     break;
     PL_BATCH_LENGTHS(PL_C)
 #undef PL_C

@@ -310,7 +310,7 @@ constexpr bool has_wide_variant(int n) { return n == 128 || n == 192 || n == 256
 // One workgroup's share of a column pass: tile `tile` of slab `slab`.
 // Threads beyond ColShape::THREADS (when a batched launch uses a larger
 // block) only take part in the barriers.
-template <typename T, int N, bool INV, int OP, int V = 0>
+template <typename T, int N, bool INV, int OP, int V = 0, bool BATCHED = false>
 __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab,
                                          cx<T>* lds_all, int block_linear) {
   using PL = Plan<N>;
@@ -325,9 +325,13 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
   // the extra registers would cost occupancy (FP32 at 512 points: 146
   // instead of about 90 VGPRs, 3 instead of 4 waves per SIMD; the split
   // tile; 1024-thread blocks, held to 128 VGPRs); the other FP64 passes are
-  // held to 2 waves per SIMD by their LDS either way.
+  // held to 2 waves per SIMD by their LDS either way.  Batched launches
+  // (BATCHED) never preload: one kernel serves every length of the batch,
+  // so its registers are those of the largest body, and the 96-point body
+  // (24 values per thread) with preloading needs 173 (FP32) to 256 (FP64)
+  // VGPRs, which would hold the blocks of every length to 1-2 waves per SIMD.
   constexpr bool SPLIT = ColShape<T, N, V>::SPLIT;
-  constexpr bool PRELOAD = !(sizeof(T) == 4 && N >= 512) && !SPLIT && ColShape<T, N, V>::THREADS <= 512;
+  constexpr bool PRELOAD = !BATCHED && !(sizeof(T) == 4 && N >= 512) && !SPLIT && ColShape<T, N, V>::THREADS <= 512;
 
   const bool active = (int)threadIdx.x < ColShape<T, N, V>::THREADS;
   const int cl = threadIdx.x % B;
