@@ -80,6 +80,33 @@ __device__ __forceinline__ void dft4(cx<T>& a0, cx<T>& a1, cx<T>& a2, cx<T>& a3)
   a3 = d02 - d13;
 }
 
+// 6 = 2 x 3: DFT3 of the even and of the odd inputs, then one radix-2 step
+// with the twiddles w6^k (w6 = exp(-+ 2 pi i / 6)):
+//   X[k] = E[k] + w6^k O[k],  X[k + 3] = E[k] - w6^k O[k],  k = 0, 1, 2
+template <bool INV, typename T>
+__device__ __forceinline__ void dft6(cx<T>* v) {
+  const T h = T(0.86602540378443864676);  // sqrt(3)/2
+  cx<T> e0 = v[0], e1 = v[2], e2 = v[4];
+  cx<T> o0 = v[1], o1 = v[3], o2 = v[5];
+  dft3<INV>(e0, e1, e2);
+  dft3<INV>(o0, o1, o2);
+  // w6 = 1/2 -+ i sqrt(3)/2, w6^2 = -1/2 -+ i sqrt(3)/2 (forward: minus)
+  cx<T> t1, t2;
+  if constexpr (INV) {
+    t1 = {T(0.5) * o1.x - h * o1.y, T(0.5) * o1.y + h * o1.x};
+    t2 = {-T(0.5) * o2.x - h * o2.y, -T(0.5) * o2.y + h * o2.x};
+  } else {
+    t1 = {T(0.5) * o1.x + h * o1.y, T(0.5) * o1.y - h * o1.x};
+    t2 = {-T(0.5) * o2.x + h * o2.y, -T(0.5) * o2.y - h * o2.x};
+  }
+  v[0] = e0 + o0;
+  v[3] = e0 - o0;
+  v[1] = e1 + t1;
+  v[4] = e1 - t1;
+  v[2] = e2 + t2;
+  v[5] = e2 - t2;
+}
+
 template <bool INV, typename T>
 __device__ __forceinline__ void dft8(cx<T>* v) {
   const T r2 = T(0.70710678118654752440);
@@ -160,6 +187,7 @@ __device__ __forceinline__ void dft_r(cx<T>* v) {
   if constexpr (R == 2) dft2<INV>(v[0], v[1]);
   else if constexpr (R == 3) dft3<INV>(v[0], v[1], v[2]);
   else if constexpr (R == 4) dft4<INV>(v[0], v[1], v[2], v[3]);
+  else if constexpr (R == 6) dft6<INV>(v);
   else if constexpr (R == 8) dft8<INV>(v);
   else if constexpr (R == 16) dft16<INV>(v);
   else static_assert(R == 2, "unsupported radix");
@@ -185,7 +213,7 @@ PL_PLAN(24, 1, 2, 8, 3, 1)
 PL_PLAN(32, 4, 2, 8, 4, 1)
 PL_PLAN(48, 4, 3, 4, 4, 3)
 PL_PLAN(64, 8, 2, 8, 8, 1)
-PL_PLAN(96, 4, 3, 8, 4, 3)
+PL_PLAN(96, 8, 3, 4, 4, 6)
 PL_PLAN(128, 8, 2, 16, 8, 1)
 PL_PLAN(192, 8, 3, 8, 8, 3)
 PL_PLAN(256, 16, 2, 16, 16, 1)
@@ -243,6 +271,8 @@ __device__ __forceinline__ void stage_compute(cx<T>* v, int t, const cx<T>* __re
         if constexpr (R > 4) {
           w[4] = tw[4 * k * STEP];
           w[5] = cmul(w[4], w[1]);
+        }
+        if constexpr (R > 6) {
           w[6] = cmul(w[4], w[2]);
           w[7] = cmul(w[4], w[3]);
         }
