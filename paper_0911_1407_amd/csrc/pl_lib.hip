@@ -1821,6 +1821,20 @@ int tune_precision(pl_plan* p, const std::string& key, std::vector<std::string>&
 
 }  // namespace
 
+// The tune cache holds the lines of both autotuners (plan and batch); each
+// rewrites the whole file with both format lines on top.
+static void write_tune_cache(const char* path, const std::vector<std::string>& lines) {
+  if (FILE* f = std::fopen(path, "w")) {
+    std::fprintf(f,
+                 "# pl_plan_autotune cache: arch grid table precision x(Krylov passes) y z x(operator passes) "
+                 "table(Krylov) table(operator) streaming-loads ms/CG-step ms/HVP\n"
+                 "# pl_batch_autotune cache: arch batch precision lengths (most cells first) "
+                 "column-variants row-variants ms/CG-step\n");
+    for (const std::string& l : lines) std::fprintf(f, "%s\n", l.c_str());
+    std::fclose(f);
+  }
+}
+
 extern "C" int pl_plan_autotune(pl_plan* p, const char* cache_path) {
   int rc = check_ready(p);
   if (rc) return rc;
@@ -1854,15 +1868,7 @@ extern "C" int pl_plan_autotune(pl_plan* p, const char* cache_path) {
     if (rc) return rc;
   }
   p->d_valid = false;  // the timing diagonal is not a linearisation of the posterior
-  if (cache_path && added) {
-    if (FILE* f = std::fopen(cache_path, "w")) {
-      std::fprintf(f,
-                   "# pl_plan_autotune cache: arch grid table precision x(Krylov passes) y z x(operator passes) "
-                   "table(Krylov) table(operator) streaming-loads ms/CG-step ms/HVP\n");
-      for (const std::string& l : lines) std::fprintf(f, "%s\n", l.c_str());
-      std::fclose(f);
-    }
-  }
+  if (cache_path && added) write_tune_cache(cache_path, lines);
   return PL_OK;
 }
 
@@ -2881,14 +2887,7 @@ int pl_batch_autotune(pl_batch* b, const char* cache_path) {
     }
   (void)hipStreamSynchronize(b->stream);
   if (rc) return rc;
-  if (cache_path && added) {
-    if (FILE* f = std::fopen(cache_path, "w")) {
-      std::fprintf(f, "# pl_batch_autotune cache: arch batch precision lengths (most cells first) "
-                      "column-variants row-variants ms/CG-step\n");
-      for (const std::string& l : lines) std::fprintf(f, "%s\n", l.c_str());
-      std::fclose(f);
-    }
-  }
+  if (cache_path && added) write_tune_cache(cache_path, lines);
   return PL_OK;
 }
 
