@@ -164,6 +164,31 @@ __global__ void __launch_bounds__(256) finalize_batch_kernel(const BatchFin* __r
                 scale2_invN ? f.invN : scale2);
 }
 
+// The Armijo pick of every active instance from its first batch of trial
+// steps (a0, a0/2, a0/4, a0/8; the same test as ls_select_kernel):
+// SC_LS_ALPHA = the accepted step or -1.  One block per instance.
+template <typename T>
+__global__ void ls_select_batch_kernel(const BatchElem<T>* __restrict__ E, double c1) {
+  const BatchElem<T> a = E[blockIdx.x];
+  if (!a.active || threadIdx.x != 0) return;
+  ls_select_scal(a.scal_rw, a.a0, c1);
+}
+
+// y += alpha x with alpha = SC_LS_ALPHA of the instance (nothing when the
+// pick found no step)
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS) axpy_batch_dev_kernel(const BatchElem<T>* __restrict__ E) {
+  const BatchElem<T> a = E[blockIdx.y];
+  if (!a.active) return;
+  const double alpha = a.scal[SC_LS_ALPHA];
+  if (!(alpha > 0.0)) return;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < a.nh; i += (long)gridDim.x * blockDim.x) {
+    cx<T> xv = a.x[i];
+    cx<double> yv = a.y[i];
+    a.y[i] = {yv.x + alpha * (double)xv.x, yv.y + alpha * (double)xv.y};
+  }
+}
+
 __global__ void batch_ctl_kernel(const BatchCtl* __restrict__ C, int count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;

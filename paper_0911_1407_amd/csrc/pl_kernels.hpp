@@ -1403,8 +1403,7 @@ __global__ void __launch_bounds__(RED_THREADS) axpy_hat_dev_kernel(cx<double>* _
 // SC_DF + j) against c1 a slope; the first accepted step goes to
 // SC_LS_ALPHA, -1 if none (or if the direction does not descend).  Written
 // with rounded (unfused) operations, the arithmetic the host test uses.
-__global__ void ls_select_kernel(double* scal, double a0, double c1) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ __forceinline__ void ls_select_scal(double* scal, double a0, double c1) {
   const double b = scal[SC_LS_B], c = scal[SC_LS_C], slope = scal[SC_LS_SLOPE];
   double alpha = -1.0;
   if (slope < 0.0) {
@@ -1419,6 +1418,11 @@ __global__ void ls_select_kernel(double* scal, double a0, double c1) {
     }
   }
   scal[SC_LS_ALPHA] = alpha;
+}
+
+__global__ void ls_select_kernel(double* scal, double a0, double c1) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  ls_select_scal(scal, a0, c1);
 }
 #endif
 

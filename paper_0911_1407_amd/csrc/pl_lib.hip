@@ -1908,6 +1908,9 @@ int xcd_remap(int hw, int total) {
   return xcd * per + (xcd < rem ? xcd : rem) + k;
 }
 
+// staging slots of the batch's control-record uploads (bctl)
+constexpr int kCtlSlots = 4;
+
 // Work list of one batched pass with its launch configuration: blocks
 // ordered so that each XCD receives a contiguous range of work items, the
 // block size and dynamic LDS the largest of the instances' tile shapes.
@@ -2008,6 +2011,9 @@ struct pl_batch {
   double* h_scal = nullptr;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t graph_c = nullptr;  // the running solve's CG chunk over W_XC / W_YC / W_RC
+  // control records: composed in slot 0 of the host blob's control region,
+  // uploaded from one of kCtlSlots staging slots in turn (bctl)
+  int ctl_next = 0, ctl_unsynced = 0;
   int graph_chunk[2] = {0, 0}, graph_maxcg[2] = {0, 0};
   std::string err;
 };
@@ -2050,7 +2056,7 @@ size_t batch_layout(pl_batch* b) {
   b->off_fin = take(sizeof(BatchFin) * K * BF_COUNT);
   b->off_e64 = take(sizeof(BatchElem<double>) * K);
   b->off_e32 = take(sizeof(BatchElem<float>) * K);
-  b->off_ctl = take(sizeof(BatchCtl) * K);
+  b->off_ctl = take(sizeof(BatchCtl) * K * (1 + kCtlSlots));
   b->off_scal = take(sizeof(double) * K * SC_COUNT);
   return off;
 }
@@ -2213,20 +2219,33 @@ int bread(pl_batch* b) {
   BHIP(b, hipMemcpyAsync(b->h_scal, b->scal_all, sizeof(double) * SC_COUNT * b->K, hipMemcpyDeviceToHost,
                          b->stream));
   BHIP(b, hipStreamSynchronize(b->stream));
+  b->ctl_unsynced = 0;  // every queued upload has completed
   return PL_OK;
 }
 
 double& hs(pl_batch* b, int i, int slot) { return b->h_scal[(size_t)i * SC_COUNT + slot]; }
 
-// Upload the control records and apply them.
+// Upload the control records composed in slot 0 and apply them.  The
+// upload goes through the next of kCtlSlots pinned staging slots, so the
+// caller may compose the next records at once; a staging slot is written
+// again only after its copy has completed (the stream is synchronized once
+// kCtlSlots uploads are outstanding; every read-back also completes them).
 int bctl(pl_batch* b) {
+  const size_t K = b->K;
+  if (b->ctl_unsynced >= kCtlSlots) {
+    BHIP(b, hipStreamSynchronize(b->stream));
+    b->ctl_unsynced = 0;
+  }
+  const int slot = 1 + b->ctl_next;
+  b->ctl_next = (b->ctl_next + 1) % kCtlSlots;
+  ++b->ctl_unsynced;
   BatchCtl* hc = blob_ptr<BatchCtl>(b, b->off_ctl, true);
-  BHIP(b, hipMemcpyAsync(blob_ptr<BatchCtl>(b, b->off_ctl, false), hc, sizeof(BatchCtl) * b->K,
-                         hipMemcpyHostToDevice, b->stream));
-  hipLaunchKernelGGL(batch_ctl_kernel, dim3((b->K + 63) / 64), dim3(64), 0, b->stream,
-                     blob_ptr<BatchCtl>(b, b->off_ctl, false), b->K);
+  BatchCtl* hs_slot = hc + (size_t)slot * K;
+  BatchCtl* ds_slot = blob_ptr<BatchCtl>(b, b->off_ctl, false) + (size_t)slot * K;
+  std::memcpy(hs_slot, hc, sizeof(BatchCtl) * K);
+  BHIP(b, hipMemcpyAsync(ds_slot, hs_slot, sizeof(BatchCtl) * K, hipMemcpyHostToDevice, b->stream));
+  hipLaunchKernelGGL(batch_ctl_kernel, dim3((b->K + 63) / 64), dim3(64), 0, b->stream, ds_slot, b->K);
   BHIP(b, hipGetLastError());
-  BHIP(b, hipStreamSynchronize(b->stream));  // staging may be rewritten next
   return PL_OK;
 }
 
@@ -2400,6 +2419,9 @@ int batch_newton(pl_batch* b, double* const* s_io, const pl_solve_opts& o, pl_so
       any = any || in[i];
     }
     if (any) {
+      // queued without a read-back: the direction in real space, the line
+      // search's dots, its first batch of trial steps (a = 1 .. 1/8), the
+      // Armijo pick and the update on the device, then the gradient
       rc = apply_mask(in);
       if (rc) return rc;
       fill_elems(in);
@@ -2413,63 +2435,104 @@ int batch_newton(pl_batch* b, double* const* s_io, const pl_solve_opts& o, pl_so
       BHIP(b, hipGetLastError());
       rc = bfin(b, BF_LS, 3, FIN_STORE, SC_LS_B, 0.0, 1);
       if (rc) return rc;
-      rc = bread(b);
-      if (rc) return rc;
-      std::vector<double> alpha(K, -1.0), a0(K, 1.0);
-      std::vector<int> pending(K, 0);
-      for (int i = 0; i < K; ++i)
-        if (in[i]) pending[i] = hs(b, i, SC_LS_SLOPE) < 0.0 ? 1 : 0;
-      for (int batch = 0; batch < 8; ++batch) {
-        bool anyp = false;
-        for (int i = 0; i < K; ++i) {
-          E[i].active = pending[i];
-          E[i].a0 = a0[i];
-          anyp = anyp || pending[i];
-        }
-        if (!anyp) break;
-        rc = belem_upload<T>(b);
-        if (rc) return rc;
-        hipLaunchKernelGGL((ls_eval_batch_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream,
-                           elems<T>(b, false));
-        BHIP(b, hipGetLastError());
-        rc = bfin(b, BF_LS, 4, FIN_STORE, SC_DF, 1.0, 0);
-        if (rc) return rc;
-        rc = bread(b);
-        if (rc) return rc;
-        for (int i = 0; i < K; ++i) {
-          if (!pending[i]) continue;
-          const double bb = hs(b, i, SC_LS_B), cc = hs(b, i, SC_LS_C), slope = hs(b, i, SC_LS_SLOPE);
-          double a = a0[i];
-          for (int j = 0; j < 4; ++j, a *= 0.5) {
-            const double df = a * bb + 0.5 * a * a * cc + hs(b, i, SC_DF + j);
-            if (df <= o.ls_c1 * a * slope) {
-              alpha[i] = a;
-              pending[i] = 0;
-              break;
-            }
-          }
-          a0[i] *= 1.0 / 16.0;
-        }
-      }
-      for (int i = 0; i < K; ++i) {
-        E[i].active = in[i] && alpha[i] > 0.0;
-        E[i].alpha = alpha[i];
-        if (in[i] && alpha[i] <= 0.0) {
-          retire(i, PL_ERR_LINESEARCH);
-          in[i] = 0;
-        }
-      }
-      rc = belem_upload<T>(b);
-      if (rc) return rc;
-      hipLaunchKernelGGL((axpy_batch_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream, elems<T>(b, false));
+      hipLaunchKernelGGL((ls_eval_batch_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream,
+                         elems<T>(b, false));
       BHIP(b, hipGetLastError());
-      // line-search failures keep their s; mask them out of the gradient
-      rc = apply_mask(in);
+      rc = bfin(b, BF_LS, 4, FIN_STORE, SC_DF, 1.0, 0);
       if (rc) return rc;
+      hipLaunchKernelGGL((ls_select_batch_kernel<T>), dim3(K), dim3(64), 0, b->stream, elems<T>(b, false),
+                         o.ls_c1);
+      BHIP(b, hipGetLastError());
+      hipLaunchKernelGGL((axpy_batch_dev_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream,
+                         elems<T>(b, false));
+      BHIP(b, hipGetLastError());
       rc = bgrad(b);
       if (rc) return rc;
       rc = bread(b);
       if (rc) return rc;
+      // an instance whose first batch accepted no step along a descent
+      // direction backtracks on the host (batches from 1/16; its iterate,
+      // real direction and linearisation are unchanged); one that is not a
+      // descent direction stops
+      std::vector<double> alpha(K, -1.0), a0(K, 1.0 / 16.0);
+      std::vector<int> pending(K, 0);
+      bool anyp = false;
+      for (int i = 0; i < K; ++i) {
+        if (!in[i]) continue;
+        alpha[i] = hs(b, i, SC_LS_ALPHA);
+        if (alpha[i] > 0.0) continue;
+        if (hs(b, i, SC_LS_SLOPE) < 0.0) {
+          pending[i] = 1;
+          anyp = true;
+        } else {
+          retire(i, PL_ERR_LINESEARCH);
+          in[i] = 0;
+        }
+      }
+      if (anyp) {
+        std::vector<int> redo = pending;
+        for (int batch = 1; batch < 8; ++batch) {
+          anyp = false;
+          for (int i = 0; i < K; ++i) {
+            E[i].active = pending[i];
+            E[i].a0 = a0[i];
+            anyp = anyp || pending[i];
+          }
+          if (!anyp) break;
+          rc = belem_upload<T>(b);
+          if (rc) return rc;
+          hipLaunchKernelGGL((ls_eval_batch_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream,
+                             elems<T>(b, false));
+          BHIP(b, hipGetLastError());
+          rc = bfin(b, BF_LS, 4, FIN_STORE, SC_DF, 1.0, 0);
+          if (rc) return rc;
+          rc = bread(b);
+          if (rc) return rc;
+          for (int i = 0; i < K; ++i) {
+            if (!pending[i]) continue;
+            const double bb = hs(b, i, SC_LS_B), cc = hs(b, i, SC_LS_C), slope = hs(b, i, SC_LS_SLOPE);
+            double a = a0[i];
+            for (int j = 0; j < 4; ++j, a *= 0.5) {
+              const double df = a * bb + 0.5 * a * a * cc + hs(b, i, SC_DF + j);
+              if (df <= o.ls_c1 * a * slope) {
+                alpha[i] = a;
+                pending[i] = 0;
+                break;
+              }
+            }
+            a0[i] *= 1.0 / 16.0;
+          }
+        }
+        std::vector<int> stepped(K, 0);
+        bool anys = false;
+        for (int i = 0; i < K; ++i) {
+          if (!redo[i]) continue;
+          if (alpha[i] > 0.0) {
+            stepped[i] = 1;
+            anys = true;
+          } else {
+            retire(i, PL_ERR_LINESEARCH);
+            in[i] = 0;
+          }
+        }
+        if (anys) {
+          for (int i = 0; i < K; ++i) {
+            E[i].active = stepped[i];
+            E[i].alpha = alpha[i];
+          }
+          rc = belem_upload<T>(b);
+          if (rc) return rc;
+          hipLaunchKernelGGL((axpy_batch_kernel<T>), dim3(NBB, K), dim3(RED_THREADS), 0, b->stream,
+                             elems<T>(b, false));
+          BHIP(b, hipGetLastError());
+          rc = apply_mask(stepped);
+          if (rc) return rc;
+          rc = bgrad(b);
+          if (rc) return rc;
+          rc = bread(b);
+          if (rc) return rc;
+        }
+      }
       for (int i = 0; i < K; ++i) {
         if (!in[i]) continue;
         gn[i] = std::sqrt(std::max(0.0, hs(b, i, SC_GG)));
