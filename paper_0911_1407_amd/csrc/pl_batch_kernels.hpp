@@ -9,6 +9,14 @@
 namespace pl {
 
 #define PL_BATCH_LENGTHS(X) X(32) X(48) X(64) X(96) X(128)
+// A batched pass is one launch per length class, each class its own kernel:
+// a kernel's registers are those of its largest body, and the 128-point
+// bodies (16 values per thread) would otherwise hold the blocks of the
+// shorter lengths to their occupancy.
+#define PL_BATCH_LENGTHS_C0(X) X(32) X(48) X(64) X(96)
+#define PL_BATCH_LENGTHS_C1(X) X(128)
+constexpr int BATCH_CLASSES = 2;
+inline int batch_class(int n) { return n == 128 ? 1 : 0; }
 constexpr int BATCH_THREADS = 256;  // the largest block of any batched pass
 
 inline bool batch_length_supported(int n) {
@@ -41,12 +49,13 @@ inline BatchShape<T> batch_shape(int n, int v) {
 }
 
 // work item: (instance, tile or row-pair block, slab, block index in the
-// instance); threads / lds_bytes: the launch's block size and dynamic LDS
+// instance); cls: the length class of every item of the launch (batch_class);
+// threads / lds_bytes: the launch's block size and dynamic LDS
 template <typename T>
-hipError_t launch_col_batch(bool inverse, int op, const ColArgs<T>* args, const int4* work, int nblocks,
+hipError_t launch_col_batch(bool inverse, int op, int cls, const ColArgs<T>* args, const int4* work, int nblocks,
                             int threads, int lds_bytes, hipStream_t st);
 template <typename T>
-hipError_t launch_row_batch(int op, const RowArgs<T>* args, const int4* work, int nblocks, int threads,
+hipError_t launch_row_batch(int op, int cls, const RowArgs<T>* args, const int4* work, int nblocks, int threads,
                             int lds_bytes, hipStream_t st);
 
 // Per-instance operands of the batched elementwise kernels (grid.y = instance)

@@ -1915,9 +1915,10 @@ constexpr int kCtlSlots = 4;
 // ordered so that each XCD receives a contiguous range of work items, the
 // block size and dynamic LDS the largest of the instances' tile shapes.
 struct BWork {
-  std::vector<int4> items;
-  std::vector<int> nb;  // blocks per instance (= partial-sum records)
-  int threads = 0, lds = 0;
+  std::vector<int4> items;  // the items of length class 0, then those of class 1
+  std::vector<int> nb;      // blocks per instance (= partial-sum records)
+  int split = 0;            // number of class-0 items
+  int threads[BATCH_CLASSES] = {0, 0}, lds[BATCH_CLASSES] = {0, 0};  // per class launch
   size_t off = 0, cap = 0;  // region in the blob and its capacity (items)
 };
 // W_XC / W_YC / W_RC: the running solve's CG passes over the instances not
@@ -1931,52 +1932,62 @@ void order_for_xcds(std::vector<int4>& nat) {
   nat.swap(w);
 }
 
+// The per-class item lists in launch order: each class XCD-ordered for its
+// own launch, class 0 first.
+void join_classes(BWork& w, std::vector<int4>* cls) {
+  order_for_xcds(cls[0]);
+  order_for_xcds(cls[1]);
+  w.items = cls[0];
+  w.items.insert(w.items.end(), cls[1].begin(), cls[1].end());
+  w.split = (int)cls[0].size();
+}
+
 // Column pass over all instances (axis 0: x, 1: y), instance i in tile
 // variant var[i].
 template <typename T>
 void col_work(const std::vector<pl_plan*>& plans, int axis, const std::vector<int>& var, BWork& w,
               const std::vector<int>* subset = nullptr) {
-  w.items.clear();
+  std::vector<int4> cls[BATCH_CLASSES];
   w.nb.assign(plans.size(), 0);
-  w.threads = 0;
-  w.lds = 0;
+  for (int c = 0; c < BATCH_CLASSES; ++c) w.threads[c] = w.lds[c] = 0;
   for (size_t i = 0; i < plans.size(); ++i) {
     if (subset && !(*subset)[i]) continue;
     const pl_plan* p = plans[i];
+    const int c = batch_class(p->n[axis]);
     const BatchShape<T> sh = batch_shape<T>(p->n[axis], var[i]);
     const int h = p->g.h;
     const int ncols = axis == 0 ? p->n[1] * h : h;
     const int nslabs = axis == 0 ? 1 : p->n[0];
     const int nbx = (ncols + sh.B - 1) / sh.B;
     for (int sl = 0; sl < nslabs; ++sl)
-      for (int t = 0; t < nbx; ++t) w.items.push_back(make_int4((int)i, t, sl, t + nbx * sl));
+      for (int t = 0; t < nbx; ++t) cls[c].push_back(make_int4((int)i, t, sl, t + nbx * sl));
     w.nb[i] = nbx * nslabs;
-    w.threads = std::max(w.threads, sh.col_threads);
-    w.lds = std::max(w.lds, sh.col_lds);
+    w.threads[c] = std::max(w.threads[c], sh.col_threads);
+    w.lds[c] = std::max(w.lds[c], sh.col_lds);
   }
-  order_for_xcds(w.items);
+  join_classes(w, cls);
 }
 
 // Row (z) pass over all instances, instance i in tile variant var[i].
 template <typename T>
 void row_work(const std::vector<pl_plan*>& plans, const std::vector<int>& var, BWork& w,
               const std::vector<int>* subset = nullptr) {
-  w.items.clear();
+  std::vector<int4> cls[BATCH_CLASSES];
   w.nb.assign(plans.size(), 0);
-  w.threads = 0;
-  w.lds = 0;
+  for (int c = 0; c < BATCH_CLASSES; ++c) w.threads[c] = w.lds[c] = 0;
   for (size_t i = 0; i < plans.size(); ++i) {
     if (subset && !(*subset)[i]) continue;
     const pl_plan* p = plans[i];
+    const int c = batch_class(p->n[2]);
     const BatchShape<T> sh = batch_shape<T>(p->n[2], var[i]);
     const int nunits = p->n[0] * p->n[1] / 2;
     const int nbu = (nunits + sh.G - 1) / sh.G;
-    for (int b = 0; b < nbu; ++b) w.items.push_back(make_int4((int)i, b, 0, b));
+    for (int b = 0; b < nbu; ++b) cls[c].push_back(make_int4((int)i, b, 0, b));
     w.nb[i] = nbu;
-    w.threads = std::max(w.threads, sh.row_threads);
-    w.lds = std::max(w.lds, sh.row_lds);
+    w.threads[c] = std::max(w.threads[c], sh.row_threads);
+    w.lds[c] = std::max(w.lds[c], sh.row_lds);
   }
-  order_for_xcds(w.items);
+  join_classes(w, cls);
 }
 
 // Column / row pass kinds of a batched solve
@@ -2124,16 +2135,31 @@ int wid_y() { return sizeof(T) == 8 ? W_Y64 : W_Y32; }
 template <typename T>
 int wid_r() { return sizeof(T) == 8 ? W_R64 : W_R32; }
 
-// One batched column / row pass over work list `wid`.
+// One batched column / row pass over work list `wid`: one launch per length
+// class present.
 template <typename T>
 hipError_t bcol(pl_batch* b, bool inverse, int op, const ColArgs<T>* args, int wid) {
   const BWork& w = b->work[wid];
-  return launch_col_batch<T>(inverse, op, args, work_dev(b, wid), (int)w.items.size(), w.threads, w.lds, b->stream);
+  const int count[2] = {w.split, (int)w.items.size() - w.split};
+  for (int c = 0, first = 0; c < BATCH_CLASSES; first += count[c], ++c) {
+    if (count[c] == 0) continue;
+    hipError_t e = launch_col_batch<T>(inverse, op, c, args, work_dev(b, wid) + first, count[c], w.threads[c],
+                                       w.lds[c], b->stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 template <typename T>
 hipError_t brow(pl_batch* b, int op, const RowArgs<T>* args, int wid) {
   const BWork& w = b->work[wid];
-  return launch_row_batch<T>(op, args, work_dev(b, wid), (int)w.items.size(), w.threads, w.lds, b->stream);
+  const int count[2] = {w.split, (int)w.items.size() - w.split};
+  for (int c = 0, first = 0; c < BATCH_CLASSES; first += count[c], ++c) {
+    if (count[c] == 0) continue;
+    hipError_t e = launch_row_batch<T>(op, c, args, work_dev(b, wid) + first, count[c], w.threads[c], w.lds[c],
+                                       b->stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // Fill the per-instance pass arguments (depends on the caller's s pointers).

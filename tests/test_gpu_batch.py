@@ -56,6 +56,27 @@ def test_batch_matches_oracle_and_single(prec):
             assert _rel(got, s1.cpu().numpy()) <= tol
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_with_128_point_axes_matches_single(prec):
+    # 128-point transforms run in their own batched kernels: instances whose
+    # x, y or z length is 128 next to shorter axes of the same and of other
+    # instances, each against a single-plan solve of the same instance
+    from paper_0911_1407_amd.binding import Batch, Plan
+    shapes = [((128, 64, 96), 11), ((64, 128, 32), 12), ((32, 48, 128), 13), ((48, 48, 48), 14)]
+    insts = [synth.make_instance(n, tuple(3.125 * v for v in n), 1.2, 1.0, 1.0, radius=1.2 * max(n),
+                                 mask_frac=0.15, seed=sd, block=8) for n, sd in shapes]
+    b = Batch(insts, precision=prec)
+    s_list, infos = b.solve(rtol=1e-10, max_newton=100, max_cg=2000)
+    tol = 1e-6 if prec == "fp64" else 1e-4
+    for inst, s, info in zip(insts, s_list, infos):
+        assert info["status"] == 0 and info["rel_grad"] <= 1e-10, (inst["n"], info)
+        plan = Plan(inst["n"], inst["box"], precision=prec)
+        plan.set_instance(inst)
+        s1, info1 = plan.solve(rtol=1e-10, max_cg=2000)
+        assert info1["status"] == 0
+        assert _rel(s.cpu().numpy(), s1.cpu().numpy()) <= tol, inst["n"]
+
+
 def test_batch_workload_64_instances():
     # the batched workload: 64 instances, n in {32, 48, 64, 96}, mixed precision
     from paper_0911_1407_amd.binding import Batch
