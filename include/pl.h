@@ -390,8 +390,9 @@ int pl_plan_set_variants(pl_plan* plan, const int32_t v[2 * PL_NUM_VARIANTS]);
 /* ---------------------------------------------------------------------------
  * Batched MAP solves: many independent reconstructions (each its own grid,
  * box and posterior) solved together.  Every pass of every Newton / CG step
- * is ONE launch over all instances (a per-block work list of (instance,
- * tile)); converged instances are masked out on the device; the CG steps
+ * is one launch over all instances per length class (32-96, and 128; a
+ * per-block work list of (instance, tile)); converged instances are masked
+ * out on the device; the CG steps
  * between host convergence checks are captured once as a HIP graph and
  * replayed.  Each axis length must be one of 32, 48, 64, 96, 128.
  * ------------------------------------------------------------------------- */
