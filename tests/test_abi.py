@@ -63,6 +63,10 @@ def test_every_pass_variant_is_instantiated():
                     continue  # variants 3-6 are column-pass tiles only
                 for op in ((0, 1, 2, 3, 4, 5) if T == "double" else (0, 1, 2, 4)):
                     assert f"row_kernel<{T}, {n}, {op}, {v}>" in syms, (T, n, op, v)
+    # batched passes: one kernel per length class (0: 32-96, 1: 128)
     for T in ("double", "float"):
-        for inv, op in [("true", 0), ("false", 0), ("false", 2), ("true", 3), ("false", 4)]:
-            assert f"col_batch_kernel<{T}, {inv}, {op}>" in syms, (T, inv, op)
+        for cls in (0, 1):
+            for inv, op in [("true", 0), ("false", 0), ("false", 2), ("true", 3), ("false", 4)]:
+                assert f"col_batch_kernel<{T}, {inv}, {op}, {cls}>" in syms, (T, inv, op, cls)
+            for op in ((0, 1, 2, 3) if T == "double" else (0, 1, 2)):
+                assert f"row_batch_kernel<{T}, {op}, {cls}>" in syms, (T, op, cls)
