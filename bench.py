@@ -141,9 +141,9 @@ def batched_workload(dev, rtol):
         bt.solve(rtol=rtol, precision=prec)  # warm-up (also builds the CG graph)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, infos = bt.solve(rtol=rtol, precision=prec)
+        s_list, infos = bt.solve(rtol=rtol, precision=prec)
         torch.cuda.synchronize()
-        return time.perf_counter() - t0, infos
+        return time.perf_counter() - t0, infos, s_list
 
     def run_sequential(prec):
         t = 0.0
@@ -164,7 +164,8 @@ def batched_workload(dev, rtol):
 
     out = {"instances": len(insts)}
     for name, prec, p in (("mixed", 1, 4), ("fp64", 0, 8)):
-        tb, binfos = run_batch(prec)
+        tb, binfos, s_list = run_batch(prec)
+        parity = batch_oracle_parity(insts, s_list)
         ts, sinfos = run_sequential(prec)
         nconv = sum(1 for i in binfos if i["status"] == 0)
         # algorithmic bytes of the CG steps each instance took, over the
@@ -176,9 +177,11 @@ def batched_workload(dev, rtol):
                      "instances_per_s_batched": len(insts) / tb, "instances_per_s_sequential": len(insts) / ts,
                      "converged": nconv, "cg_its_total": sum(i["cg_its"] for i in binfos),
                      "fp64_steps": sum(i["fp64_steps"] for i in binfos),
-                     "cg_algorithmic_bytes": cg_bytes, "cg_bytes_per_s_lower_bound_GBs": cg_bytes / tb / 1e9}
+                     "cg_algorithmic_bytes": cg_bytes, "cg_bytes_per_s_lower_bound_GBs": cg_bytes / tb / 1e9,
+                     "oracle_parity": parity}
         print(f"# batch {name}: {1e3 * tb:.0f} ms batched vs {1e3 * ts:.0f} ms sequential "
-              f"({ts / tb:.2f}x, {nconv}/64 converged, CG bytes {cg_bytes / tb / 1e9:.0f} GB/s over the solve)",
+              f"({ts / tb:.2f}x, {nconv}/64 converged, CG bytes {cg_bytes / tb / 1e9:.0f} GB/s over the solve; "
+              f"max rel-L2 vs the stored oracle MAPs {parity['max_rel_l2'] if parity else None})",
               file=sys.stderr, flush=True)
     out["speedup_mixed_batched_vs_fp64_sequential"] = out["fp64"]["ms_sequential"] / out["mixed"]["ms_batched"]
     return out
@@ -210,6 +213,33 @@ def oracle_parity(workload, inst, fields):
         out[name] = {"rel_l2": float(np.linalg.norm(a - r) / np.linalg.norm(r)),
                      "max_cell_rel": float(np.max(np.abs(a - r) / scale))}
     return out
+
+
+def batch_oracle_parity(insts, s_list):
+    """Each batched MAP against the stored oracle MAP of its instance
+    (tests/golden/batch64_map.json) over that instance's sampled cells: the
+    largest relative L2 error and the largest worst-cell error (units of
+    max(|ref|, 1e-2 max|ref|)) over the instances; None when no stored result
+    exists or an instance's inputs differ from the stored run's."""
+    import hashlib
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "batch64_map.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        ref = json.load(f)["instances"]
+    if len(ref) != len(insts):
+        return None
+    rel, worst = 0.0, 0.0
+    for it, s, rec in zip(insts, s_list, ref):
+        if hashlib.sha256(np.ascontiguousarray(it["counts"]).tobytes()).hexdigest() != rec["inputs"]["counts_sha256"]:
+            return None
+        cells = np.asarray(rec["cells"])
+        r = np.asarray(rec["s_star_cells"])
+        a = s.detach().cpu().numpy().ravel()[cells]
+        rel = max(rel, float(np.linalg.norm(a - r) / np.linalg.norm(r)))
+        worst = max(worst, float(np.max(np.abs(a - r) / np.maximum(np.abs(r), 1e-2 * np.abs(r).max()))))
+    return {"instances": len(insts), "oracle_rtol": ref[0]["oracle_solve"]["rtol"], "max_rel_l2": rel,
+            "max_cell_rel": worst}
 
 
 def cpu_oracle_baseline(inst, v, full=False):
@@ -479,10 +509,11 @@ def main():
         splan.solve(rtol=1e-8, precision=prec)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, sinfo = splan.solve(rtol=1e-8, precision=prec)
+        s32, sinfo = splan.solve(rtol=1e-8, precision=prec)
         torch.cuda.synchronize()
         plain32[name] = {"ms": 1e3 * (time.perf_counter() - t0), "newton_its": sinfo["newton_its"],
-                         "cg_its": sinfo["cg_its"], "status": sinfo["status"], "fp64_steps": sinfo["fp64_steps"]}
+                         "cg_its": sinfo["cg_its"], "status": sinfo["status"], "fp64_steps": sinfo["fp64_steps"],
+                         "oracle_parity": oracle_parity("plain32", small, {"s": s32})}
     splan.close()
     print(f"# plain32 (rtol 1e-8): {plain32}", file=sys.stderr, flush=True)
 

@@ -1,6 +1,6 @@
 """Write the stored oracle results that the full-size GPU parity tests use.
 
-    python tests/golden/make_golden.py [sel256] [bias256] [batch64] [big512]
+    python tests/golden/make_golden.py [plain32] [sel256] [bias256] [batch64] [big512]
 
 Every value written here comes from the CPU oracle (``oracle/``) on inputs
 drawn by the seeded generator (``paper_0911_1407_amd.synth``, which holds
@@ -24,6 +24,8 @@ section 2.3 / eq. 3 with the power-law bias of section 2.4, found by the
 oracle's spectral Newton-PCG of section 3.1 solved to ||g|| / ||g0|| <= 1e-10,
 well below the 1e-6 tolerance of the parity tests):
 
+* ``plain32`` -- the 32^3 plain workload (no selection), whose MAP the
+  benchmark compares its 32^3 solves against;
 * ``sel256``  -- 256^3 selection workload (sigma_G 1.5, radial selection
   R = 200 Mpc/h, 20% masked 8^3 blocks, nbar 0.5, unit bias);
 * ``bias256`` -- the same selection with beta = 1.5, nbar = 2, plus the
@@ -168,7 +170,9 @@ def golden_batch(n_cells=64):
 if __name__ == "__main__":
     which = sys.argv[1:] or ["sel256", "bias256", "batch64"]
     for w in which:
-        if w == "sel256":
+        if w == "plain32":
+            golden_map("plain32", 3)
+        elif w == "sel256":
             golden_map("sel256", 1)
         elif w == "bias256":
             # beta = 1.5, nbar = 2 under the radial selection: the Hessian

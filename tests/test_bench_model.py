@@ -39,3 +39,50 @@ def test_measured_traffic_only_for_the_profiled_kernels():
     assert bench.measured_traffic("big512", sched) is None
     # within a few percent of the algorithmic bytes: no wasted re-reads
     assert 1.0 <= m["bytes_per_hvp"] / bench.hvp_bytes((256, 256, 256), 8) < 1.1
+
+
+def test_oracle_parity_reports_against_the_stored_samples():
+    # a field that holds the stored oracle values at the sampled cells has
+    # zero error there; a perturbed one reports its size; other inputs give None
+    import json
+    import os
+
+    import numpy as np
+    import torch
+
+    from paper_0911_1407_amd import synth
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "plain32_map.json")
+    ref = json.load(open(path))
+    inst = synth.config_instance("plain32")
+    s = np.zeros(inst["n"])
+    s.ravel()[ref["cells"]] = ref["s_star_cells"]
+    out = bench.oracle_parity("plain32", inst, {"s": torch.from_numpy(s)})
+    assert out["s"]["rel_l2"] == 0.0 and out["s"]["max_cell_rel"] == 0.0
+    s.ravel()[ref["cells"]] *= 1.0 + 1e-6
+    out = bench.oracle_parity("plain32", inst, {"s": torch.from_numpy(s)})
+    assert abs(out["s"]["rel_l2"] - 1e-6) < 1e-9
+    other = dict(inst, counts=inst["counts"] + 1.0)
+    assert bench.oracle_parity("plain32", other, {"s": torch.from_numpy(s)}) is None
+
+
+def test_batch_oracle_parity_takes_the_worst_instance():
+    import json
+    import os
+
+    import numpy as np
+    import torch
+
+    from paper_0911_1407_amd import synth
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch64_map.json")
+    ref = json.load(open(path))["instances"]
+    insts = synth.batch_instances(count=64)
+    fields = []
+    for it, rec in zip(insts, ref):
+        s = np.zeros(it["n"])
+        s.ravel()[rec["cells"]] = rec["s_star_cells"]
+        fields.append(torch.from_numpy(s))
+    out = bench.batch_oracle_parity(insts, fields)
+    assert out["instances"] == 64 and out["max_rel_l2"] == 0.0 and out["max_cell_rel"] == 0.0
+    fields[17] = fields[17] * (1.0 + 2e-6)
+    out = bench.batch_oracle_parity(insts, fields)
+    assert abs(out["max_rel_l2"] - 2e-6) < 1e-9
