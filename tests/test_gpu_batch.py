@@ -77,6 +77,35 @@ def test_batch_with_128_point_axes_matches_single(prec):
         assert _rel(s.cpu().numpy(), s1.cpu().numpy()) <= tol, inst["n"]
 
 
+def test_batch_host_backtracking_matches_single():
+    # Armijo constant 0.97: near a quadratic model only steps below about
+    # 0.06 of the Newton step qualify, so the device-side pick over the first
+    # trial batch (1 .. 1/8) finds none and every Newton step backtracks on
+    # the host (from 1/16).  Inner solves to 1e-9 (eta_max) make the
+    # directions agree (to the inner tolerance, amplified by the conditioning),
+    # so two such steps of the batch equal two of the single-plan solver,
+    # which backtracks the same way; a different accepted step would differ
+    # by a sizeable fraction of the step.
+    from paper_0911_1407_amd.binding import PL_ERR_NOT_CONVERGED, Batch, Plan
+    insts = synth.batch_instances(count=3, sizes=(32, 48, 64), master_seed=7)
+    opts = dict(rtol=1e-12, max_newton=2, max_cg=5000, eta_max=1e-9, ls_c1=0.97, precision=0)
+    b = Batch(insts, precision="fp64")
+    s_list, infos = b.solve(**opts)
+    for inst, s, info in zip(insts, s_list, infos):
+        assert info["status"] == PL_ERR_NOT_CONVERGED and info["newton_its"] == 2, info
+        plan = Plan(inst["n"], inst["box"], precision="fp64")
+        plan.set_instance(inst)
+        s1, info1 = plan.solve(**opts)
+        assert info1["status"] == PL_ERR_NOT_CONVERGED and info1["newton_its"] == 2, info1
+        assert abs(info["rel_grad"] - info1["rel_grad"]) <= 1e-6 * info1["rel_grad"]
+        assert _rel(s.cpu().numpy(), s1.cpu().numpy()) <= 1e-6, inst["n"]
+        # near-exact Newton directions scale the gradient by about (1 - a) per
+        # step: two steps of 1/32 leave about 0.94 of it, one step the device
+        # could have accepted (1/8 or more) at most 0.88
+        print(f"batch backtracking n={inst['n']}: ||g||/||g0|| after 2 steps {info['rel_grad']:.4f}", flush=True)
+        assert 0.9 < info["rel_grad"] < 0.99, info
+
+
 def test_batch_workload_64_instances():
     # the batched workload: 64 instances, n in {32, 48, 64, 96}, mixed precision
     from paper_0911_1407_amd.binding import Batch
