@@ -27,3 +27,22 @@ def test_fft_plans_match_the_dft_on_the_host(tmp_path):
     lines = [l for l in r.stdout.splitlines() if l.startswith("N=")]
     # 12 lengths, forward and inverse
     assert len(lines) == 24 and all(l.endswith(" ok") for l in lines), r.stdout
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_fft_plans_are_clean_under_address_and_undefined_behaviour_sanitizers(tmp_path):
+    # the same check built with AddressSanitizer and UBSan: every register
+    # array index of the stage code (values, twiddle powers) and every
+    # exchange position stays in bounds for every plan (an out-of-range
+    # twiddle power, say, stops the run with a runtime error)
+    exe = str(tmp_path / "fft_plan_check_san")
+    cmd = ["g++", "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-fno-omit-frame-pointer", "-I" + os.path.join(HERE, "host"), "-I" + CSRC,
+           os.path.join(HERE, "host", "fft_plan_check.cpp"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0 and ("asan" in r.stderr or "ubsan" in r.stderr):
+        pytest.skip("sanitizer runtimes not installed: " + r.stderr[-300:])
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, (r.stdout + r.stderr)[-3000:]
+    assert "runtime error" not in r.stderr and "AddressSanitizer" not in r.stderr
