@@ -2021,7 +2021,6 @@ struct pl_batch {
   double* scal_all = nullptr;
   double* h_scal = nullptr;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
-  hipGraphExec_t graph_c = nullptr;  // the running solve's CG chunk over W_XC / W_YC / W_RC
   // control records: composed in slot 0 of the host blob's control region,
   // uploaded from one of kCtlSlots staging slots in turn (bctl)
   int ctl_next = 0, ctl_unsynced = 0;
@@ -2372,9 +2371,11 @@ int batch_newton(pl_batch* b, double* const* s_io, const pl_solve_opts& o, pl_so
   enum { PH_OFF = 0, PH_START, PH_CG, PH_STEP };
   std::vector<int> phase(K, PH_OFF), newton(K, 0);
   // the CG chunks run from the graph over every instance until the cells of
-  // the unfinished ones fall to half of those it covers; then from a graph
-  // over the unfinished instances only (rebuilt each time they halve again)
-  hipGraphExec_t cg_graph = b->graph[ti];
+  // the unfinished ones fall to half of those it covers; then as direct
+  // launches over work lists of the unfinished instances only (rebuilt each
+  // time their cells halve again)
+  const hipGraphExec_t cg_graph = b->graph[ti];
+  bool compacted = false;
   double graph_cells = 0.0;
   for (int i = 0; i < K; ++i) graph_cells += (double)b->plans[i]->N;
   for (int i = 0; i < K; ++i) {
@@ -2633,24 +2634,20 @@ int batch_newton(pl_batch* b, double* const* s_io, const pl_solve_opts& o, pl_so
       if (cells <= 0.5 * graph_cells) {
         rc = build_compact<T>(b, unfinished);
         if (rc) return bfail(b, rc, "compacted work lists exceed their capacity");
-        if (b->graph_c) {
-          (void)hipGraphExecDestroy(b->graph_c);
-          b->graph_c = nullptr;
-        }
-        BHIP(b, hipStreamSynchronize(b->stream));
-        hipGraph_t g = nullptr;
-        BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-        int crc = bcg_chunk<T>(b, o.check_every, o.max_cg, W_XC, W_YC, W_RC);
-        hipError_t e = hipStreamEndCapture(b->stream, &g);
-        if (crc) return crc;
-        BHIP(b, e);
-        BHIP(b, hipGraphInstantiate(&b->graph_c, g, nullptr, nullptr, 0));
-        (void)hipGraphDestroy(g);
-        cg_graph = b->graph_c;
+        compacted = true;
         graph_cells = cells;
       }
     }
-    BHIP(b, hipGraphLaunch(cg_graph, b->stream));
+    // the full work lists replay their graph; compacted ones (rebuilt a few
+    // times per solve) are launched directly: capturing and instantiating a
+    // graph for each would keep the GPU idle while the host does it, where
+    // direct launches are issued while the GPU runs the previous ones
+    if (compacted) {
+      rc = bcg_chunk<T>(b, o.check_every, o.max_cg, W_XC, W_YC, W_RC);
+      if (rc) return rc;
+    } else {
+      BHIP(b, hipGraphLaunch(cg_graph, b->stream));
+    }
     rc = bread(b);
     if (rc) return rc;
     for (int i = 0; i < K; ++i) {
@@ -3009,7 +3006,6 @@ int pl_batch_destroy(pl_batch* b) {
   if (!b) return PL_ERR_INVALID_ARG;
   for (int t = 0; t < 2; ++t)
     if (b->graph[t]) (void)hipGraphExecDestroy(b->graph[t]);
-  if (b->graph_c) (void)hipGraphExecDestroy(b->graph_c);
   for (pl_plan* p : b->plans) pl_plan_destroy(p);
   if (b->h_blob) (void)hipHostFree(b->h_blob);
   if (b->ev) (void)hipEventDestroy(b->ev);
