@@ -14,6 +14,23 @@ __global__ void __launch_bounds__(BATCH_THREADS) col_batch_kernel(const ColArgs<
   const int4 w = work[blockIdx.x];
   const ColArgs<T> a = args[w.x];
   if (a.skip && *a.skip != 0.0) return;
+  if (w.y < 0) {
+    // one work item per instance after the tiles of the y work lists: the
+    // finalize riding on the launch (the CG's alpha on its forward y pass,
+    // which only reads partials of earlier launches); inert elsewhere
+    if constexpr (!INV && OP == COL_PLAIN) {
+      if (a.fin_on && a.fin.scal[SC_INACTIVE] == 0.0) {
+        const FinArgs& f = a.fin;
+        if (blockDim.x == 256)
+          finalize_body<256>(f.partials, f.nb, f.K, f.kind, f.dst, f.scale, f.scal, f.aux, f.partials2, f.nb2,
+                             f.scale2);
+        else
+          finalize_body<128>(f.partials, f.nb, f.K, f.kind, f.dst, f.scale, f.scal, f.aux, f.partials2, f.nb2,
+                             f.scale2);
+      }
+    }
+    return;
+  }
 #define PL_C(NN)                                                      \
   case NN:                                                            \
     if (a.variant == 2)                                               \

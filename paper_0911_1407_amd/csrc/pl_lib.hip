@@ -1966,6 +1966,16 @@ void col_work(const std::vector<pl_plan*>& plans, int axis, const std::vector<in
     w.lds[c] = std::max(w.lds[c], sh.col_lds);
   }
   join_classes(w, cls);
+  if (axis == 1) {
+    // one rider item per instance (tile -1) at the end of the first class's
+    // launch: the finalize that a y pass may carry (col_batch_kernel)
+    std::vector<int4> riders;
+    for (size_t i = 0; i < plans.size(); ++i)
+      if (!subset || (*subset)[i]) riders.push_back(make_int4((int)i, -1, 0, 0));
+    const bool first = w.split > 0;
+    w.items.insert(w.items.begin() + (first ? w.split : (long)w.items.size()), riders.begin(), riders.end());
+    if (first) w.split += (int)riders.size();
+  }
 }
 
 // Row (z) pass over all instances, instance i in tile variant var[i].
@@ -2227,6 +2237,10 @@ void fill_args(pl_batch* b, double* const* s_io) {
     fins(b, BF_GRAD_X, true)[i] = BatchFin{part_a, b->work[W_X64].nb[i], nullptr, 0, p->scal, invN};
     fins(b, BF_INIT, true)[i] = BatchFin{part_a, NBB, nullptr, 0, p->scal, invN};
     fins(b, BF_ALPHA, true)[i] = BatchFin{part_b, nbr[i], part_a, nbx[i], p->scal, invN};
+    // alpha = r^H z / p^H H p, finalized by a rider of the forward y pass
+    ColArgs<T>* cyf = &cargs_t<T>(b, BT_CGYF, true)[i];
+    cyf->fin_on = 1;
+    cyf->fin = FinArgs{part_b, nbr[i], 2, FIN_CG_ALPHA, 0, 1.0, p->scal, 0.0, part_a, nbx[i], invN};
     fins(b, BF_BETA, true)[i] = BatchFin{part_a, nbx[i], nullptr, 0, p->scal, invN};
     fins(b, BF_LS, true)[i] = BatchFin{part_a, NBB, nullptr, 0, p->scal, invN};
   }
@@ -2299,11 +2313,10 @@ int bcg_chunk(pl_batch* b, int chunk, int max_cg, int wx = wid_x<T>(), int wy = 
     BHIP(b, bcol<T>(b, true, COL_CG_FIRST, cargs_t<T>(b, BT_CG1, false), wx));
     BHIP(b, bcol<T>(b, true, COL_PLAIN, cargs_t<T>(b, BT_CGYI, false), wy));
     BHIP(b, brow<T>(b, ROW_HVP, rargs_t<T>(b, BRT_HVP, false), wr));
-    int rc = bfin(b, BF_ALPHA, 2, FIN_CG_ALPHA, 0, 1.0, 0, 0.0, 0.0, 1);
-    if (rc) return rc;
+    // the forward y pass carries the alpha finalize (a rider per instance)
     BHIP(b, bcol<T>(b, false, COL_PLAIN, cargs_t<T>(b, BT_CGYF, false), wy));
     BHIP(b, bcol<T>(b, false, COL_CG_LAST, cargs_t<T>(b, BT_CG5, false), wx));
-    rc = bfin(b, BF_BETA, 2, FIN_CG_BETA, 0, 0.0, 1, (double)max_cg);
+    int rc = bfin(b, BF_BETA, 2, FIN_CG_BETA, 0, 0.0, 1, (double)max_cg);
     if (rc) return rc;
   }
   return PL_OK;
