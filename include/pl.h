@@ -394,7 +394,9 @@ int pl_plan_set_variants(pl_plan* plan, const int32_t v[2 * PL_NUM_VARIANTS]);
  * per-block work list of (instance, tile)); converged instances are masked
  * out on the device; the CG steps
  * between host convergence checks are captured once as a HIP graph and
- * replayed.  Each axis length must be one of 32, 48, 64, 96, 128.
+ * replayed (launched directly over the unfinished instances only, once
+ * their cells have halved).  Each axis length must be one of 32, 48, 64,
+ * 96, 128.
  * ------------------------------------------------------------------------- */
 typedef struct pl_batch pl_batch;
 
