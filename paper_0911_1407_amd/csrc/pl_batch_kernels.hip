@@ -22,10 +22,10 @@ __global__ void __launch_bounds__(BATCH_THREADS) col_batch_kernel(const ColArgs<
       if (a.fin_on && a.fin.scal[SC_INACTIVE] == 0.0) {
         const FinArgs& f = a.fin;
         if (blockDim.x == 256)
-          finalize_body<256>(f.partials, f.nb, f.K, f.kind, f.dst, f.scale, f.scal, f.aux, f.partials2, f.nb2,
+          finalize_body<256, true>(f.partials, f.nb, f.K, f.kind, f.dst, f.scale, f.scal, f.aux, f.partials2, f.nb2,
                              f.scale2);
         else
-          finalize_body<128>(f.partials, f.nb, f.K, f.kind, f.dst, f.scale, f.scal, f.aux, f.partials2, f.nb2,
+          finalize_body<128, true>(f.partials, f.nb, f.K, f.kind, f.dst, f.scale, f.scal, f.aux, f.partials2, f.nb2,
                              f.scale2);
       }
     }

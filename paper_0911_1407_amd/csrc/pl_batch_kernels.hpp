@@ -169,7 +169,7 @@ __global__ void __launch_bounds__(256) finalize_batch_kernel(const BatchFin* __r
                                                              double scale2, int scale2_invN) {
   const BatchFin f = F[blockIdx.x];
   if (f.scal[SC_INACTIVE] != 0.0) return;
-  finalize_body<256>(f.partials, f.nb, K, kind, dst, scale_invN ? f.invN : scale, f.scal, aux, f.partials2, f.nb2,
+  finalize_body<256, true>(f.partials, f.nb, K, kind, dst, scale_invN ? f.invN : scale, f.scal, aux, f.partials2, f.nb2,
                 scale2_invN ? f.invN : scale2);
 }
 

@@ -205,7 +205,7 @@ struct FinArgs {
   double scale2;
 };
 
-template <int NT>
+template <int NT, bool DEVCOUNT = false>
 __device__ __forceinline__ void finalize_body(const double* __restrict__ partials, int nb, int K, int kind, int dst,
                                               double scale, double* __restrict__ scal, double aux,
                                               const double* __restrict__ partials2, int nb2, double scale2);
@@ -383,18 +383,36 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
         }
     } else {
       double beta_k = beta;
-      if (a.beta_part) {
+      int cg_k = a.cg_k;
+      const double* beta_part = a.beta_part;
+      if constexpr (BATCHED) {
+        // instances at different iteration counts under one launch: the
+        // count is the instance's SC_ITS, which the last pass advances
+        // after each iteration (so this launch only reads it); at 0 there
+        // is no previous iteration to close (beta = 0)
+        cg_k = (int)a.scal[SC_ITS];
+        if (cg_k == 0) beta_part = nullptr;
+      }
+      if (beta_part) {
         double v2[2];
-        fin_sums<ColShape<T, N, V>::THREADS, 2>(a.beta_part, a.beta_nb, v2);
+        if constexpr (BATCHED) {
+          // a batched launch may give this tile a larger block than its own
+          if (blockDim.x == 256)
+            fin_sums<256, 2>(beta_part, a.beta_nb, v2);
+          else
+            fin_sums<128, 2>(beta_part, a.beta_nb, v2);
+        } else {
+          fin_sums<ColShape<T, N, V>::THREADS, 2>(beta_part, a.beta_nb, v2);
+        }
         const double rr = v2[0] * a.beta_scale, rz = v2[1] * a.beta_scale;
-        const double rzo = a.scal[cg_rz_slot(a.cg_k - 1)];
+        const double rzo = a.scal[cg_rz_slot(cg_k - 1)];
         beta_k = rzo > 0.0 ? rz / rzo : 0.0;
-        const bool done = rr <= a.scal[SC_TOL2] || (double)a.cg_k >= a.cg_max;
+        const bool done = rr <= a.scal[SC_TOL2] || (double)cg_k >= a.cg_max;
         if (block_linear == 0 && threadIdx.x == 0) {
           double* sc = const_cast<double*>(a.scal);
-          sc[SC_ITS] = (double)a.cg_k;
+          if constexpr (!BATCHED) sc[SC_ITS] = (double)cg_k;
           sc[SC_RR] = rr;
-          sc[cg_rz_slot(a.cg_k)] = rz;
+          sc[cg_rz_slot(cg_k)] = rz;
           sc[SC_BETA] = beta_k;
           if (done) sc[SC_DONE] = 1.0;
         }
@@ -514,6 +532,10 @@ __device__ __forceinline__ void col_body(const ColArgs<T>& a, int tile, int slab
         }
       }
     block_reduce_store<2>(acc, a.partials, block_linear);
+    // batched CG: this iteration is complete (no other workgroup of this
+    // launch reads the count)
+    if constexpr (BATCHED)
+      if (block_linear == 0 && threadIdx.x == 0) const_cast<double*>(a.scal)[SC_ITS] += 1.0;
     return;
   } else {
     // forward transform; out = scale * X + (1/lambda) (base - shift at mode 0);
@@ -1044,7 +1066,7 @@ __global__ void __launch_bounds__(RED_THREADS) cg_init_kernel(const cx<double>* 
 }
 
 enum FinKind { FIN_STORE = 0, FIN_CG_INIT = 1, FIN_CG_ALPHA = 2, FIN_CG_BETA = 3, FIN_DBAR = 4, FIN_CG_ALPHA_ADD = 5,
-               FIN_CG_ALPHA_FIRST = 6, FIN_CG_BETA_K = 7 };
+               FIN_CG_ALPHA_FIRST = 6, FIN_CG_BETA_K = 7, FIN_CG_BETA_DEV = 8 };
 
 // Sum partials[nb][K] in a fixed order; then scalar bookkeeping.
 // kind FIN_CG_ALPHA: p^H H p = scale2 * sum(partials2[nb2]) (prior part from
@@ -1089,7 +1111,10 @@ __device__ __forceinline__ void fin_sums(const double* __restrict__ src, int n, 
 
 // Device-side reduction of per-block partials and the scalar bookkeeping
 // of the Krylov / Newton loops (kind: FinKind).  One block of NT threads.
-template <int NT>
+// DEVCOUNT: the batched CG's forms, with the iteration count in SC_ITS
+// (the alpha slot for aux < 0, FIN_CG_BETA_DEV); the single-grid callers
+// compile without them.
+template <int NT, bool DEVCOUNT>
 __device__ __forceinline__ void finalize_body(const double* __restrict__ partials, int nb, int K, int kind, int dst,
                                               double scale, double* __restrict__ scal, double aux,
                                               const double* __restrict__ partials2, int nb2, double scale2) {
@@ -1112,6 +1137,20 @@ __device__ __forceinline__ void finalize_body(const double* __restrict__ partial
   }
   if (threadIdx.x != 0) return;
   for (int k = 0; k < K; ++k) v[k] *= scale;
+  if constexpr (DEVCOUNT) {
+    if (kind == FIN_CG_BETA_DEV) {
+      // the same bookkeeping as FIN_CG_BETA_K with the iterations completed
+      // taken from SC_ITS, which the batched CG's last pass advances
+      if (scal[SC_DONE] != 0.0) return;  // iteration skipped
+      const int k = (int)scal[SC_ITS];
+      scal[SC_RR] = v[0];
+      const double rzo = scal[cg_rz_slot(k - 1)];
+      scal[cg_rz_slot(k)] = v[1];
+      scal[SC_BETA] = rzo > 0.0 ? v[1] / rzo : 0.0;
+      if (v[0] <= scal[SC_TOL2] || (double)k >= aux) scal[SC_DONE] = 1.0;
+      return;
+    }
+  }
   switch (kind) {
     case FIN_STORE:
       for (int k = 0; k < K; ++k) scal[dst + k] = v[k];
@@ -1130,9 +1169,13 @@ __device__ __forceinline__ void finalize_body(const double* __restrict__ partial
       if (scal[SC_DONE] != 0.0) break;  // iteration skipped
       const double pq = v[0] + extra + (kind == FIN_CG_ALPHA_ADD ? scal[dst] : 0.0);
       scal[SC_PQ] = pq;
-      // aux > 0: the slot holding r^H M^-1 r (cg_rz_slot), else SC_RZ
+      // aux > 0: the slot holding r^H M^-1 r (cg_rz_slot); with DEVCOUNT and
+      // aux < 0: the slot of the iteration count in SC_ITS; else SC_RZ
+      int rz_at = aux > 0.0 ? (int)aux : (int)SC_RZ;
+      if constexpr (DEVCOUNT)
+        if (aux < 0.0) rz_at = cg_rz_slot((int)scal[SC_ITS]);
       double al = 0.0;
-      if (scal[SC_DONE] == 0.0 && pq > 0.0) al = scal[aux > 0.0 ? (int)aux : SC_RZ] / pq;
+      if (scal[SC_DONE] == 0.0 && pq > 0.0) al = scal[rz_at] / pq;
       if (scal[SC_DONE] == 0.0 && !(pq > 0.0)) scal[SC_DONE] = 2.0;  // breakdown
       scal[SC_ALPHA] = al;
       break;

@@ -2210,16 +2210,22 @@ void fill_args(pl_batch* b, double* const* s_io) {
     cx<T>*x = View<T>::x(p), *rr = View<T>::r(p), *pp = View<T>::pv(p), *t = View<T>::t(p);
     double* part_a = p->partials;
     double* part_b = p->partials + p->partials_len;
+    double* part_c = p->partials + 2 * p->partials_len;  // the last pass's (r^H r, r^H M^-1 r)
     ColArgs<T>* ct;
     ct = &cargs_t<T>(b, BT_CG1, true)[i]; *ct = col_args<T>(p, 0, pp, t);
     ct->cg_r = rr; ct->scal = p->scal; ct->partials = part_a; ct->skip = done; ct->variant = vT;
+    // the first pass closes the previous iteration itself (beta, the
+    // convergence test, the bookkeeping) from the last pass's partials, at
+    // the iteration count in SC_ITS (cg_max is set per solve)
+    ct->beta_part = part_c;
+    ct->beta_scale = 1.0 / (double)p->N;
     ct->radial = p->radial ? TAB_SHELL : TAB_MODE;
     ct->inv_lam = View<T>::tab(p, p->radial);
     ct = &cargs_t<T>(b, BT_CGYI, true)[i]; *ct = col_args<T>(p, 1, t, t); ct->skip = done; ct->variant = vT;
     ct = &cargs_t<T>(b, BT_CGYF, true)[i]; *ct = col_args<T>(p, 1, t, t); ct->skip = done; ct->variant = vT;
     ct = &cargs_t<T>(b, BT_CG5, true)[i]; *ct = col_args<T>(p, 0, t, t);
-    ct->base = pp; ct->cg_r = rr; ct->cg_x = x; ct->scal = p->scal; ct->partials = part_a; ct->skip = done;
-    ct->variant = vT;
+    ct->base = pp; ct->cg_r = rr; ct->cg_x = x; ct->scal = p->scal; ct->partials = part_c; ct->skip = done;
+    ct->variant = vT;  // (the last pass advances SC_ITS after each iteration)
     ct->radial = p->radial ? TAB_SHELL : TAB_MODE;
     ct->inv_lam = View<T>::tab(p, p->radial);
     ct = &cargs_t<T>(b, BT_XCINV, true)[i]; *ct = col_args<T>(p, 0, x, t); ct->skip = inactive; ct->variant = vT;
@@ -2240,10 +2246,18 @@ void fill_args(pl_batch* b, double* const* s_io) {
     // alpha = r^H z / p^H H p, finalized by a rider of the forward y pass
     ColArgs<T>* cyf = &cargs_t<T>(b, BT_CGYF, true)[i];
     cyf->fin_on = 1;
-    cyf->fin = FinArgs{part_b, nbr[i], 2, FIN_CG_ALPHA, 0, 1.0, p->scal, 0.0, part_a, nbx[i], invN};
-    fins(b, BF_BETA, true)[i] = BatchFin{part_a, nbx[i], nullptr, 0, p->scal, invN};
+    cyf->fin = FinArgs{part_b, nbr[i], 2, FIN_CG_ALPHA, 0, 1.0, p->scal, -1.0, part_a, nbx[i], invN};
+    fins(b, BF_BETA, true)[i] = BatchFin{part_c, nbx[i], nullptr, 0, p->scal, invN};
+    cargs_t<T>(b, BT_CG1, true)[i].beta_nb = nbx[i];
     fins(b, BF_LS, true)[i] = BatchFin{part_a, NBB, nullptr, 0, p->scal, invN};
   }
+}
+
+// The CG iteration cap the batched first pass tests (per solve; the host
+// blob is uploaded after this).
+template <typename T>
+void set_cg_max(pl_batch* b, int max_cg) {
+  for (int i = 0; i < b->K; ++i) cargs_t<T>(b, BT_CG1, true)[i].cg_max = (double)max_cg;
 }
 
 int bfin(pl_batch* b, int which, int K, int kind, int dst, double scale, int scale_invN, double aux = 0.0,
@@ -2316,10 +2330,11 @@ int bcg_chunk(pl_batch* b, int chunk, int max_cg, int wx = wid_x<T>(), int wy = 
     // the forward y pass carries the alpha finalize (a rider per instance)
     BHIP(b, bcol<T>(b, false, COL_PLAIN, cargs_t<T>(b, BT_CGYF, false), wy));
     BHIP(b, bcol<T>(b, false, COL_CG_LAST, cargs_t<T>(b, BT_CG5, false), wx));
-    int rc = bfin(b, BF_BETA, 2, FIN_CG_BETA, 0, 0.0, 1, (double)max_cg);
-    if (rc) return rc;
   }
-  return PL_OK;
+  // the next first pass closes each iteration; after the chunk one finalize
+  // closes the last for the host's check (the next chunk's first pass
+  // repeats it, to the same values)
+  return bfin(b, BF_BETA, 2, FIN_CG_BETA_DEV, 0, 0.0, 1, (double)max_cg);
 }
 
 template <typename T>
@@ -2327,6 +2342,7 @@ int batch_newton(pl_batch* b, double* const* s_io, const pl_solve_opts& o, pl_so
   const int K = b->K;
   const int ti = sizeof(T) == 8 ? 0 : 1;
   fill_args<T>(b, s_io);
+  set_cg_max<T>(b, o.max_cg);
   BHIP(b, hipMemcpyAsync(b->d_blob, b->h_blob, b->off_e64, hipMemcpyHostToDevice, b->stream));
   BatchCtl* ctl = blob_ptr<BatchCtl>(b, b->off_ctl, true);
   BatchElem<T>* E = elems<T>(b, true);
@@ -2714,6 +2730,8 @@ int time_batch_cg(pl_batch* b, int reps, float* ms) {
   std::vector<double*> dummy(b->K);
   for (int i = 0; i < b->K; ++i) dummy[i] = b->plans[i]->s_ws;
   fill_args<T>(b, dummy.data());
+  const int big = 1 << 30;
+  set_cg_max<T>(b, big);
   BHIP(b, hipMemcpyAsync(b->d_blob, b->h_blob, b->off_e64, hipMemcpyHostToDevice, b->stream));
   for (int i = 0; i < b->K; ++i) {
     pl_plan* p = b->plans[i];
@@ -2723,7 +2741,6 @@ int time_batch_cg(pl_batch* b, int reps, float* ms) {
     if (rc) return bfail(b, rc, pl_last_error(p));
   }
   BHIP(b, hipMemsetAsync(b->scal_all, 0, sizeof(double) * SC_COUNT * b->K, b->stream));
-  const int big = 1 << 30;
   int rc = bcg_chunk<T>(b, 2, big);
   if (rc) return rc;
   hipEvent_t e0, e1;

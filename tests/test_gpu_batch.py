@@ -106,6 +106,28 @@ def test_batch_host_backtracking_matches_single():
         assert 0.9 < info["rel_grad"] < 0.99, info
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_cg_cap_matches_single(prec):
+    # every Newton step's CG stopped by the iteration cap (5, inside a chunk
+    # of 16; the forcing term 1e-9 keeps the CG from stopping earlier): the
+    # batched solver and the single-plan solver take the same truncated
+    # directions, so the same iterates and CG counts
+    from paper_0911_1407_amd.binding import PL_ERR_NOT_CONVERGED, Batch, Plan
+    insts = synth.batch_instances(count=3, sizes=(32, 48, 64), master_seed=11)
+    opts = dict(rtol=1e-12, max_newton=4, max_cg=5, check_every=16, eta_max=1e-9)
+    b = Batch(insts, precision=prec)
+    s_list, infos = b.solve(**opts)
+    for inst, s, info in zip(insts, s_list, infos):
+        plan = Plan(inst["n"], inst["box"], precision=prec)
+        plan.set_instance(inst)
+        s1, info1 = plan.solve(**opts)
+        assert info["status"] == info1["status"] == PL_ERR_NOT_CONVERGED, (info, info1)
+        assert info["newton_its"] == info1["newton_its"] == 4
+        assert info["cg_its"] == info1["cg_its"], (info["cg_its"], info1["cg_its"])
+        assert 16 <= info["cg_its"] <= 20, info  # at most 5 per step, most steps capped
+        assert _rel(s.cpu().numpy(), s1.cpu().numpy()) <= (1e-9 if prec == "fp64" else 1e-5), inst["n"]
+
+
 def test_batch_workload_64_instances():
     # the batched workload: 64 instances, n in {32, 48, 64, 96}, mixed precision
     from paper_0911_1407_amd.binding import Batch
