@@ -56,7 +56,7 @@ TUNE_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_091
 # paper_0911_1407_amd/csrc/*.hip and *.hpp, sorted by path, first 16 hex
 # digits) and the FP64 schedule it ran; otherwise the bench reports null.
 MEASURED_TRAFFIC = {
-    "sel256": {"src_sha": "59d54941924e932a", "fp64_schedule": [5, 0, 0, 0, 2, 2, 30],
+    "sel256": {"src_sha": "2e23c239b2167119", "fp64_schedule": [5, 0, 0, 0, 2, 2, 30],
                "bytes_per_hvp": 1685961696},
 }
 

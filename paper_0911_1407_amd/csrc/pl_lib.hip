@@ -2005,7 +2005,7 @@ enum BCol { BC_SHAT_Y = 0, BC_SHAT_X, BC_G_XINV, BC_G_YINV, BC_G_YFWD, BC_G_XADD
 enum BColT { BT_CG1 = 0, BT_CGYI, BT_CGYF, BT_CG5, BT_XCINV, BT_YCINV, BT_COUNT };
 enum BRow { BR_R2C = 0, BR_GRAD, BR_COUNT64 };
 enum BRowT { BRT_HVP = 0, BRT_C2R, BRT_COUNT };
-enum BFin { BF_GRAD_ROW = 0, BF_GRAD_X, BF_INIT, BF_ALPHA, BF_BETA, BF_LS, BF_COUNT };
+enum BFin { BF_GRAD_ROW = 0, BF_GRAD_X, BF_INIT, BF_BETA, BF_LS, BF_COUNT };
 
 }  // namespace
 
@@ -2242,7 +2242,6 @@ void fill_args(pl_batch* b, double* const* s_io) {
     fins(b, BF_GRAD_ROW, true)[i] = BatchFin{part_a, b->work[W_R64].nb[i], nullptr, 0, p->scal, invN};
     fins(b, BF_GRAD_X, true)[i] = BatchFin{part_a, b->work[W_X64].nb[i], nullptr, 0, p->scal, invN};
     fins(b, BF_INIT, true)[i] = BatchFin{part_a, NBB, nullptr, 0, p->scal, invN};
-    fins(b, BF_ALPHA, true)[i] = BatchFin{part_b, nbr[i], part_a, nbx[i], p->scal, invN};
     // alpha = r^H z / p^H H p, finalized by a rider of the forward y pass
     ColArgs<T>* cyf = &cargs_t<T>(b, BT_CGYF, true)[i];
     cyf->fin_on = 1;
